@@ -1,0 +1,175 @@
+"""Chain primitives in float64: messages, min-marginals and minorants.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+Notation (paper App. A.1).  A chain has nodes 0..n-1 with unary cost vectors
+a_j in R^K and edges (j, j+1) with pairwise cost w_j * rho(x_j - x_{j+1}),
+where rho(t) = min(|t|, T) is the truncated-linear penalty obtained by
+sampling the regulariser r at the label positions (Sec. 2.1, regulariser and
+its figure; Sec. 2.2 "Stereo").  Potts is the case T = 1.
+
+Arrays are batched over independent chains: ``a`` has shape (C, n, K) and
+``w`` has shape (C, n-1).  Every function works on all C chains at once; the
+loops along a chain follow the paper's order.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "rho",
+    "pairwise_table",
+    "message",
+    "message_bruteforce",
+    "left_right_messages",
+    "min_marginals",
+    "chain_energy",
+    "iterative_minorant",
+    "naive_minorant",
+]
+
+
+def rho(t, T: int):
+    """Truncated-linear penalty min(|t|, T) (regulariser sampled at labels, Sec. 2.1)."""
+    return np.minimum(np.abs(t), T)
+
+
+def pairwise_table(K: int, T: int) -> np.ndarray:
+    """K x K table rho(a - b) for labels a, b in {0..K-1}."""
+    k = np.arange(K)
+    return rho(k[:, None] - k[None, :], T).astype(np.float64)
+
+
+def message_bruteforce(v: np.ndarray, w: np.ndarray, T: int) -> np.ndarray:
+    """Message of the min-sum recursion, taken literally (App. A.1, eq. msg-pass).
+
+    phi(b) = min_a [ v(a) + w * rho(a - b) ],  v: (C, K), w: (C,) -> (C, K).
+    O(K^2) per chain; used as the definition against which ``message`` is pinned.
+    """
+    v = np.asarray(v, dtype=np.float64)
+    K = v.shape[-1]
+    P = pairwise_table(K, T)                       # P[a, b]
+    return np.min(v[:, :, None] + np.asarray(w, np.float64)[:, None, None] * P[None], axis=1)
+
+
+def message(v: np.ndarray, w: np.ndarray, T: int) -> np.ndarray:
+    """Message phi(b) = min_a [v(a) + w rho(a-b)] written with the truncation made explicit.
+
+    For |a - b| >= T the pairwise cost is the constant w*T, so
+        phi(b) = min( min_{|a-b| < T} v(a) + w|a-b| ,  min_a v(a) + w T ).
+    This is the same definition as ``message_bruteforce`` (no distance
+    transform, no reordering), evaluated over the 2T-1 labels that can beat
+    the truncation.  Requires w >= 0.
+    """
+    v = np.asarray(v, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)[:, None]
+    C, K = v.shape
+    out = v.min(axis=1, keepdims=True) + w * T
+    out = np.broadcast_to(out, (C, K)).copy()
+    for d in range(-(T - 1), T):
+        if abs(d) >= K:
+            continue
+        shifted = np.full((C, K), np.inf)
+        # candidate a = b + d
+        if d >= 0:
+            shifted[:, : K - d] = v[:, d:]
+        else:
+            shifted[:, -d:] = v[:, : K + d]
+        out = np.minimum(out, shifted + w * abs(d))
+    return out
+
+
+def left_right_messages(a: np.ndarray, w: np.ndarray, T: int):
+    """Left and right min-marginal messages of chains (App. A.1 definitions).
+
+    L[:, j] = phi_{j-1,j}: min over x_0..x_{j-1} of the part of the chain left of j
+    R[:, j] = phi_{j+1,j}: min over x_{j+1}..x_{n-1} of the part right of j
+    computed by the recursion phi_{j,j+1} = Msg(phi_{j-1,j} + a_j) (eq. msg-pass).
+    """
+    a = np.asarray(a, dtype=np.float64)
+    C, n, K = a.shape
+    L = np.zeros((C, n, K))
+    R = np.zeros((C, n, K))
+    for j in range(1, n):
+        L[:, j] = message(L[:, j - 1] + a[:, j - 1], w[:, j - 1], T)
+    for j in range(n - 2, -1, -1):
+        R[:, j] = message(R[:, j + 1] + a[:, j + 1], w[:, j], T)
+    return L, R
+
+
+def min_marginals(a: np.ndarray, w: np.ndarray, T: int, normalized: bool = True) -> np.ndarray:
+    """Min-marginals m_j = a_j + phi_{j-1,j} + phi_{j+1,j} (App. A.1, eq. min-marg-expression).
+
+    With ``normalized`` the per-node minimum is subtracted (as in the paper's
+    worked example of App. A.3.1), so each node's minimum is 0.
+    """
+    L, R = left_right_messages(a, w, T)
+    m = np.asarray(a, np.float64) + L + R
+    if normalized:
+        m = m - m.min(axis=2, keepdims=True)
+    return m
+
+
+def chain_energy(a: np.ndarray, w: np.ndarray, T: int, x: np.ndarray) -> np.ndarray:
+    """Energy of labelings x (C, n) of chains a (C, n, K): sum of unaries and pairwise terms."""
+    a = np.asarray(a, np.float64)
+    C, n, K = a.shape
+    e = np.take_along_axis(a, x[:, :, None], axis=2)[:, :, 0].sum(axis=1)
+    if n > 1:
+        e = e + (np.asarray(w, np.float64) * rho(x[:, 1:] - x[:, :-1], T)).sum(axis=1)
+    return e
+
+
+def iterative_minorant(a: np.ndarray, w: np.ndarray, T: int, gammas) -> np.ndarray:
+    """Iterative minorant of chains a (App. A.3.2, Alg. Iterative Minorant).
+
+    Starting from h = 0 and the remainder r = a - h, the algorithm makes
+    ``len(gammas)`` directional passes, forward on the first, then alternating
+    ("reverse the chain").  At every node it forms the min-marginal of the
+    remainder dynamically (message recursion + min-marginal expression) and
+    moves the fraction gamma_s of it into the minorant.  The min-marginal is
+    taken normalized (minimum over labels subtracted), so the remainder keeps
+    the chain optimum and h >= 0.  The last gamma must be 1 for the result to
+    be maximal (App. A.3, Lemma on maximal minorants).
+
+    Before the first forward pass the right messages of the unmodified chain
+    are computed by one backward message pass; during a pass the message
+    arriving from the not-yet-visited side stays valid, because those nodes
+    have not been modified since it was computed.
+
+    Returns h with the shape of a.
+    """
+    a = np.asarray(a, dtype=np.float64)
+    C, n, K = a.shape
+    r = a.copy()
+    h = np.zeros_like(r)
+    L = np.zeros((C, n, K))
+    R = np.zeros((C, n, K))
+    for j in range(n - 2, -1, -1):
+        R[:, j] = message(R[:, j + 1] + r[:, j + 1], w[:, j], T)
+    for s, g in enumerate(gammas):
+        if s % 2 == 0:
+            order = range(n)
+        else:
+            order = range(n - 1, -1, -1)
+        for j in order:
+            m = r[:, j] + L[:, j] + R[:, j]
+            d = g * (m - m.min(axis=1, keepdims=True))
+            r[:, j] -= d
+            h[:, j] += d
+            if s % 2 == 0 and j + 1 < n:
+                L[:, j + 1] = message(L[:, j] + r[:, j], w[:, j], T)
+            if s % 2 == 1 and j - 1 >= 0:
+                R[:, j - 1] = message(R[:, j] + r[:, j], w[:, j - 1], T)
+    return h
+
+
+def naive_minorant(a: np.ndarray, w: np.ndarray, T: int) -> np.ndarray:
+    """Naive minorant: normalized min-marginals divided by the chain length (Sec. 2.3, App. A.1).
+
+    This is the parallel block update obtained by splitting the chain into n
+    copies of cost f/n, each contributing its min-marginal at one node.
+    """
+    a = np.asarray(a, dtype=np.float64)
+    n = a.shape[1]
+    return min_marginals(a, w, T, normalized=True) / float(n)
