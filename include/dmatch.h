@@ -1,0 +1,135 @@
+/*
+ * dmatch.h - C ABI of the MI355X (gfx950) library for discrete-continuous dense matching.
+ *
+ * Method: Shekhovtsov, Reinbacher, Graber, Pock, "Solving Dense Image Matching in
+ * Real-Time using Discrete-Continuous Optimization" (CVWW 2016).
+ *
+ * Conventions shared by every entry point
+ *   - Every array pointer is a DEVICE pointer (e.g. the storage of a torch tensor on
+ *     the GPU) unless stated otherwise; parameter structs are HOST pointers.
+ *   - Images and per-pixel arrays are row-major [H][W]: pixel (x, y) at y*W + x.
+ *   - Volumes are label-major [H][W][K]: label k of pixel (x, y) at (y*W + x)*K + k.
+ *   - Edge arrays: w_h[H][W-1] holds the edge between (x, y) and (x+1, y) at
+ *     y*(W-1) + x; w_v[H-1][W] holds the edge between (x, y) and (x, y+1) at y*W + x.
+ *     Edge weights must be finite and >= 0.
+ *   - The caller owns every buffer.  Calls that need scratch memory take a caller
+ *     workspace whose size is given by the matching *_workspace() query; the library
+ *     allocates no device memory in these calls.
+ *   - Work is enqueued on `hip_stream` (a hipStream_t, NULL = the null stream) and is
+ *     asynchronous: outputs are valid once the stream has completed.
+ *   - Return value: DM_OK or a negative dm_status.  Arguments are validated on the
+ *     host before anything is enqueued; on a validation error nothing is launched and
+ *     no output is touched.  A launch failure, or an asynchronous fault left by an
+ *     earlier call, is returned as DM_ERR_HIP.  No C++ exception crosses this ABI.
+ *     dm_last_error_message() gives a thread-local description of the last error.
+ *   - Non-finite values (NaN/Inf) in cost volumes or images give unspecified results.
+ */
+#ifndef DMATCH_H
+#define DMATCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DM_OK = 0,
+    DM_ERR_NULL = -1,        /* a required pointer is NULL                       */
+    DM_ERR_SHAPE = -2,       /* W, H or K out of range                           */
+    DM_ERR_PARAM = -3,       /* a parameter value is out of range                */
+    DM_ERR_DTYPE = -4,       /* unknown dm_dtype                                 */
+    DM_ERR_WORKSPACE = -5,   /* workspace NULL or smaller than the size query    */
+    DM_ERR_UNSUPPORTED = -6, /* valid but not supported by this build            */
+    DM_ERR_HIP = -7          /* HIP runtime error (launch or asynchronous fault) */
+} dm_status;
+
+typedef enum { DM_F32 = 0, DM_F16 = 1 } dm_dtype;   /* storage type of the cost volume */
+
+typedef enum { DM_MINORANT_ITERATIVE = 0, DM_MINORANT_NAIVE = 1 } dm_minorant;
+
+/* Grid of W x H pixels with K labels; 1 <= W, H <= 16384, 1 <= K <= 256. */
+typedef struct { int W, H, K; } dm_shape;
+
+/* ---------------------------------------------------------------------------------
+ * Cost volume (paper Sec. 2.2 "Stereo": the data term sampled at every label; the
+ * paper's own data term is Census + Hamming, Sec. 3.1 - this library provides a
+ * truncated SAD of the same role).
+ *
+ *   e(x,y,d)     = |I_L(x,y) - I_R(x-d,y)|  if x-d >= 0, else trunc
+ *   cost[y][x][d] = min(trunc, mean of e over the window x.+-r, y.+-r clamped to the image)
+ *   w_h[y][x]    = lambda_pw * exp(-|I_L(x+1,y) - I_L(x,y)| / contrast_sigma)
+ *   w_v[y][x]    = lambda_pw * exp(-|I_L(x,y+1) - I_L(x,y)| / contrast_sigma)
+ * (edge strengths lower across image edges, Sec. 2.1 below eq. regularizer-form).
+ *
+ * I_left, I_right: [H][W] float32.  cost_out: [H][W][K] of out_dtype (FP16 values are
+ * the FP32 result rounded to nearest even).  w_h / w_v may be NULL (not computed).
+ * window: odd, 1..15.  trunc > 0, lambda_pw >= 0, contrast_sigma > 0.
+ * ------------------------------------------------------------------------------- */
+typedef struct { int window; float trunc; float lambda_pw; float contrast_sigma; } dm_cost_params;
+
+int dm_build_cost_volume(const float* I_left, const float* I_right, dm_shape s,
+                         const dm_cost_params* p, dm_dtype out_dtype, void* cost_out,
+                         float* w_h, float* w_v, void* hip_stream);
+
+/* ---------------------------------------------------------------------------------
+ * Discrete stage: Dual_MM (paper Sec. 2.3, Alg. Dual_MM; minorants App. A.3).
+ *
+ * Energy (Sec. 2.2, eq. energy-pairwise):
+ *   E(x) = sum_i cost_i(x_i) + sum_h w_h rho(x_i - x_j) + sum_v w_v rho(x_i - x_j),
+ *   rho(t) = min(|t|, trunc_T)    (truncated linear; Potts for trunc_T = 1).
+ * Decomposition: horizontal chains F with unaries cost - lambda and vertical chains G
+ * with unaries lambda (lambda = dual_inout).  One dual iteration = a horizontal
+ * half-step (each row hands its minorant to G: lambda += h) followed by a vertical
+ * half-step (each column hands its minorant to F: lambda -= h).
+ * Minorant DM_MINORANT_ITERATIVE: App. A.3.2 Alg. Iterative Minorant with max_pass
+ * directional passes (forward first, then alternating) and steps gamma[0..max_pass-1];
+ * gamma[max_pass-1] must be 1 (maximal minorant).  DM_MINORANT_NAIVE: normalized
+ * min-marginals divided by the chain length (Sec. 2.3, App. A.1).
+ *
+ * Outputs after the last half-step:
+ *   labels_out  [H][W] int32: argmin over k of the normalized row min-marginals of F
+ *               (lowest k on exact ties).  May be NULL.
+ *   minmarg_out [H][W][K] float32: those normalized min-marginals.  May be NULL.
+ *   dual_inout  [H][W][K] float32: lambda.  Read as the starting point if warm_start,
+ *               else overwritten with 0 first; holds the final lambda.  Required.
+ *   bounds_out  device double[2] = {LB, E(labels)}; LB = min F + min G (eq. DD-dual).
+ *               May be NULL.
+ *   lb_trace_out device double[number of half-steps]: LB after each half-step.  May be NULL.
+ * Numerics: FP32 state (lambda, messages), cost read as FP32 or FP16 and widened to
+ * FP32; messages are renormalised to minimum 0 at every step; LB/E accumulate in FP64
+ * in a fixed order (results are run-to-run deterministic).
+ * ------------------------------------------------------------------------------- */
+typedef struct {
+    int   n_iters;          /* dual iterations (>= 0)                                   */
+    int   n_half_steps;     /* > 0 overrides 2*n_iters (odd = ends after a horizontal)  */
+    int   trunc_T;          /* truncation of rho, >= 1                                  */
+    int   minorant;         /* dm_minorant                                              */
+    int   max_pass;         /* 1..8 (iterative minorant)                                */
+    float gamma[8];         /* each in (0, 1]; gamma[max_pass-1] == 1                   */
+    int   warm_start;       /* 0: lambda := 0 first; 1: start from dual_inout           */
+    int   tile_lanes;       /* 0 = automatic; else lanes per chain: 4, 8, 16, 32 or 64  */
+    int   labels_per_lane;  /* 0 = automatic; else 1..8 with tile_lanes*lpl >= K        */
+} dm_discrete_params;
+
+size_t dm_solve_discrete_workspace(dm_shape s, dm_dtype cost_dtype, const dm_discrete_params* p);
+
+int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const float* w_h, const float* w_v,
+                      dm_shape s, const dm_discrete_params* p,
+                      int32_t* labels_out, float* minmarg_out, float* dual_inout,
+                      double* bounds_out, double* lb_trace_out,
+                      void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Status text for a dm_status value, and the thread-local detail of the last error. */
+const char* dm_status_string(int status);
+const char* dm_last_error_message(void);
+
+/* Library build identifier (gfx target and feature list). */
+const char* dm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMATCH_H */

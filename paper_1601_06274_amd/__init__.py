@@ -1,0 +1,16 @@
+"""MI355X (gfx950) library for discrete-continuous dense matching.
+
+Hot path of Shekhovtsov, Reinbacher, Graber and Pock, "Solving Dense Image
+Matching in Real-Time using Discrete-Continuous Optimization" (CVWW 2016):
+a W x H x K cost volume, the Dual_MM discrete solver over horizontal and
+vertical chains, and the continuous primal-dual refinement, all as hand-written
+HIP kernels behind the C ABI of ``include/dmatch.h``.
+
+The Python layer only marshals arguments (torch tensors for device memory and
+streams).  Importing the package does not load the shared library; the first
+call does, and it raises if ``libdmatch.so`` has not been built.
+"""
+from ._lib import DmError, lib  # noqa: F401
+from .ops import DiscreteResult, solve_discrete, tile_for  # noqa: F401
+
+__all__ = ["DmError", "lib", "DiscreteResult", "solve_discrete", "tile_for"]

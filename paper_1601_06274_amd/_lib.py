@@ -1,0 +1,87 @@
+"""ctypes view of the C ABI declared in include/dmatch.h (argument marshalling only).
+
+The shared library is built in place by ``paper_1601_06274_amd.build``.  Loading
+fails loudly when it is missing: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdmatch.so")
+
+DM_OK = 0
+DM_F32 = 0
+DM_F16 = 1
+DM_MINORANT_ITERATIVE = 0
+DM_MINORANT_NAIVE = 1
+
+STATUS_NAMES = {
+    0: "DM_OK", -1: "DM_ERR_NULL", -2: "DM_ERR_SHAPE", -3: "DM_ERR_PARAM", -4: "DM_ERR_DTYPE",
+    -5: "DM_ERR_WORKSPACE", -6: "DM_ERR_UNSUPPORTED", -7: "DM_ERR_HIP",
+}
+
+
+class DmShape(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_int), ("H", ctypes.c_int), ("K", ctypes.c_int)]
+
+
+class DmCostParams(ctypes.Structure):
+    _fields_ = [("window", ctypes.c_int), ("trunc", ctypes.c_float), ("lambda_pw", ctypes.c_float),
+                ("contrast_sigma", ctypes.c_float)]
+
+
+class DmDiscreteParams(ctypes.Structure):
+    _fields_ = [("n_iters", ctypes.c_int), ("n_half_steps", ctypes.c_int), ("trunc_T", ctypes.c_int),
+                ("minorant", ctypes.c_int), ("max_pass", ctypes.c_int), ("gamma", ctypes.c_float * 8),
+                ("warm_start", ctypes.c_int), ("tile_lanes", ctypes.c_int), ("labels_per_lane", ctypes.c_int)]
+
+
+class DmError(RuntimeError):
+    def __init__(self, fn: str, status: int, detail: str):
+        super().__init__(f"{fn} failed: {STATUS_NAMES.get(status, status)}: {detail}")
+        self.status = status
+
+
+_lib = None
+
+# (name, restype, argtypes) for every exported symbol declared in include/dmatch.h
+_VP = ctypes.c_void_p
+_SIGNATURES = [
+    ("dm_build_cost_volume", ctypes.c_int,
+     [_VP, _VP, DmShape, ctypes.POINTER(DmCostParams), ctypes.c_int, _VP, _VP, _VP, _VP]),
+    ("dm_solve_discrete_workspace", ctypes.c_size_t, [DmShape, ctypes.c_int, ctypes.POINTER(DmDiscreteParams)]),
+    ("dm_solve_discrete", ctypes.c_int,
+     [_VP, ctypes.c_int, _VP, _VP, DmShape, ctypes.POINTER(DmDiscreteParams), _VP, _VP, _VP, _VP, _VP, _VP,
+      ctypes.c_size_t, _VP]),
+    ("dm_status_string", ctypes.c_char_p, [ctypes.c_int]),
+    ("dm_last_error_message", ctypes.c_char_p, []),
+    ("dm_version", ctypes.c_char_p, []),
+]
+
+
+def exported_names():
+    return [n for n, _, _ in _SIGNATURES]
+
+
+def lib():
+    """Load libdmatch.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1601_06274_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGNATURES:
+            if hasattr(L, name):
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(fn: str, status: int):
+    if status != DM_OK:
+        detail = lib().dm_last_error_message().decode(errors="replace")
+        raise DmError(fn, status, detail)

@@ -1,0 +1,40 @@
+// common.h - host-side helpers shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "../../include/dmatch.h"
+
+namespace dm {
+
+// Thread-local detail for dm_last_error_message().
+void set_error(const char* fmt, ...);
+void clear_error();
+
+// Converts a pending HIP error (sticky or from the last launch) into DM_ERR_HIP.
+int check_hip(const char* where);
+
+#define DM_REQUIRE(cond, code, ...)            \
+    do {                                       \
+        if (!(cond)) {                         \
+            ::dm::set_error(__VA_ARGS__);      \
+            return (code);                     \
+        }                                      \
+    } while (0)
+
+#define DM_HIP_TRY(expr, where)                                                           \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            ::dm::set_error("%s: %s (%s)", (where), hipGetErrorName(e_), hipGetErrorString(e_)); \
+            return DM_ERR_HIP;                                                            \
+        }                                                                                 \
+    } while (0)
+
+int validate_shape(const dm_shape& s);
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace dm
