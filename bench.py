@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark: one frame of the discrete-continuous stereo hot path on one MI355X.
+
+Workload (default): a 1242 x 375 stereo frame with K = 192 disparities from the
+seeded synthetic generator (textured left image, slanted piecewise-planar
+disparity, 4 occlusion bands, sensor noise; it stands in for driving-scene
+frames of that size).  One step is
+
+    build_cost_volume (3x3 SAD, truncated at 0.3, stored FP16; contrast weights)
+    -> solve_discrete  (Dual_MM, 20 dual iterations, iterative minorant, T = 3)
+    -> refine_continuous (5 warps x 40 primal-dual iterations)
+
+on images already resident in HBM.  ``value`` is the whole-step throughput in
+chain-DP label-node updates per second: every dual iteration visits every
+label-node in 8 chain sweeps (4 per half-step), the final labeling in 2 more.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+
+WORKLOAD = dict(W=1242, H=375, K=192, seed=3000, slope=0.08, occlusion_bands=4, segments=16,
+                n_iters=20, T=3, gammas=(0.25, 0.25, 1.0), n_warps=5, refine_iters=40, C=3.0)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(pair, wl, target_s):
+    """The FP64 oracle, as it is, on a bounded sample of the same frame: horizontal
+    half-steps on a band of rows and vertical half-steps on a band of columns of the
+    frame's cost volume.  Returns label-node updates / s (4 sweeps per half-step)."""
+    from oracle import cost_volume as ocv, dmm as odmm
+    rows = 16
+    th_rows = ocv.sad_cost_volume(pair.left[:rows], pair.right[:rows], wl["K"])
+    w_h, _ = ocv.contrast_weights(pair.left[:rows])
+    cols = 32
+    th_cols = ocv.sad_cost_volume(pair.left[:, :cols], pair.right[:, :cols], wl["K"])
+    _, w_v = ocv.contrast_weights(pair.left[:, :cols])
+    updates = 0
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        lam = np.zeros_like(th_rows)
+        lam = odmm.half_step(th_rows, lam, w_h, np.zeros((rows - 1, wl["W"])), wl["T"], "h", gammas=wl["gammas"])
+        updates += th_rows.size * 4
+        lam = np.zeros_like(th_cols)
+        odmm.half_step(th_cols, lam, np.zeros((wl["H"], cols - 1)), w_v, wl["T"], "v", gammas=wl["gammas"])
+        updates += th_cols.size * 4
+        reps += 1
+        if time.perf_counter() - t0 >= target_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": updates / el, "unit": "label-node updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps}x (horizontal half-step on {rows} rows x {wl['W']} + vertical half-step on "
+                      f"{cols} columns x {wl['H']}) of the frame's cost volume, K={wl['K']}, FP64 numpy, "
+                      f"{el:.1f} s, single thread"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        return 2
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        return 1
+    import synth
+    import paper_1601_06274_amd as P
+    from paper_1601_06274_amd import ops
+
+    wl = WORKLOAD
+    W, H, K = wl["W"], wl["H"], wl["K"]
+    pair = synth.stereo_pair(W, H, K, seed=wl["seed"], segments=wl["segments"], slope=wl["slope"],
+                             occlusion_bands=wl["occlusion_bands"])
+    dev = torch.device("cuda:0")
+    IL = torch.from_numpy(pair.left).to(dev)
+    IR = torch.from_numpy(pair.right).to(dev)
+    cost = torch.empty((H, W, K), dtype=torch.float16, device=dev)
+    w_h = torch.empty((H, W - 1), dtype=torch.float32, device=dev)
+    w_v = torch.empty((H - 1, W), dtype=torch.float32, device=dev)
+    dual = torch.empty((H, W, K), dtype=torch.float32, device=dev)
+    minmarg = torch.empty((H, W, K), dtype=torch.float32, device=dev)
+    labels = torch.empty((H, W), dtype=torch.int32, device=dev)
+    u = torch.empty((H, W), dtype=torch.float32, device=dev)
+    import ctypes
+    lib = P.lib()
+    dp = ops.discrete_params(T=wl["T"], n_iters=wl["n_iters"], gammas=wl["gammas"])
+    ws_d = torch.empty(lib.dm_solve_discrete_workspace(P._lib.DmShape(W, H, K), P._lib.DM_F16, ctypes.byref(dp)),
+                       dtype=torch.uint8, device=dev)
+    rp = ops.refine_params(C=wl["C"], n_warps=wl["n_warps"], n_iters=wl["refine_iters"])
+    ws_r = torch.empty(lib.dm_refine_continuous_workspace(P._lib.DmShape(W, H, K), ctypes.byref(rp)),
+                       dtype=torch.uint8, device=dev)
+
+    def step():
+        ops.build_cost_volume(IL, IR, K, dtype=torch.float16, cost_out=cost, w_h=w_h, w_v=w_v)
+        res = ops.solve_discrete(cost, w_h, w_v, T=wl["T"], n_iters=wl["n_iters"], gammas=wl["gammas"], dual=dual,
+                                 workspace=ws_d, labels=labels, minmarg=minmarg, want_bounds=True)
+        ops.refine_continuous(cost, labels, w_h, w_v, C=wl["C"], n_warps=wl["n_warps"], n_iters=wl["refine_iters"],
+                              workspace=ws_r, u_out=u)
+        return res
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # Timed region: the sweep kernels are bracketed by HIP events on their stream.
+    ops.profiler_enable(["sweep_h", "sweep_v", "sweep_final", "cost_volume"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ops.profiler_disable()
+    ms_per_step = el * 1e3 / args.steps
+
+    prof = {k: ops.profiler_query(k) for k in ["sweep_h", "sweep_v", "sweep_final", "cost_volume"]}
+    n_h, ms_h, by_h = prof["sweep_h"]
+    achieved = (by_h / n_h) / (ms_h / n_h * 1e-3) / 1e9 if n_h else 0.0
+    per_launch_gb = by_h / n_h / 1e9 if n_h else 0.0
+
+    # Bandwidth-level traffic from rocprofv3 counters of the same kernel, if recorded.
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "sweep_h_traffic.json")
+    if os.path.exists(tpath):
+        try:
+            with open(tpath) as f:
+                t = json.load(f)
+            if t.get("kernel_source_hash") == _sweep_source_hash():
+                traffic = t.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    N = H * W * K
+    updates = N * (8 * wl["n_iters"] + 2)
+    bounds = res.bounds.cpu().numpy()
+
+    out = {
+        "metric": "chain-DP label-node updates/s + HBM GB/s; fwd+bwd ms/frame at 1242x375x192",
+        "value": updates / (ms_per_step * 1e-3),
+        "unit": "label-node updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "stereo 1242x375, K=192 disparities, FP16 cost volume (3x3 SAD), Dual_MM 20 dual its "
+                        "(iterative minorant 1/4,1/4,1, T=3) + refinement 5 warps x 40 its; forward only "
+                        "(backward not yet in the step)",
+            "W": W, "H": H, "K": K, "cost_storage": "f16", "state": "f32",
+            "stages": ["build_cost_volume", "solve_discrete", "refine_continuous"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "horizontal half-step chain sweep (R0 + 3 update passes, FP16 cost)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "alg_bytes_per_launch": by_h / n_h if n_h else None,
+            "avg_launch_ms": ms_h / n_h if n_h else None,
+        },
+        "stage_ms": {
+            "cost_volume": prof["cost_volume"][1] / max(prof["cost_volume"][0], 1),
+            "sweep_h_per_launch": ms_h / max(n_h, 1),
+            "sweep_v_per_launch": prof["sweep_v"][1] / max(prof["sweep_v"][0], 1),
+            "sweep_v_GBps": (prof["sweep_v"][2] / prof["sweep_v"][1] / 1e6) if prof["sweep_v"][1] else None,
+            "final_per_launch": prof["sweep_final"][1] / max(prof["sweep_final"][0], 1),
+        },
+        "lower_bound": float(bounds[0]),
+        "energy": float(bounds[1]),
+        "alg_gb_per_sweep_h": per_launch_gb,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pair, wl, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def _sweep_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for fn in ["dmm_kernels.h", "wave.h"]:
+        with open(os.path.join(ROOT, "paper_1601_06274_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    sys.exit(main())

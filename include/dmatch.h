@@ -121,6 +121,61 @@ int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const float* w_h, c
                       double* bounds_out, double* lb_trace_out,
                       void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* ---------------------------------------------------------------------------------
+ * Continuous refinement (paper Sec. 2.4 and Sec. 3.1).
+ *
+ * Minimises D(u) + sum_e w_e r((Au)_e) with (Au)_e = u_i - u_j over the grid edges and
+ * r = r_{eps,delta} - r_{0, C + delta - eps*delta}  (eq. r-decompose; eps = 1, delta = 0
+ * gives r(t) = min(|t|, C)), by Valkonen's non-linear primal-dual iteration
+ * (eq. cont_iterates) on the reformulation with x = (u, q), y = (p, 1):
+ *     u+ = prox_{tau D~}(u - tau A^T (p - q)),  q+ = prox_{tau R_-^*}(q + tau A u),
+ *     p+ = prox_{sigma R_+^*}(p + sigma A (2u+ - u))     (conjugate proxes: eq. pprox).
+ * The data term is replaced around u0 by the convex two-slope model D~ of Sec. 3.1 on
+ * [u0 - h, u0 + h] (intersected with [0, K-1]); D between labels is the linear
+ * interpolation of the cost volume along the label axis.  Slopes:
+ * s_L = (D(u0) - D(u0-h))/h, s_R = (D(u0+h) - D(u0))/h, both set to their mean when
+ * s_L > s_R; at the ends of the label range the missing slope copies the other.
+ * Every warp re-linearises at the current u and runs n_iters iterations.  Start:
+ * u = u0 = labels (as floats), p = q = 0.
+ *
+ * labels: [H][W] int32 in [0, K-1] (values outside are clamped).  u_out: [H][W] float32.
+ * Parameter ranges: C > 0, eps in [0, 1], delta >= 0, h > 0, tau > 0, sigma > 0
+ * (convergence needs tau * sigma * 8 < 1), n_warps >= 0, n_iters >= 0.
+ * ------------------------------------------------------------------------------- */
+typedef struct { float C, eps, delta, h, tau, sigma; int n_warps, n_iters; } dm_refine_params;
+
+size_t dm_refine_continuous_workspace(dm_shape s, const dm_refine_params* p);
+
+int dm_refine_continuous(const void* cost, dm_dtype cost_dtype, const int32_t* labels,
+                         const float* w_h, const float* w_v, dm_shape s, const dm_refine_params* p,
+                         float* u_out, void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* ---------------------------------------------------------------------------------
+ * Kernel profiler.  While enabled, every kernel launch of the library is bracketed by
+ * HIP events recorded on the launch stream, and tagged with a kind and with the
+ * algorithmic HBM bytes of that launch (bytes the method must move, not counters).
+ * dm_profiler_query waits for the recorded events and returns, for one kind, the
+ * number of launches, the summed event time and the summed algorithmic bytes.
+ * Host-side state, process-wide; not thread-safe against concurrent solver calls.
+ * ------------------------------------------------------------------------------- */
+typedef enum {
+    DM_PROF_SWEEP_H = 0,          /* horizontal half-step (rows of F)              */
+    DM_PROF_SWEEP_V = 1,          /* vertical half-step (columns of G)             */
+    DM_PROF_SWEEP_FINAL = 2,      /* final row min-marginal / label pass           */
+    DM_PROF_SWEEP_OPT = 3,        /* column optimum pass for the bound             */
+    DM_PROF_BOUNDS = 4,           /* energy / bound reductions                     */
+    DM_PROF_COST_VOLUME = 5,      /* SAD cost volume + contrast weights            */
+    DM_PROF_REFINE_LINEARIZE = 6, /* per-warp data-term linearisation              */
+    DM_PROF_REFINE_ITER = 7,      /* primal-dual iteration                         */
+    DM_PROF_OTHER = 8,            /* fills, copies                                 */
+    DM_PROF_KINDS = 16
+} dm_prof_kind;
+
+/* kind_mask != 0: clear all records and record launches of the kinds whose bit
+ * (1 << kind) is set; kind_mask == 0: stop recording (records stay queryable). */
+int dm_profiler_enable(unsigned kind_mask);
+int dm_profiler_query(int kind, long long* launches, double* total_ms, double* alg_bytes);
+
 /* Status text for a dm_status value, and the thread-local detail of the last error. */
 const char* dm_status_string(int status);
 const char* dm_last_error_message(void);

@@ -17,6 +17,9 @@ DM_F16 = 1
 DM_MINORANT_ITERATIVE = 0
 DM_MINORANT_NAIVE = 1
 
+PROF_KINDS = {"sweep_h": 0, "sweep_v": 1, "sweep_final": 2, "sweep_opt": 3, "bounds": 4, "cost_volume": 5,
+              "refine_linearize": 6, "refine_iter": 7, "other": 8}
+
 STATUS_NAMES = {
     0: "DM_OK", -1: "DM_ERR_NULL", -2: "DM_ERR_SHAPE", -3: "DM_ERR_PARAM", -4: "DM_ERR_DTYPE",
     -5: "DM_ERR_WORKSPACE", -6: "DM_ERR_UNSUPPORTED", -7: "DM_ERR_HIP",
@@ -38,6 +41,11 @@ class DmDiscreteParams(ctypes.Structure):
                 ("warm_start", ctypes.c_int), ("tile_lanes", ctypes.c_int), ("labels_per_lane", ctypes.c_int)]
 
 
+class DmRefineParams(ctypes.Structure):
+    _fields_ = [("C", ctypes.c_float), ("eps", ctypes.c_float), ("delta", ctypes.c_float), ("h", ctypes.c_float),
+                ("tau", ctypes.c_float), ("sigma", ctypes.c_float), ("n_warps", ctypes.c_int), ("n_iters", ctypes.c_int)]
+
+
 class DmError(RuntimeError):
     def __init__(self, fn: str, status: int, detail: str):
         super().__init__(f"{fn} failed: {STATUS_NAMES.get(status, status)}: {detail}")
@@ -55,6 +63,12 @@ _SIGNATURES = [
     ("dm_solve_discrete", ctypes.c_int,
      [_VP, ctypes.c_int, _VP, _VP, DmShape, ctypes.POINTER(DmDiscreteParams), _VP, _VP, _VP, _VP, _VP, _VP,
       ctypes.c_size_t, _VP]),
+    ("dm_refine_continuous_workspace", ctypes.c_size_t, [DmShape, ctypes.POINTER(DmRefineParams)]),
+    ("dm_refine_continuous", ctypes.c_int,
+     [_VP, ctypes.c_int, _VP, _VP, _VP, DmShape, ctypes.POINTER(DmRefineParams), _VP, _VP, ctypes.c_size_t, _VP]),
+    ("dm_profiler_enable", ctypes.c_int, [ctypes.c_uint]),
+    ("dm_profiler_query", ctypes.c_int,
+     [ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     ("dm_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("dm_last_error_message", ctypes.c_char_p, []),
     ("dm_version", ctypes.c_char_p, []),

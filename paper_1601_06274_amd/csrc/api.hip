@@ -1,6 +1,9 @@
 // api.hip - status strings, error reporting and shared validation of the C ABI.
 #include <string.h>
 
+#include <mutex>
+#include <vector>
+
 #include "common.h"
 
 namespace dm {
@@ -32,7 +35,96 @@ int validate_shape(const dm_shape& s) {
     return DM_OK;
 }
 
+// ------------------------------------------------------------------ profiler
+namespace {
+struct ProfRecord {
+    int kind;
+    double bytes;
+    hipEvent_t start, stop;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+unsigned g_prof_mask = 0;
+std::vector<ProfRecord> g_prof;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t take_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+void recycle_all() {
+    for (auto& r : g_prof) {
+        if (r.start) g_event_pool.push_back(r.start);
+        if (r.stop) g_event_pool.push_back(r.stop);
+    }
+    g_prof.clear();
+}
+}  // namespace
+
+bool profiler_on() { return g_prof_on; }
+
+int profiler_begin(int kind, double bytes, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on || !(g_prof_mask & (1u << kind))) return -1;
+    ProfRecord r{kind, bytes, take_event(), take_event()};
+    if (!r.start || !r.stop) return -1;
+    if (hipEventRecord(r.start, s) != hipSuccess) return -1;
+    g_prof.push_back(r);
+    return (int)g_prof.size() - 1;
+}
+
+void profiler_end(int id, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (id < 0 || id >= (int)g_prof.size()) return;
+    (void)hipEventRecord(g_prof[id].stop, s);
+}
+
 }  // namespace dm
+
+extern "C" int dm_profiler_enable(unsigned kind_mask) {
+    std::lock_guard<std::mutex> lk(dm::g_prof_mu);
+    const bool on = kind_mask != 0;
+    if (on) {
+        for (auto& r : dm::g_prof) {
+            (void)hipEventSynchronize(r.stop);
+        }
+        dm::recycle_all();
+    }
+    dm::g_prof_on = on;
+    if (on) dm::g_prof_mask = kind_mask;
+    return DM_OK;
+}
+
+extern "C" int dm_profiler_query(int kind, long long* launches, double* total_ms, double* alg_bytes) {
+    std::lock_guard<std::mutex> lk(dm::g_prof_mu);
+    long long n = 0;
+    double ms = 0.0, bytes = 0.0;
+    for (auto& r : dm::g_prof) {
+        if (r.kind != kind) continue;
+        if (hipEventSynchronize(r.stop) != hipSuccess) {
+            dm::set_error("profiler: event synchronize failed");
+            return DM_ERR_HIP;
+        }
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, r.start, r.stop) != hipSuccess) {
+            dm::set_error("profiler: elapsed time failed");
+            return DM_ERR_HIP;
+        }
+        ++n;
+        ms += t;
+        bytes += r.bytes;
+    }
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = ms;
+    if (alg_bytes) *alg_bytes = bytes;
+    return DM_OK;
+}
 
 extern "C" const char* dm_status_string(int status) {
     switch (status) {

@@ -37,4 +37,21 @@ int validate_shape(const dm_shape& s);
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Kernel profiler (see dm_profiler_enable).  Usage around a launch:
+//     ProfScope ps(DM_PROF_SWEEP_H, bytes, stream);  launch(...);  ps.stop();
+bool profiler_on();
+int profiler_begin(int kind, double bytes, hipStream_t s);   // returns record id or -1
+void profiler_end(int id, hipStream_t s);
+
+struct ProfScope {
+    int id;
+    hipStream_t s;
+    ProfScope(int kind, double bytes, hipStream_t st) : id(profiler_on() ? profiler_begin(kind, bytes, st) : -1), s(st) {}
+    void stop() {
+        if (id >= 0) profiler_end(id, s);
+        id = -1;
+    }
+    ~ProfScope() { stop(); }
+};
+
 }  // namespace dm

@@ -82,12 +82,15 @@ extern "C" int dm_build_cost_volume(const float* I_left, const float* I_right, d
     const unsigned blocks = (unsigned)std::min<long long>((total + 255) / 256, 65535LL * 8);
     const int r = p->window / 2;
     const float inv_area = 1.0f / (float)(p->window * p->window);
+    // algorithmic bytes: the volume written once, the two images read once
+    ProfScope ps(DM_PROF_COST_VOLUME, (double)total * (out_dtype == DM_F16 ? 2 : 4) + 8.0 * s.W * s.H, stream);
     if (out_dtype == DM_F16)
         hipLaunchKernelGGL(sad_kernel<_Float16>, dim3(blocks), dim3(256), 0, stream, I_left, I_right, s.W, s.H, s.K, r,
                            p->trunc, inv_area, static_cast<_Float16*>(cost_out));
     else
         hipLaunchKernelGGL(sad_kernel<float>, dim3(blocks), dim3(256), 0, stream, I_left, I_right, s.W, s.H, s.K, r,
                            p->trunc, inv_area, static_cast<float*>(cost_out));
+    ps.stop();
     DM_HIP_TRY(hipGetLastError(), "sad launch");
     if (w_h != nullptr || w_v != nullptr) {
         const long long npx = (long long)s.W * s.H;

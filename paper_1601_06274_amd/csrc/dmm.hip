@@ -159,6 +159,34 @@ hipError_t launch_sweep(Tile t, const SweepArgs& a, dm_dtype dt, hipStream_t st)
     return hipErrorInvalidValue;
 }
 
+// Algorithmic HBM bytes of one sweep launch: what the passes must read and write per
+// label-node (cost b bytes, dual / messages / min-marginals 4 bytes), times the labels.
+double sweep_bytes(const SweepArgs& a, dm_dtype dt) {
+    const double b = a.theta != nullptr ? (dt == DM_F16 ? 2.0 : 4.0) : 0.0;
+    const double nodes = (double)a.n * a.n_chains * a.K;
+    double per = 0.0;
+    switch (a.mode) {
+        case kModeIterative:
+            per = b + 8.0;                                 // R0: cost, dual; message out
+            for (int s = 0; s < a.n_pass; ++s) per += (s < a.n_pass - 1) ? b + 16.0 : b + 12.0;
+            break;
+        case kModeNaive: per = (b + 8.0) + (b + 12.0); break;
+        case kModeOptimum: per = b + 4.0; break;
+        case kModeFinal: per = (b + 8.0) + (b + 8.0) + (a.minmarg != nullptr ? 4.0 : 0.0); break;
+        default: break;
+    }
+    return per * nodes + (a.mode == kModeFinal ? 4.0 * a.n * a.n_chains : 0.0);
+}
+
+hipError_t launch_sweep_prof(Tile t, const SweepArgs& a, dm_dtype dt, hipStream_t st) {
+    int kind = DM_PROF_SWEEP_H;
+    if (a.mode == kModeFinal) kind = DM_PROF_SWEEP_FINAL;
+    else if (a.mode == kModeOptimum) kind = DM_PROF_SWEEP_OPT;
+    else if (a.theta == nullptr) kind = DM_PROF_SWEEP_V;
+    ProfScope ps(kind, profiler_on() ? sweep_bytes(a, dt) : 0.0, st);
+    return launch_sweep(t, a, dt, st);
+}
+
 struct WsLayout {
     size_t msg, opt, partial, labels, total;
     long long max_chains;
@@ -264,6 +292,7 @@ extern "C" int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const fl
     const long long vol = (long long)s.W * s.H * s.K;
     DM_REQUIRE(vol * 4 < (long long)kOOB, DM_ERR_UNSUPPORTED, "volume of %lld labels exceeds the 4 GiB buffer range", vol);
     if (!p->warm_start) {
+        ProfScope ps(DM_PROF_OTHER, 4.0 * vol, stream);
         hipLaunchKernelGGL(fill_f32_kernel, dim3(2048), dim3(256), 0, stream, dual_inout, vol, 0.0f);
         DM_HIP_TRY(hipGetLastError(), "fill dual");
     }
@@ -308,7 +337,7 @@ extern "C" int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const fl
     for (int k = 0; k < S; ++k) {
         SweepArgs a = (k % 2 == 0) ? rows : cols;
         a.opt = want_bounds ? opt + (long long)k * L.max_chains : nullptr;
-        DM_HIP_TRY(launch_sweep(tile, a, cost_dtype, stream), "half-step launch");
+        DM_HIP_TRY(launch_sweep_prof(tile, a, cost_dtype, stream), "half-step launch");
     }
     // Final row pass: normalized min-marginals of F, labels, row optima (slot S).
     {
@@ -317,7 +346,7 @@ extern "C" int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const fl
         a.minmarg = minmarg_out;
         a.labels = labels;
         a.opt = want_bounds ? opt + (long long)S * L.max_chains : nullptr;
-        DM_HIP_TRY(launch_sweep(tile, a, cost_dtype, stream), "final pass launch");
+        DM_HIP_TRY(launch_sweep_prof(tile, a, cost_dtype, stream), "final pass launch");
     }
     if (want_bounds) {
         // G's optimum: preserved from the last vertical half-step if that was the last
@@ -327,9 +356,10 @@ extern "C" int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const fl
             SweepArgs a = cols;
             a.mode = kModeOptimum;
             a.opt = opt + (long long)(S + 1) * L.max_chains;
-            DM_HIP_TRY(launch_sweep(tile, a, cost_dtype, stream), "column optimum launch");
+            DM_HIP_TRY(launch_sweep_prof(tile, a, cost_dtype, stream), "column optimum launch");
             slot_g = S + 1;
         }
+        ProfScope ps(DM_PROF_BOUNDS, (double)s.W * s.H * ((cost_dtype == DM_F16 ? 2 : 4) + 12), stream);
         if (bounds_out != nullptr) {
             if (cost_dtype == DM_F16)
                 hipLaunchKernelGGL(energy_partial_kernel<_Float16>, dim3(kEnergyBlocks), dim3(256), 0, stream,

@@ -365,7 +365,12 @@ struct Walker {
     }
 };
 
-template <int G, int LPL, int PF, typename TT, bool FULL, bool HAS_THETA>
+// Mode groups compiled as separate kernels (separate symbols in profiles, and each
+// kernel holds only the passes it runs): half-step (iterative or naive minorant),
+// final row pass, column optimum pass.
+enum ModeGroup : int { kGroupHalfStep = 0, kGroupFinal = 1, kGroupOptimum = 2 };
+
+template <int G, int LPL, int PF, typename TT, bool FULL, bool HAS_THETA, int MG>
 __global__ __launch_bounds__(64) void chain_kernel(SweepArgs a) {
     constexpr int CPW = 64 / G;
     const int lane = threadIdx.x;
@@ -373,29 +378,30 @@ __global__ __launch_bounds__(64) void chain_kernel(SweepArgs a) {
     const int chain = blockIdx.x * CPW + lane / G;
     Walker<G, LPL, PF, TT, FULL, HAS_THETA> wk(a, chain, sub);
     double opt = 0.0;
-    const int mode = a.mode;
-    if (mode == kModeIterative) {
-        wk.template pass<false, 0>(0.0f, true, opt);
-        for (int s = 0; s < a.n_pass; ++s) {
-            const bool last = s == a.n_pass - 1;
-            // select instead of a dynamic index: keeps the argument block out of scratch
-            float g = a.gamma[0];
+    if constexpr (MG == kGroupHalfStep) {
+        if (a.mode == kModeIterative) {
+            wk.template pass<false, 0>(0.0f, true, opt);
+            for (int s = 0; s < a.n_pass; ++s) {
+                const bool last = s == a.n_pass - 1;
+                // select instead of a dynamic index: keeps the argument block out of scratch
+                float g = a.gamma[0];
 #pragma unroll
-            for (int i = 1; i < 8; ++i)
-                if (s == i) g = a.gamma[i];
-            if ((s & 1) == 0)
-                wk.template pass<true, 1>(g, !last, opt);
-            else
-                wk.template pass<false, 1>(g, !last, opt);
+                for (int i = 1; i < 8; ++i)
+                    if (s == i) g = a.gamma[i];
+                if ((s & 1) == 0)
+                    wk.template pass<true, 1>(g, !last, opt);
+                else
+                    wk.template pass<false, 1>(g, !last, opt);
+            }
+        } else {
+            wk.template pass<false, 0>(0.0f, true, opt);
+            wk.template pass<true, 2>(0.0f, false, opt);
         }
-    } else if (mode == kModeNaive) {
-        wk.template pass<false, 0>(0.0f, true, opt);
-        wk.template pass<true, 2>(0.0f, false, opt);
-    } else if (mode == kModeOptimum) {
-        wk.template pass<false, 0>(0.0f, false, opt);
-    } else if (mode == kModeFinal) {
+    } else if constexpr (MG == kGroupFinal) {
         wk.template pass<false, 0>(0.0f, true, opt);
         wk.template pass<true, 3>(0.0f, false, opt);
+    } else {
+        wk.template pass<false, 0>(0.0f, false, opt);
     }
     if (a.opt != nullptr && wk.ok && sub == 0) a.opt[chain] = opt;
 }
@@ -403,15 +409,28 @@ __global__ __launch_bounds__(64) void chain_kernel(SweepArgs a) {
 // ------------------------------------------------------------------ launch
 constexpr int kPF = 8;
 
-template <int G, int LPL, typename TT, bool HAS_THETA>
-hipError_t launch_tt(const SweepArgs& a, hipStream_t st) {
+template <int G, int LPL, typename TT, bool HAS_THETA, int MG>
+hipError_t launch_mg(const SweepArgs& a, hipStream_t st) {
     constexpr int CPW = 64 / G;
     const unsigned blocks = (unsigned)((a.n_chains + CPW - 1) / CPW);
     if (a.K == G * LPL)
-        hipLaunchKernelGGL((chain_kernel<G, LPL, kPF, TT, true, HAS_THETA>), dim3(blocks), dim3(64), 0, st, a);
+        hipLaunchKernelGGL((chain_kernel<G, LPL, kPF, TT, true, HAS_THETA, MG>), dim3(blocks), dim3(64), 0, st, a);
     else
-        hipLaunchKernelGGL((chain_kernel<G, LPL, kPF, TT, false, HAS_THETA>), dim3(blocks), dim3(64), 0, st, a);
+        hipLaunchKernelGGL((chain_kernel<G, LPL, kPF, TT, false, HAS_THETA, MG>), dim3(blocks), dim3(64), 0, st, a);
     return hipGetLastError();
+}
+
+template <int G, int LPL, typename TT, bool HAS_THETA>
+hipError_t launch_tt(const SweepArgs& a, hipStream_t st) {
+    if (a.mode == kModeFinal) {
+        if constexpr (HAS_THETA) return launch_mg<G, LPL, TT, true, kGroupFinal>(a, st);
+        return hipErrorInvalidValue;
+    }
+    if (a.mode == kModeOptimum) {
+        if constexpr (!HAS_THETA) return launch_mg<G, LPL, TT, false, kGroupOptimum>(a, st);
+        return hipErrorInvalidValue;
+    }
+    return launch_mg<G, LPL, TT, HAS_THETA, kGroupHalfStep>(a, st);
 }
 
 template <int G, int LPL>

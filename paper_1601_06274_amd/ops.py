@@ -13,7 +13,8 @@ import torch
 
 from . import _lib as L
 
-__all__ = ["DiscreteResult", "solve_discrete", "discrete_params", "tile_for"]
+__all__ = ["DiscreteResult", "solve_discrete", "discrete_params", "tile_for", "refine_params", "refine_continuous",
+           "build_cost_volume"]
 
 
 def _ptr(t):
@@ -125,3 +126,72 @@ def solve_discrete(cost, w_h, w_v, *, T=3, n_iters=10, n_half_steps=0, minorant=
     L.check("dm_solve_discrete", st)
     return DiscreteResult(labels=labels, minmarg=minmarg, dual=dual, bounds=bounds,
                           lb_trace=None if trace is None else trace[:S])
+
+
+def refine_params(C=3.0, eps=1.0, delta=0.0, h=1.0, tau=0.3, sigma=0.3, n_warps=5, n_iters=40) -> L.DmRefineParams:
+    return L.DmRefineParams(float(C), float(eps), float(delta), float(h), float(tau), float(sigma), int(n_warps),
+                            int(n_iters))
+
+
+def refine_continuous(cost, labels, w_h, w_v, *, C=3.0, eps=1.0, delta=0.0, h=1.0, tau=0.3, sigma=0.3, n_warps=5,
+                      n_iters=40, stream=None, workspace=None, u_out=None):
+    """Warped non-linear primal-dual refinement (dm_refine_continuous); returns u [H][W] float32."""
+    H, W, K = cost.shape
+    _check_dev("cost", cost)
+    _check_dev("labels", labels, torch.int32, (H, W))
+    _check_dev("w_h", w_h, torch.float32, (H, W - 1))
+    _check_dev("w_v", w_v, torch.float32, (H - 1, W))
+    p = refine_params(C, eps, delta, h, tau, sigma, n_warps, n_iters)
+    shape = L.DmShape(W, H, K)
+    lib = L.lib()
+    ws_bytes = max(int(lib.dm_refine_continuous_workspace(shape, ctypes.byref(p))), 256)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=cost.device)
+    if u_out is None:
+        u_out = torch.empty((H, W), dtype=torch.float32, device=cost.device)
+    st = lib.dm_refine_continuous(_ptr(cost), _cost_dtype(cost), _ptr(labels), _ptr(w_h), _ptr(w_v), shape,
+                                  ctypes.byref(p), _ptr(u_out), _ptr(workspace), ctypes.c_size_t(workspace.numel()),
+                                  _stream(stream))
+    L.check("dm_refine_continuous", st)
+    return u_out
+
+
+def build_cost_volume(I_left, I_right, K, *, window=3, trunc=0.3, lambda_pw=0.1, contrast_sigma=0.1,
+                      dtype=torch.float32, stream=None, cost_out=None, w_h=None, w_v=None):
+    """Truncated windowed SAD cost volume and contrast weights (dm_build_cost_volume)."""
+    H, W = I_left.shape
+    _check_dev("I_left", I_left, torch.float32, (H, W))
+    _check_dev("I_right", I_right, torch.float32, (H, W))
+    dev = I_left.device
+    if cost_out is None:
+        cost_out = torch.empty((H, W, K), dtype=dtype, device=dev)
+    if w_h is None:
+        w_h = torch.empty((H, W - 1), dtype=torch.float32, device=dev)
+    if w_v is None:
+        w_v = torch.empty((H - 1, W), dtype=torch.float32, device=dev)
+    cp = L.DmCostParams(int(window), float(trunc), float(lambda_pw), float(contrast_sigma))
+    st = L.lib().dm_build_cost_volume(_ptr(I_left), _ptr(I_right), L.DmShape(W, H, K), ctypes.byref(cp),
+                                      _cost_dtype(cost_out), _ptr(cost_out), _ptr(w_h), _ptr(w_v), _stream(stream))
+    L.check("dm_build_cost_volume", st)
+    return cost_out, w_h, w_v
+
+
+def profiler_enable(kinds=None):
+    """Record HIP-event timings of library launches of the given kinds (names of
+    ``_lib.PROF_KINDS``; None = all).  Clears earlier records."""
+    mask = 0xFFFF if kinds is None else sum(1 << L.PROF_KINDS[k] for k in kinds)
+    L.check("dm_profiler_enable", L.lib().dm_profiler_enable(ctypes.c_uint(mask)))
+
+
+def profiler_disable():
+    L.check("dm_profiler_enable", L.lib().dm_profiler_enable(ctypes.c_uint(0)))
+
+
+def profiler_query(kind: str):
+    """(launches, total_ms, algorithmic_bytes) recorded for one kind."""
+    n = ctypes.c_longlong(0)
+    ms = ctypes.c_double(0.0)
+    by = ctypes.c_double(0.0)
+    L.check("dm_profiler_query", L.lib().dm_profiler_query(L.PROF_KINDS[kind], ctypes.byref(n), ctypes.byref(ms),
+                                                          ctypes.byref(by)))
+    return int(n.value), float(ms.value), float(by.value)
