@@ -109,8 +109,13 @@ typedef struct {
     int   max_pass;         /* 1..8 (iterative minorant)                                */
     float gamma[8];         /* each in (0, 1]; gamma[max_pass-1] == 1                   */
     int   warm_start;       /* 0: lambda := 0 first; 1: start from dual_inout           */
-    int   tile_lanes;       /* 0 = automatic; else lanes per chain: 4, 8, 16, 32 or 64  */
-    int   labels_per_lane;  /* 0 = automatic; else 1..8 with tile_lanes*lpl >= K        */
+    int   tile_lanes;       /* row chains: 0 = automatic; else lanes per chain (4..64)  */
+    int   labels_per_lane;  /* row chains: 0 = automatic; else with tile_lanes*lpl >= K */
+    int   tile_lanes_v;     /* column chains: 0 = same as rows (see dm_autotune_tiles)  */
+    int   labels_per_lane_v;
+    int   keep_checkpoints; /* 1: the workspace keeps the dual before every half-step
+                               (one FP32 volume each; the size query includes them) for
+                               dm_solve_discrete_backward                                */
 } dm_discrete_params;
 
 size_t dm_solve_discrete_workspace(dm_shape s, dm_dtype cost_dtype, const dm_discrete_params* p);
@@ -120,6 +125,38 @@ int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const float* w_h, c
                       int32_t* labels_out, float* minmarg_out, float* dual_inout,
                       double* bounds_out, double* lb_trace_out,
                       void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Autotuner: measures every compiled (lanes per chain, labels per lane) tile on one
+ * half-step of a synthetic instance of shape s (row and column chains separately) and
+ * writes the fastest into p->tile_lanes / labels_per_lane (rows) and tile_lanes_v /
+ * labels_per_lane_v (columns).  Allocates and frees scratch device memory (unlike the
+ * solver calls); synchronises hip_stream; results are cached for the process per
+ * (W, H, K, cost dtype, minorant, max_pass). */
+int dm_autotune_tiles(dm_shape s, dm_dtype cost_dtype, dm_discrete_params* p, void* hip_stream);
+
+/* Adjoint of dm_solve_discrete (reverse mode; the paper gives no derivative - this is
+ * the exact derivative of the piecewise-linear Dual_MM map as computed: minimisations
+ * route the adjoint to the selected candidate, lowest label on exact ties).
+ * Loss inputs: grad_minmarg [H][W][K] = dL/d(normalized row min-marginals) (may be NULL)
+ * and grad_lb = dL/d(lower bound) (the bound's derivative is the one-hot of the row and
+ * column optima, unique optima assumed).  Labels carry no gradient.
+ *   dual          [H][W][K] the final dual of the forward call.
+ *   fwd_workspace the forward's workspace, run with keep_checkpoints = 1 and the same
+ *                 parameters, unchanged since.
+ *   grad_cost     [H][W][K] float32 dL/dcost; grad_w_h, grad_w_v dL/dw (may be NULL).
+ *   accumulate    0: outputs overwritten; 1: gradients added.
+ * Per half-step (in reverse) the forward passes are recomputed from the checkpoint,
+ * keeping every pass's messages, then the passes are differentiated chain by chain.
+ * The backward workspace holds (max_pass + 1) message volumes, max_pass - 1 dual
+ * volumes, three adjoint volumes and FP64 edge accumulators. */
+size_t dm_solve_discrete_backward_workspace(dm_shape s, const dm_discrete_params* p);
+
+int dm_solve_discrete_backward(const float* grad_minmarg, double grad_lb, const void* cost,
+                               dm_dtype cost_dtype, const float* w_h, const float* w_v, dm_shape s,
+                               const dm_discrete_params* p, const float* dual,
+                               const void* fwd_workspace, size_t fwd_workspace_bytes,
+                               float* grad_cost, float* grad_w_h, float* grad_w_v, int accumulate,
+                               void* workspace, size_t workspace_bytes, void* hip_stream);
 
 /* ---------------------------------------------------------------------------------
  * Continuous refinement (paper Sec. 2.4 and Sec. 3.1).
@@ -142,13 +179,71 @@ int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const float* w_h, c
  * Parameter ranges: C > 0, eps in [0, 1], delta >= 0, h > 0, tau > 0, sigma > 0
  * (convergence needs tau * sigma * 8 < 1), n_warps >= 0, n_iters >= 0.
  * ------------------------------------------------------------------------------- */
-typedef struct { float C, eps, delta, h, tau, sigma; int n_warps, n_iters; } dm_refine_params;
+typedef struct {
+    float C, eps, delta, h, tau, sigma;
+    int   n_warps, n_iters;
+    int   keep_tape;   /* 1: the workspace also keeps, for the backward call, u0 of every warp
+                          (FP64 [H][W]) and the prox branch mask of every iteration (16 bits
+                          per pixel); the workspace query includes that space */
+} dm_refine_params;
 
 size_t dm_refine_continuous_workspace(dm_shape s, const dm_refine_params* p);
 
 int dm_refine_continuous(const void* cost, dm_dtype cost_dtype, const int32_t* labels,
                          const float* w_h, const float* w_v, dm_shape s, const dm_refine_params* p,
                          float* u_out, void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Adjoint of dm_refine_continuous (reverse mode through the unrolled iterations; no
+ * derivative in the paper - this is the exact derivative of the piecewise-linear
+ * iteration map, taking at exact branch ties the branch the forward took and, for the
+ * interpolated data term at an integer argument, the segment [k, k+1]).
+ *   grad_u      [H][W] float32: dL/du_out.
+ *   fwd_workspace: the workspace of the forward call, run with keep_tape = 1 and the
+ *               same parameters, unchanged since.
+ *   grad_cost   [H][W][K] float32: dL/dcost (nonzero only at the labels the data term
+ *               was interpolated from).  grad_w_h / grad_w_v: dL/dw (may be NULL).
+ *   accumulate  0: outputs are overwritten; 1: the gradients are added to them.
+ * The labels carry no gradient (piecewise constant).  Needs its own workspace of
+ * dm_refine_continuous_backward_workspace() bytes. */
+size_t dm_refine_continuous_backward_workspace(dm_shape s, const dm_refine_params* p);
+
+int dm_refine_continuous_backward(const float* grad_u, const void* cost, dm_dtype cost_dtype,
+                                  const float* w_h, const float* w_v, dm_shape s,
+                                  const dm_refine_params* p, const void* fwd_workspace,
+                                  size_t fwd_workspace_bytes, float* grad_cost, float* grad_w_h,
+                                  float* grad_w_v, int accumulate, void* workspace,
+                                  size_t workspace_bytes, void* hip_stream);
+
+/* ---------------------------------------------------------------------------------
+ * Batched form: many instances of uneven size (each with its own W, H, K) solved by
+ * one hipGraph launch.  dm_plan_batched picks a chain tile per labels count and chain
+ * family (dm_autotune_tiles unless p fixes tile_lanes), builds the work tables and
+ * captures: per half-step one persistent work-queue launch per tile class (lane
+ * groups of chains pulled from an atomic counter, longest chains first; classes run
+ * as parallel graph branches), the final row pass (labels), and - if rp != NULL - the
+ * refinement of every instance (one launch per primal-dual iteration over all
+ * instances' tiles).  The plan owns device memory (work tables, one message volume
+ * per instance, refinement state) until dm_plan_destroy; the caller owns every
+ * instance buffer, which must stay valid and at the same addresses.
+ * dm_run_batched replays the graph on hip_stream.  Instances with warm_start = 0 get
+ * dual := 0 at the start of every run.  All instances share the cost dtype and the
+ * parameters.  No bounds / min-marginals are produced in this form.
+ * ------------------------------------------------------------------------------- */
+typedef struct {
+    dm_shape s;
+    const void* cost;      /* [H][W][K] of the plan's cost dtype                    */
+    const float* w_h;      /* [H][W-1]                                              */
+    const float* w_v;      /* [H-1][W]                                              */
+    int32_t* labels;       /* [H][W] output                                         */
+    float* dual;           /* [H][W][K] dual state                                  */
+    float* u;              /* [H][W] refined disparities (required with refinement) */
+} dm_instance;
+
+int dm_plan_batched(const dm_instance* inst, int n, dm_dtype cost_dtype, const dm_discrete_params* p,
+                    const dm_refine_params* rp, void** plan_out);
+int dm_run_batched(void* plan, void* hip_stream);
+size_t dm_plan_device_bytes(const void* plan);
+void dm_plan_destroy(void* plan);
 
 /* ---------------------------------------------------------------------------------
  * Kernel profiler.  While enabled, every kernel launch of the library is bracketed by

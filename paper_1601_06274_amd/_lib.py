@@ -38,12 +38,19 @@ class DmCostParams(ctypes.Structure):
 class DmDiscreteParams(ctypes.Structure):
     _fields_ = [("n_iters", ctypes.c_int), ("n_half_steps", ctypes.c_int), ("trunc_T", ctypes.c_int),
                 ("minorant", ctypes.c_int), ("max_pass", ctypes.c_int), ("gamma", ctypes.c_float * 8),
-                ("warm_start", ctypes.c_int), ("tile_lanes", ctypes.c_int), ("labels_per_lane", ctypes.c_int)]
+                ("warm_start", ctypes.c_int), ("tile_lanes", ctypes.c_int), ("labels_per_lane", ctypes.c_int),
+                ("tile_lanes_v", ctypes.c_int), ("labels_per_lane_v", ctypes.c_int), ("keep_checkpoints", ctypes.c_int)]
 
 
 class DmRefineParams(ctypes.Structure):
     _fields_ = [("C", ctypes.c_float), ("eps", ctypes.c_float), ("delta", ctypes.c_float), ("h", ctypes.c_float),
-                ("tau", ctypes.c_float), ("sigma", ctypes.c_float), ("n_warps", ctypes.c_int), ("n_iters", ctypes.c_int)]
+                ("tau", ctypes.c_float), ("sigma", ctypes.c_float), ("n_warps", ctypes.c_int), ("n_iters", ctypes.c_int),
+                ("keep_tape", ctypes.c_int)]
+
+
+class DmInstance(ctypes.Structure):
+    _fields_ = [("s", DmShape), ("cost", ctypes.c_void_p), ("w_h", ctypes.c_void_p), ("w_v", ctypes.c_void_p),
+                ("labels", ctypes.c_void_p), ("dual", ctypes.c_void_p), ("u", ctypes.c_void_p)]
 
 
 class DmError(RuntimeError):
@@ -63,12 +70,27 @@ _SIGNATURES = [
     ("dm_solve_discrete", ctypes.c_int,
      [_VP, ctypes.c_int, _VP, _VP, DmShape, ctypes.POINTER(DmDiscreteParams), _VP, _VP, _VP, _VP, _VP, _VP,
       ctypes.c_size_t, _VP]),
+    ("dm_autotune_tiles", ctypes.c_int, [DmShape, ctypes.c_int, ctypes.POINTER(DmDiscreteParams), _VP]),
+    ("dm_solve_discrete_backward_workspace", ctypes.c_size_t, [DmShape, ctypes.POINTER(DmDiscreteParams)]),
+    ("dm_solve_discrete_backward", ctypes.c_int,
+     [_VP, ctypes.c_double, _VP, ctypes.c_int, _VP, _VP, DmShape, ctypes.POINTER(DmDiscreteParams), _VP, _VP,
+      ctypes.c_size_t, _VP, _VP, _VP, ctypes.c_int, _VP, ctypes.c_size_t, _VP]),
     ("dm_refine_continuous_workspace", ctypes.c_size_t, [DmShape, ctypes.POINTER(DmRefineParams)]),
     ("dm_refine_continuous", ctypes.c_int,
      [_VP, ctypes.c_int, _VP, _VP, _VP, DmShape, ctypes.POINTER(DmRefineParams), _VP, _VP, ctypes.c_size_t, _VP]),
     ("dm_profiler_enable", ctypes.c_int, [ctypes.c_uint]),
     ("dm_profiler_query", ctypes.c_int,
      [ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    ("dm_refine_continuous_backward_workspace", ctypes.c_size_t, [DmShape, ctypes.POINTER(DmRefineParams)]),
+    ("dm_refine_continuous_backward", ctypes.c_int,
+     [_VP, _VP, ctypes.c_int, _VP, _VP, DmShape, ctypes.POINTER(DmRefineParams), _VP, ctypes.c_size_t, _VP, _VP, _VP,
+      ctypes.c_int, _VP, ctypes.c_size_t, _VP]),
+    ("dm_plan_batched", ctypes.c_int,
+     [ctypes.POINTER(DmInstance), ctypes.c_int, ctypes.c_int, ctypes.POINTER(DmDiscreteParams),
+      ctypes.POINTER(DmRefineParams), ctypes.POINTER(ctypes.c_void_p)]),
+    ("dm_run_batched", ctypes.c_int, [_VP, _VP]),
+    ("dm_plan_device_bytes", ctypes.c_size_t, [_VP]),
+    ("dm_plan_destroy", None, [_VP]),
     ("dm_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("dm_last_error_message", ctypes.c_char_p, []),
     ("dm_version", ctypes.c_char_p, []),

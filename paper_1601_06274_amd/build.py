@@ -19,7 +19,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # (source, extra defines, object name)
 TILES = [(4, 1), (4, 2), (8, 4), (16, 4), (32, 3), (32, 4), (64, 3), (64, 4)]
 UNITS = [("api.hip", [], "api"), ("dmm.hip", [], "dmm"), ("cost_volume.hip", [], "cost_volume"),
-         ("refine.hip", [], "refine")]
+         ("refine.hip", [], "refine"), ("batched.hip", [], "batched")]
 UNITS += [("dmm_tile.hip", [f"-DDM_TILE_G={g}", f"-DDM_TILE_L={l}"], f"dmm_tile_{g}x{l}") for g, l in TILES]
 
 FLAGS = [

@@ -34,6 +34,7 @@ int check_hip(const char* where);
     } while (0)
 
 int validate_shape(const dm_shape& s);
+int validate_discrete(const dm_shape& s, const dm_discrete_params* p);
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 

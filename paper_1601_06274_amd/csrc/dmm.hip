@@ -5,11 +5,17 @@
 // dmm_kernels.h; each (lanes, labels-per-lane) tile is compiled in its own unit.
 #include <hip/hip_fp16.h>
 
-#include "dmm_kernels.h"
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "dmm_adjoint.h"
 
 namespace dm {
 
-#define DM_EXTERN_TILE(g, l) extern template hipError_t launch_tile<g, l>(const SweepArgs&, dm_dtype, hipStream_t);
+#define DM_EXTERN_TILE(g, l)                                                            \
+    extern template hipError_t launch_tile<g, l>(const SweepArgs&, dm_dtype, hipStream_t); \
+    extern template hipError_t launch_adjoint_tile<g, l>(const AdjArgs&, dm_dtype, hipStream_t);
 DM_EXTERN_TILE(4, 1)
 DM_EXTERN_TILE(4, 2)
 DM_EXTERN_TILE(8, 4)
@@ -25,6 +31,37 @@ __global__ void fill_f32_kernel(float* __restrict__ p, long long n, float v) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void copy_f32_kernel(const float* __restrict__ a, float* __restrict__ b, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) b[i] = a[i];
+}
+
+// Lower-bound adjoint of the column optima of G (unaries lambda): one-hot at the column
+// optimum labels, and the pairwise terms of the column optima for the vertical weights.
+__global__ void lb_col_adjoint_kernel(const int* __restrict__ lab, int W, int H, int K, int T, double g,
+                                      float* __restrict__ lbar, double* __restrict__ gw_v) {
+    const long long n = (long long)W * H;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
+        const int l = min(max(lab[p], 0), K - 1);
+        lbar[p * K + l] += (float)g;
+        if (p / W + 1 < H) {
+            const int d = abs(l - min(max(lab[p + W], 0), K - 1));
+            gw_v[p] += g * (double)(d < T ? d : T);
+        }
+    }
+}
+
+__global__ void zero_f64_kernel(double* __restrict__ p, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+__global__ void edge_out_kernel(const double* __restrict__ acc, long long n, int accumulate, float* __restrict__ out) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = (accumulate ? out[i] : 0.0f) + (float)acc[i];
 }
 
 // Per-block FP64 partial sums of the grid energy, fixed order.
@@ -144,9 +181,31 @@ Tile default_tile(int K) {
     return best;
 }
 
+Tile row_tile(const dm_shape& s, const dm_discrete_params& p) {
+    return p.tile_lanes != 0 ? Tile{p.tile_lanes, p.labels_per_lane} : default_tile(s.K);
+}
+Tile col_tile(const dm_shape& s, const dm_discrete_params& p) {
+    return p.tile_lanes_v != 0 ? Tile{p.tile_lanes_v, p.labels_per_lane_v} : row_tile(s, p);
+}
+
 hipError_t launch_sweep(Tile t, const SweepArgs& a, dm_dtype dt, hipStream_t st) {
 #define DM_TILE_CASE(g, l) \
     if (t.G == g && t.LPL == l) return launch_tile<g, l>(a, dt, st);
+    DM_TILE_CASE(4, 1)
+    DM_TILE_CASE(4, 2)
+    DM_TILE_CASE(8, 4)
+    DM_TILE_CASE(16, 4)
+    DM_TILE_CASE(32, 3)
+    DM_TILE_CASE(32, 4)
+    DM_TILE_CASE(64, 3)
+    DM_TILE_CASE(64, 4)
+#undef DM_TILE_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint(Tile t, const AdjArgs& a, dm_dtype dt, hipStream_t st) {
+#define DM_TILE_CASE(g, l) \
+    if (t.G == g && t.LPL == l) return launch_adjoint_tile<g, l>(a, dt, st);
     DM_TILE_CASE(4, 1)
     DM_TILE_CASE(4, 2)
     DM_TILE_CASE(8, 4)
@@ -188,7 +247,8 @@ hipError_t launch_sweep_prof(Tile t, const SweepArgs& a, dm_dtype dt, hipStream_
 }
 
 struct WsLayout {
-    size_t msg, opt, partial, labels, total;
+    size_t msg, opt, partial, labels, ckpt, total;
+    size_t vol_bytes;
     long long max_chains;
     int n_slots, n_partial;
 };
@@ -213,6 +273,9 @@ WsLayout layout(const dm_shape& s, const dm_discrete_params& p) {
     off = align_up(off + (size_t)L.n_partial * sizeof(double), 256);
     L.labels = off;
     off = align_up(off + (size_t)s.W * s.H * sizeof(int), 256);
+    L.vol_bytes = align_up(vol * sizeof(float), 256);
+    L.ckpt = off;
+    if (p.keep_checkpoints) off += (size_t)S * L.vol_bytes;  // dual before every half-step
     L.total = off;
     return L;
 }
@@ -236,11 +299,18 @@ int validate_params(const dm_shape& s, const dm_discrete_params* p) {
                    "gamma[max_pass-1] must be 1 for a maximal minorant (got %g)", (double)p->gamma[p->max_pass - 1]);
     }
     DM_REQUIRE(p->warm_start == 0 || p->warm_start == 1, DM_ERR_PARAM, "warm_start must be 0 or 1");
+    DM_REQUIRE(p->keep_checkpoints == 0 || p->keep_checkpoints == 1, DM_ERR_PARAM, "keep_checkpoints must be 0 or 1");
     if (p->tile_lanes != 0 || p->labels_per_lane != 0) {
         DM_REQUIRE(tile_compiled(p->tile_lanes, p->labels_per_lane), DM_ERR_UNSUPPORTED,
                    "tile %d lanes x %d labels is not compiled in", p->tile_lanes, p->labels_per_lane);
         DM_REQUIRE(p->tile_lanes * p->labels_per_lane >= s.K, DM_ERR_PARAM, "tile %dx%d holds fewer than K=%d labels",
                    p->tile_lanes, p->labels_per_lane, s.K);
+    }
+    if (p->tile_lanes_v != 0 || p->labels_per_lane_v != 0) {
+        DM_REQUIRE(tile_compiled(p->tile_lanes_v, p->labels_per_lane_v), DM_ERR_UNSUPPORTED,
+                   "column tile %d lanes x %d labels is not compiled in", p->tile_lanes_v, p->labels_per_lane_v);
+        DM_REQUIRE(p->tile_lanes_v * p->labels_per_lane_v >= s.K, DM_ERR_PARAM,
+                   "column tile %dx%d holds fewer than K=%d labels", p->tile_lanes_v, p->labels_per_lane_v, s.K);
     }
     return DM_OK;
 }
@@ -288,10 +358,23 @@ extern "C" int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const fl
     double* partial = reinterpret_cast<double*>(ws + L.partial);
     int* labels = labels_out != nullptr ? labels_out : reinterpret_cast<int*>(ws + L.labels);
 
-    const Tile tile = (p->tile_lanes != 0) ? Tile{p->tile_lanes, p->labels_per_lane} : default_tile(s.K);
+    const Tile tile = row_tile(s, *p), tile_v = col_tile(s, *p);
     const long long vol = (long long)s.W * s.H * s.K;
     DM_REQUIRE(vol * 4 < (long long)kOOB, DM_ERR_UNSUPPORTED, "volume of %lld labels exceeds the 4 GiB buffer range", vol);
-    if (!p->warm_start) {
+    const int S = half_step_count(*p);
+    // With checkpoints, half-step k reads the dual from ckpt[k] and writes ckpt[k+1] (the
+    // last one writes dual_inout): the checkpoints cost no extra traffic.
+    float* ckpt0 = reinterpret_cast<float*>(ws + L.ckpt);
+    auto ckpt = [&](int k) { return reinterpret_cast<float*>(ws + L.ckpt + (size_t)k * L.vol_bytes); };
+    const bool use_ckpt = p->keep_checkpoints && S > 0;
+    if (use_ckpt) {
+        ProfScope ps(DM_PROF_OTHER, 8.0 * vol, stream);
+        if (p->warm_start)
+            hipLaunchKernelGGL(copy_f32_kernel, dim3(2048), dim3(256), 0, stream, dual_inout, ckpt0, vol);
+        else
+            hipLaunchKernelGGL(fill_f32_kernel, dim3(2048), dim3(256), 0, stream, ckpt0, vol, 0.0f);
+        DM_HIP_TRY(hipGetLastError(), "init checkpoint");
+    } else if (!p->warm_start) {
         ProfScope ps(DM_PROF_OTHER, 4.0 * vol, stream);
         hipLaunchKernelGGL(fill_f32_kernel, dim3(2048), dim3(256), 0, stream, dual_inout, vol, 0.0f);
         DM_HIP_TRY(hipGetLastError(), "fill dual");
@@ -332,12 +415,15 @@ extern "C" int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const fl
     cols.sign = -1.0f;
     cols.inv_n = 1.0f / (float)s.H;
 
-    const int S = half_step_count(*p);
     const bool want_bounds = bounds_out != nullptr || lb_trace_out != nullptr;
     for (int k = 0; k < S; ++k) {
         SweepArgs a = (k % 2 == 0) ? rows : cols;
         a.opt = want_bounds ? opt + (long long)k * L.max_chains : nullptr;
-        DM_HIP_TRY(launch_sweep_prof(tile, a, cost_dtype, stream), "half-step launch");
+        if (use_ckpt) {
+            a.lam_in = ckpt(k);
+            a.lam = (k + 1 < S) ? ckpt(k + 1) : dual_inout;
+        }
+        DM_HIP_TRY(launch_sweep_prof(k % 2 == 0 ? tile : tile_v, a, cost_dtype, stream), "half-step launch");
     }
     // Final row pass: normalized min-marginals of F, labels, row optima (slot S).
     {
@@ -356,7 +442,7 @@ extern "C" int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const fl
             SweepArgs a = cols;
             a.mode = kModeOptimum;
             a.opt = opt + (long long)(S + 1) * L.max_chains;
-            DM_HIP_TRY(launch_sweep_prof(tile, a, cost_dtype, stream), "column optimum launch");
+            DM_HIP_TRY(launch_sweep_prof(tile_v, a, cost_dtype, stream), "column optimum launch");
             slot_g = S + 1;
         }
         ProfScope ps(DM_PROF_BOUNDS, (double)s.W * s.H * ((cost_dtype == DM_F16 ? 2 : 4) + 12), stream);
@@ -380,5 +466,375 @@ extern "C" int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const fl
             DM_HIP_TRY(hipGetLastError(), "lb trace launch");
         }
     }
+    return DM_OK;
+}
+
+// ------------------------------------------------------------------ backward
+namespace dm {
+namespace {
+
+struct BwdLayout {
+    size_t vol, msg, lam, bbar, lbar, gwh, gwv, lab, total;
+    int P;
+};
+
+BwdLayout bwd_layout(const dm_shape& s, const dm_discrete_params& p) {
+    BwdLayout L{};
+    L.P = p.minorant == DM_MINORANT_ITERATIVE ? p.max_pass : 1;
+    L.vol = align_up((size_t)s.W * s.H * s.K * sizeof(float), 256);
+    size_t off = 0;
+    L.msg = off;
+    off += (size_t)(L.P + 1) * L.vol;
+    L.lam = off;
+    off += (size_t)(L.P > 1 ? L.P - 1 : 0) * L.vol;
+    L.bbar = off;
+    off += 2 * L.vol;
+    L.lbar = off;
+    off += L.vol;
+    L.gwh = off;
+    off += align_up((size_t)s.H * (s.W > 1 ? s.W - 1 : 1) * sizeof(double), 256);
+    L.gwv = off;
+    off += align_up((size_t)(s.H > 1 ? s.H - 1 : 1) * s.W * sizeof(double), 256);
+    L.lab = off;
+    off += align_up((size_t)s.W * s.H * sizeof(int), 256);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+}  // namespace dm
+
+extern "C" size_t dm_solve_discrete_backward_workspace(dm_shape s, const dm_discrete_params* p) {
+    if (validate_params(s, p) != DM_OK) return 0;
+    return bwd_layout(s, *p).total;
+}
+
+extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad_lb, const void* cost,
+                                          dm_dtype cost_dtype, const float* w_h, const float* w_v, dm_shape s,
+                                          const dm_discrete_params* p, const float* dual, const void* fwd_workspace,
+                                          size_t fwd_workspace_bytes, float* grad_cost, float* grad_w_h,
+                                          float* grad_w_v, int accumulate, void* workspace, size_t workspace_bytes,
+                                          void* hip_stream) {
+    clear_error();
+    int st = validate_params(s, p);
+    if (st != DM_OK) return st;
+    DM_REQUIRE(cost_dtype == DM_F32 || cost_dtype == DM_F16, DM_ERR_DTYPE, "unknown cost dtype %d", (int)cost_dtype);
+    DM_REQUIRE(cost != nullptr && dual != nullptr && grad_cost != nullptr && fwd_workspace != nullptr, DM_ERR_NULL,
+               "cost, dual, grad_cost and the forward workspace are required");
+    DM_REQUIRE(s.W == 1 || w_h != nullptr, DM_ERR_NULL, "w_h is required when W > 1");
+    DM_REQUIRE(s.H == 1 || w_v != nullptr, DM_ERR_NULL, "w_v is required when H > 1");
+    DM_REQUIRE(p->keep_checkpoints == 1, DM_ERR_PARAM, "the forward must have been run with keep_checkpoints = 1");
+    DM_REQUIRE(accumulate == 0 || accumulate == 1, DM_ERR_PARAM, "accumulate must be 0 or 1");
+    const WsLayout LF = layout(s, *p);
+    DM_REQUIRE(fwd_workspace_bytes >= LF.total, DM_ERR_WORKSPACE, "forward workspace %zu bytes, need %zu",
+               fwd_workspace_bytes, LF.total);
+    const BwdLayout LB = bwd_layout(s, *p);
+    DM_REQUIRE(workspace != nullptr && workspace_bytes >= LB.total, DM_ERR_WORKSPACE, "workspace %zu bytes, need %zu",
+               workspace_bytes, LB.total);
+    const long long vol = (long long)s.W * s.H * s.K;
+    DM_REQUIRE(vol * 4 < (long long)kOOB, DM_ERR_UNSUPPORTED, "volume exceeds the 4 GiB buffer range");
+    DM_REQUIRE(((uintptr_t)cost % 16) == 0 && ((uintptr_t)dual % 16) == 0 && ((uintptr_t)grad_cost % 16) == 0 &&
+                   ((uintptr_t)grad_minmarg % 16) == 0 && ((uintptr_t)workspace % 256) == 0,
+               DM_ERR_PARAM, "volumes need 16-byte alignment, workspace 256");
+    {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            set_error("pending HIP error before dm_solve_discrete_backward: %s", hipGetErrorString(e));
+            return DM_ERR_HIP;
+        }
+    }
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const char* fws = static_cast<const char*>(fwd_workspace);
+    char* ws = static_cast<char*>(workspace);
+    auto vol_at = [&](size_t off, int i) { return reinterpret_cast<float*>(ws + off + (size_t)i * LB.vol); };
+    float* lbar = vol_at(LB.lbar, 0);
+    double* gwh = reinterpret_cast<double*>(ws + LB.gwh);
+    double* gwv = reinterpret_cast<double*>(ws + LB.gwv);
+    int* lab = reinterpret_cast<int*>(ws + LB.lab);
+    const Tile tile = row_tile(s, *p), tile_v = col_tile(s, *p);
+    const int S = half_step_count(*p);
+    const int P = LB.P;
+    const long long n_wh = (long long)s.H * (s.W - 1), n_wv = (long long)(s.H - 1) * s.W;
+
+    if (!accumulate) {
+        hipLaunchKernelGGL(fill_f32_kernel, dim3(2048), dim3(256), 0, stream, grad_cost, vol, 0.0f);
+        DM_HIP_TRY(hipGetLastError(), "zero grad");
+    }
+    if (n_wh > 0) hipLaunchKernelGGL(zero_f64_kernel, dim3(512), dim3(256), 0, stream, gwh, n_wh);
+    if (n_wv > 0) hipLaunchKernelGGL(zero_f64_kernel, dim3(512), dim3(256), 0, stream, gwv, n_wv);
+    DM_HIP_TRY(hipGetLastError(), "zero edge grads");
+
+    // Sweep descriptions (same as the forward) and the adjoint descriptions.
+    SweepArgs rows{};
+    rows.theta = cost;
+    rows.w = w_h;
+    rows.chain_px = s.W;
+    rows.node_px = 1;
+    rows.w_chain = s.W - 1;
+    rows.w_node = 1;
+    rows.vol_bytes_f32 = (unsigned)(vol * 4);
+    rows.vol_bytes_theta = (unsigned)(vol * (cost_dtype == DM_F16 ? 2 : 4));
+    rows.w_bytes = (unsigned)(n_wh * 4);
+    rows.K = s.K;
+    rows.n = s.W;
+    rows.n_chains = s.H;
+    rows.T = p->trunc_T;
+    rows.sign = 1.0f;
+    rows.inv_n = 1.0f / (float)s.W;
+    rows.n_pass = p->max_pass;
+    for (int i = 0; i < 8; ++i) rows.gamma[i] = p->gamma[i];
+    rows.mode = p->minorant == DM_MINORANT_NAIVE ? kModeNaive : kModeIterative;
+    for (int i = 0; i <= P && i < 9; ++i) rows.rec_msg[i] = vol_at(LB.msg, i);
+    for (int i = 1; i < P && i < 8; ++i) rows.rec_lam[i] = vol_at(LB.lam, i - 1);
+    rows.msg = rows.rec_msg[0];
+    rows.labels = lab;
+    SweepArgs cols = rows;
+    cols.theta = nullptr;
+    cols.w = w_v;
+    cols.w_bytes = (unsigned)(n_wv * 4);
+    cols.chain_px = 1;
+    cols.node_px = s.W;
+    cols.w_chain = 1;
+    cols.w_node = s.W;
+    cols.n = s.H;
+    cols.n_chains = s.W;
+    cols.sign = -1.0f;
+    cols.inv_n = 1.0f / (float)s.H;
+
+    auto adj_from = [&](const SweepArgs& a, double* gw) {
+        AdjArgs b{};
+        b.theta = a.theta;
+        b.w = a.w;
+        b.lbar = lbar;
+        b.bbar[0] = vol_at(LB.bbar, 0);
+        b.bbar[1] = vol_at(LB.bbar, 1);
+        b.grad_theta = a.theta != nullptr ? grad_cost : nullptr;
+        b.grad_w = gw;
+        for (int i = 0; i < 9; ++i) b.rec_msg[i] = a.rec_msg[i];
+        for (int i = 0; i < 8; ++i) b.rec_lam[i] = a.rec_lam[i];
+        b.chain_px = a.chain_px;
+        b.node_px = a.node_px;
+        b.w_chain = a.w_chain;
+        b.w_node = a.w_node;
+        b.vol_bytes_f32 = a.vol_bytes_f32;
+        b.vol_bytes_theta = a.vol_bytes_theta;
+        b.w_bytes = a.w_bytes;
+        b.K = a.K;
+        b.n = a.n;
+        b.n_chains = a.n_chains;
+        b.T = a.T;
+        b.mode = a.mode;
+        b.n_pass = a.n_pass;
+        b.sign = a.sign;
+        b.inv_n = a.inv_n;
+        for (int i = 0; i < 8; ++i) b.gamma[i] = a.gamma[i];
+        return b;
+    };
+
+    // 1. final row pass: dL/dminmarg and the row part of dL/dLB -> dL/dcost, dL/d(final dual)
+    {
+        SweepArgs a = rows;
+        a.mode = kModeFinal | kRecordFlag;
+        a.lam_in = dual;
+        a.lam = const_cast<float*>(dual);  // never written in record mode
+        DM_HIP_TRY(launch_sweep(tile, a, cost_dtype, stream), "final recompute");
+        AdjArgs b = adj_from(rows, gwh);
+        b.mode = kModeFinal;
+        b.lam0 = dual;
+        b.grad_mm = grad_minmarg;
+        b.g_lb = grad_lb;
+        DM_HIP_TRY(launch_adjoint(tile, b, cost_dtype, stream), "final adjoint");
+    }
+    // 2. column part of dL/dLB: one-hot at the column optima of G
+    if (grad_lb != 0.0) {
+        SweepArgs a = cols;
+        a.mode = kModeFinal;
+        a.lam = const_cast<float*>(dual);
+        a.lam_in = dual;
+        a.msg = vol_at(LB.msg, 0);
+        a.minmarg = nullptr;
+        a.labels = lab;
+        a.opt = nullptr;
+        DM_HIP_TRY(launch_sweep(tile_v, a, cost_dtype, stream), "column optimum labels");
+        hipLaunchKernelGGL(lb_col_adjoint_kernel, dim3(1024), dim3(256), 0, stream, lab, s.W, s.H, s.K, p->trunc_T,
+                           grad_lb, lbar, gwv);
+        DM_HIP_TRY(hipGetLastError(), "column bound adjoint");
+    }
+    // 3. half-steps in reverse: recompute from the checkpoint, then differentiate
+    for (int k = S - 1; k >= 0; --k) {
+        const float* ck = reinterpret_cast<const float*>(fws + LF.ckpt + (size_t)k * LF.vol_bytes);
+        const bool h = (k % 2) == 0;
+        SweepArgs a = h ? rows : cols;
+        a.mode = a.mode | kRecordFlag;
+        a.lam_in = ck;
+        a.lam = const_cast<float*>(ck);
+        DM_HIP_TRY(launch_sweep(h ? tile : tile_v, a, cost_dtype, stream), "half-step recompute");
+        AdjArgs b = adj_from(h ? rows : cols, h ? gwh : gwv);
+        b.lam0 = ck;
+        DM_HIP_TRY(launch_adjoint(h ? tile : tile_v, b, cost_dtype, stream), "half-step adjoint");
+    }
+    if (grad_w_h != nullptr && n_wh > 0)
+        hipLaunchKernelGGL(edge_out_kernel, dim3(512), dim3(256), 0, stream, gwh, n_wh, accumulate, grad_w_h);
+    if (grad_w_v != nullptr && n_wv > 0)
+        hipLaunchKernelGGL(edge_out_kernel, dim3(512), dim3(256), 0, stream, gwv, n_wv, accumulate, grad_w_v);
+    DM_HIP_TRY(hipGetLastError(), "edge grads");
+    return DM_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+namespace dm {
+int validate_discrete(const dm_shape& s, const dm_discrete_params* p) { return validate_params(s, p); }
+
+namespace {
+
+__global__ void hash_fill_kernel(float* __restrict__ f32, _Float16* __restrict__ f16, long long n, unsigned seed) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        unsigned x = (unsigned)i * 2654435761u ^ seed;
+        x ^= x >> 15;
+        x *= 2246822519u;
+        x ^= x >> 13;
+        const float v = (float)(x & 0xFFFFFF) * (1.0f / 16777216.0f);
+        if (f32) f32[i] = v;
+        if (f16) f16[i] = (_Float16)v;
+    }
+}
+
+struct TuneKey {
+    int W, H, K, dt, minorant, max_pass;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(W, H, K, dt, minorant, max_pass) < std::tie(o.W, o.H, o.K, o.dt, o.minorant, o.max_pass);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<Tile, Tile>> g_tune_cache;
+
+}  // namespace
+}  // namespace dm
+
+// Picks, for the row and the column family separately, the compiled (lanes, labels per
+// lane) tile with the shortest measured half-step on a synthetic instance of the same
+// shape, and writes the choice into p (tile_lanes/labels_per_lane for rows, the _v fields
+// for columns).  Allocates (and frees) scratch device memory; results are cached per
+// (W, H, K, cost dtype, minorant, max_pass) for the process.
+extern "C" int dm_autotune_tiles(dm_shape s, dm_dtype cost_dtype, dm_discrete_params* p, void* hip_stream) {
+    clear_error();
+    DM_REQUIRE(p != nullptr, DM_ERR_NULL, "params is NULL");
+    int st = validate_params(s, p);
+    if (st != DM_OK) return st;
+    DM_REQUIRE(cost_dtype == DM_F32 || cost_dtype == DM_F16, DM_ERR_DTYPE, "unknown cost dtype");
+    const TuneKey key{s.W, s.H, s.K, (int)cost_dtype, p->minorant, p->max_pass};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            p->tile_lanes = it->second.first.G;
+            p->labels_per_lane = it->second.first.LPL;
+            p->tile_lanes_v = it->second.second.G;
+            p->labels_per_lane_v = it->second.second.LPL;
+            return DM_OK;
+        }
+    }
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const long long vol = (long long)s.W * s.H * s.K;
+    DM_REQUIRE(vol * 4 < (long long)kOOB, DM_ERR_UNSUPPORTED, "volume exceeds the 4 GiB buffer range");
+    void *theta = nullptr, *lam = nullptr, *msg = nullptr, *wh = nullptr, *wv = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (theta) (void)hipFree(theta);
+        if (lam) (void)hipFree(lam);
+        if (msg) (void)hipFree(msg);
+        if (wh) (void)hipFree(wh);
+        if (wv) (void)hipFree(wv);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    const size_t tb = (size_t)vol * (cost_dtype == DM_F16 ? 2 : 4);
+    const long long n_wh = (long long)s.H * (s.W - 1), n_wv = (long long)(s.H - 1) * s.W;
+    if (hipMalloc(&theta, tb) != hipSuccess || hipMalloc(&lam, vol * 4) != hipSuccess ||
+        hipMalloc(&msg, vol * 4) != hipSuccess || hipMalloc(&wh, (n_wh > 0 ? n_wh : 1) * 4) != hipSuccess ||
+        hipMalloc(&wv, (n_wv > 0 ? n_wv : 1) * 4) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        set_error("autotune: device allocation failed");
+        return DM_ERR_HIP;
+    }
+    hipLaunchKernelGGL(hash_fill_kernel, dim3(2048), dim3(256), 0, stream,
+                       cost_dtype == DM_F32 ? static_cast<float*>(theta) : nullptr,
+                       cost_dtype == DM_F16 ? static_cast<_Float16*>(theta) : nullptr, vol, 12345u);
+    hipLaunchKernelGGL(fill_f32_kernel, dim3(2048), dim3(256), 0, stream, static_cast<float*>(lam), vol, 0.0f);
+    if (n_wh > 0) hipLaunchKernelGGL(fill_f32_kernel, dim3(256), dim3(256), 0, stream, static_cast<float*>(wh), n_wh, 0.1f);
+    if (n_wv > 0) hipLaunchKernelGGL(fill_f32_kernel, dim3(256), dim3(256), 0, stream, static_cast<float*>(wv), n_wv, 0.1f);
+
+    SweepArgs rows{};
+    rows.theta = theta;
+    rows.lam = static_cast<float*>(lam);
+    rows.msg = static_cast<float*>(msg);
+    rows.w = static_cast<float*>(wh);
+    rows.chain_px = s.W;
+    rows.node_px = 1;
+    rows.w_chain = s.W - 1;
+    rows.w_node = 1;
+    rows.vol_bytes_f32 = (unsigned)(vol * 4);
+    rows.vol_bytes_theta = (unsigned)tb;
+    rows.w_bytes = (unsigned)(n_wh * 4);
+    rows.K = s.K;
+    rows.n = s.W;
+    rows.n_chains = s.H;
+    rows.T = p->trunc_T;
+    rows.sign = 1.0f;
+    rows.inv_n = 1.0f / (float)s.W;
+    rows.n_pass = p->max_pass;
+    for (int i = 0; i < 8; ++i) rows.gamma[i] = p->gamma[i];
+    rows.mode = p->minorant == DM_MINORANT_NAIVE ? kModeNaive : kModeIterative;
+    SweepArgs cols = rows;
+    cols.theta = nullptr;
+    cols.w = static_cast<float*>(wv);
+    cols.w_bytes = (unsigned)(n_wv * 4);
+    cols.chain_px = 1;
+    cols.node_px = s.W;
+    cols.w_chain = 1;
+    cols.w_node = s.W;
+    cols.n = s.H;
+    cols.n_chains = s.W;
+    cols.sign = -1.0f;
+    cols.inv_n = 1.0f / (float)s.H;
+
+    Tile best[2] = {default_tile(s.K), default_tile(s.K)};
+    for (int fam = 0; fam < 2; ++fam) {
+        const SweepArgs& a = fam == 0 ? rows : cols;
+        float best_ms = 1e30f;
+        for (const Tile& t : kTiles) {
+            if (t.G * t.LPL < s.K) continue;
+            if (launch_sweep(t, a, cost_dtype, stream) != hipSuccess) continue;  // warm-up
+            float ms_min = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                (void)hipEventRecord(e0, stream);
+                (void)launch_sweep(t, a, cost_dtype, stream);
+                (void)hipEventRecord(e1, stream);
+                if (hipEventSynchronize(e1) != hipSuccess) break;
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                ms_min = ms < ms_min ? ms : ms_min;
+            }
+            if (ms_min < best_ms) {
+                best_ms = ms_min;
+                best[fam] = t;
+            }
+        }
+    }
+    const hipError_t err = hipStreamSynchronize(stream);
+    cleanup();
+    if (err != hipSuccess) {
+        set_error("autotune: %s", hipGetErrorString(err));
+        return DM_ERR_HIP;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = {best[0], best[1]};
+    }
+    p->tile_lanes = best[0].G;
+    p->labels_per_lane = best[0].LPL;
+    p->tile_lanes_v = best[1].G;
+    p->labels_per_lane_v = best[1].LPL;
     return DM_OK;
 }

@@ -49,10 +49,15 @@ enum SweepMode : int {
     kModeOptimum = 2,    // chain optimum only (backward message pass, no stores)
     kModeFinal = 3,      // normalized min-marginals + argmin labels + optimum
 };
+// Launch flag (added to mode): recompute a half-step keeping every pass's messages and
+// intermediate duals (the adjoint's input).
+constexpr int kRecordFlag = 16;
 
 struct SweepArgs {
     const void* theta;   // [H][W][K] cost (horizontal family) or nullptr (vertical family)
-    float* lam;          // [H][W][K] dual variables
+    float* lam;          // [H][W][K] dual variables (written; read after the first update pass)
+    const float* lam_in; // dual variables read by the message pass and the first update pass
+                         // (== lam for an in-place half-step; a checkpoint otherwise)
     float* msg;          // [H][W][K] message buffer
     const float* w;      // edge weights of this family
     float* minmarg;      // kModeFinal: [H][W][K] (may be null)
@@ -69,6 +74,8 @@ struct SweepArgs {
     float sign;          // +1: lambda += delta (horizontal), -1: lambda -= delta (vertical)
     float inv_n;         // 1/n for the naive minorant
     float gamma[8];
+    float* rec_lam[8];   // record mode: dual after update pass s (s = 1 .. n_pass-1)
+    float* rec_msg[9];   // record mode: messages written by pass s (s = 0: backward message pass)
 };
 
 // Offset that is outside every buffer: loads return 0, stores are dropped.
@@ -170,7 +177,10 @@ struct Walker {
         float w;
     };
 
-    __amdgpu_buffer_rsrc_t r_theta, r_lam, r_msg, r_w, r_mm;
+    __amdgpu_buffer_rsrc_t r_theta, r_w, r_mm;
+    // buffers of the current pass: dual loads / stores, reverse-message loads, message stores
+    __amdgpu_buffer_rsrc_t r_lam_ld, r_lam_st, r_msg_ld, r_msg_st;
+    unsigned vol_bytes;
     int* __restrict__ labels;
     long long base_px, wbase, node_px, w_node;
     int sub, n, K, T;
@@ -186,8 +196,11 @@ struct Walker {
         base_px = (long long)(ok ? chain : 0) * args.chain_px;
         wbase = (long long)(ok ? chain : 0) * args.w_chain;
         r_theta = make_rsrc(args.theta, HAS_THETA ? args.vol_bytes_theta : 0u);
-        r_lam = make_rsrc(args.lam, args.vol_bytes_f32);
-        r_msg = make_rsrc(args.msg, args.vol_bytes_f32);
+        vol_bytes = args.vol_bytes_f32;
+        r_lam_ld = make_rsrc(args.lam_in != nullptr ? args.lam_in : args.lam, vol_bytes);
+        r_lam_st = make_rsrc(args.lam, vol_bytes);
+        r_msg_ld = make_rsrc(args.msg, vol_bytes);
+        r_msg_st = r_msg_ld;
         r_w = make_rsrc(args.w, args.w_bytes);
         r_mm = make_rsrc(args.minmarg, args.minmarg != nullptr ? args.vol_bytes_f32 : 0u);
 #pragma unroll
@@ -218,11 +231,11 @@ struct Walker {
             nd.th.load(r_theta, o0, os);
         }
         offsets<4>(j, true, o0, os);
-        nd.lam.load(r_lam, o0, os);
+        nd.lam.load(r_lam_ld, o0, os);
         const bool has = FWD ? (j < n - 1) : (j > 0);
         if constexpr (WANT_REV) {
             offsets<4>(FWD ? j : j - 1, has, o0, os);
-            nd.rev.load(r_msg, o0, os);
+            nd.rev.load(r_msg_ld, o0, os);
         }
         const long long ei = wbase + (long long)(FWD ? j : j - 1) * w_node;
         const unsigned wo = (has && ok) ? (unsigned)(ei * 4) : kOOB;
@@ -330,7 +343,7 @@ struct Walker {
                 }
                 unsigned o0, os[LPL];
                 offsets<4>(j, true, o0, os);
-                store_f32<LPL, FULL>(r_lam, o0, os, nl);
+                store_f32<LPL, FULL>(r_lam_st, o0, os, nl);
             } else {  // KIND == 3: normalized min-marginals and argmin
                 float mm[LPL];
                 int first = 0x7fffffff;
@@ -358,7 +371,7 @@ struct Walker {
                 if (store_msg) {
                     unsigned o0, os[LPL];
                     offsets<4>(FWD ? j : j - 1, true, o0, os);
-                    store_f32<LPL, FULL>(r_msg, o0, os, carry);
+                    store_f32<LPL, FULL>(r_msg_st, o0, os, carry);
                 }
             }
         }
@@ -368,21 +381,23 @@ struct Walker {
 // Mode groups compiled as separate kernels (separate symbols in profiles, and each
 // kernel holds only the passes it runs): half-step (iterative or naive minorant),
 // final row pass, column optimum pass.
-enum ModeGroup : int { kGroupHalfStep = 0, kGroupFinal = 1, kGroupOptimum = 2 };
+enum ModeGroup : int { kGroupHalfStep = 0, kGroupFinal = 1, kGroupOptimum = 2, kGroupRecord = 3 };
 
+// All passes of one mode group for the chain owned by this lane group.
 template <int G, int LPL, int PF, typename TT, bool FULL, bool HAS_THETA, int MG>
-__global__ __launch_bounds__(64) void chain_kernel(SweepArgs a) {
-    constexpr int CPW = 64 / G;
-    const int lane = threadIdx.x;
-    const int sub = lane % G;
-    const int chain = blockIdx.x * CPW + lane / G;
+__device__ __forceinline__ void run_chain(const SweepArgs& a, int chain, int sub) {
     Walker<G, LPL, PF, TT, FULL, HAS_THETA> wk(a, chain, sub);
     double opt = 0.0;
     if constexpr (MG == kGroupHalfStep) {
+        // R0 and the first update pass read lam_in; update passes write lam
+        const __amdgpu_buffer_rsrc_t lam_out = wk.r_lam_st;
+        wk.r_lam_st = make_rsrc(nullptr, 0u);
+        wk.template pass<false, 0>(0.0f, true, opt);
+        wk.r_lam_st = lam_out;
         if (a.mode == kModeIterative) {
-            wk.template pass<false, 0>(0.0f, true, opt);
             for (int s = 0; s < a.n_pass; ++s) {
                 const bool last = s == a.n_pass - 1;
+                if (s == 1) wk.r_lam_ld = lam_out;
                 // select instead of a dynamic index: keeps the argument block out of scratch
                 float g = a.gamma[0];
 #pragma unroll
@@ -394,16 +409,59 @@ __global__ __launch_bounds__(64) void chain_kernel(SweepArgs a) {
                     wk.template pass<false, 1>(g, !last, opt);
             }
         } else {
-            wk.template pass<false, 0>(0.0f, true, opt);
             wk.template pass<true, 2>(0.0f, false, opt);
         }
     } else if constexpr (MG == kGroupFinal) {
         wk.template pass<false, 0>(0.0f, true, opt);
         wk.template pass<true, 3>(0.0f, false, opt);
-    } else {
+    } else if constexpr (MG == kGroupOptimum) {
         wk.template pass<false, 0>(0.0f, false, opt);
+    } else {  // kGroupRecord: recompute a half-step keeping every pass's messages and duals
+        const unsigned vb = wk.vol_bytes;
+        wk.r_lam_st = make_rsrc(nullptr, 0u);
+        wk.r_msg_st = make_rsrc(a.rec_msg[0], vb);
+        wk.template pass<false, 0>(0.0f, true, opt);
+        const int P = a.mode == kModeIterative ? a.n_pass : 1;
+        for (int s = 0; s < P; ++s) {
+            const float* ld = a.lam_in;
+            float* st = nullptr;
+            float* mld = a.rec_msg[0];
+            float* mst = a.rec_msg[1];
+#pragma unroll
+            for (int i = 1; i < 8; ++i) {
+                if (s == i) {
+                    ld = a.rec_lam[i];
+                    mld = a.rec_msg[i];
+                    mst = a.rec_msg[i + 1];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (s == i && s + 1 < P) st = a.rec_lam[i + 1];
+            wk.r_lam_ld = make_rsrc(ld, vb);
+            wk.r_lam_st = make_rsrc(st, st != nullptr ? vb : 0u);
+            wk.r_msg_ld = make_rsrc(mld, vb);
+            wk.r_msg_st = make_rsrc(mst, vb);
+            float g = a.gamma[0];
+#pragma unroll
+            for (int i = 1; i < 8; ++i)
+                if (s == i) g = a.gamma[i];
+            if (a.mode != kModeIterative)
+                wk.template pass<true, 2>(0.0f, true, opt);
+            else if ((s & 1) == 0)
+                wk.template pass<true, 1>(g, true, opt);
+            else
+                wk.template pass<false, 1>(g, true, opt);
+        }
     }
     if (a.opt != nullptr && wk.ok && sub == 0) a.opt[chain] = opt;
+}
+
+template <int G, int LPL, int PF, typename TT, bool FULL, bool HAS_THETA, int MG>
+__global__ __launch_bounds__(64) void chain_kernel(SweepArgs a) {
+    constexpr int CPW = 64 / G;
+    const int lane = threadIdx.x;
+    run_chain<G, LPL, PF, TT, FULL, HAS_THETA, MG>(a, blockIdx.x * CPW + lane / G, lane % G);
 }
 
 // ------------------------------------------------------------------ launch
@@ -422,10 +480,12 @@ hipError_t launch_mg(const SweepArgs& a, hipStream_t st) {
 
 template <int G, int LPL, typename TT, bool HAS_THETA>
 hipError_t launch_tt(const SweepArgs& a, hipStream_t st) {
-    if (a.mode == kModeFinal) {
-        if constexpr (HAS_THETA) return launch_mg<G, LPL, TT, true, kGroupFinal>(a, st);
-        return hipErrorInvalidValue;
+    if (a.mode & kRecordFlag) {
+        SweepArgs b = a;
+        b.mode = a.mode & ~kRecordFlag;
+        return launch_mg<G, LPL, TT, HAS_THETA, kGroupRecord>(b, st);
     }
+    if (a.mode == kModeFinal) return launch_mg<G, LPL, TT, HAS_THETA, kGroupFinal>(a, st);
     if (a.mode == kModeOptimum) {
         if constexpr (!HAS_THETA) return launch_mg<G, LPL, TT, false, kGroupOptimum>(a, st);
         return hipErrorInvalidValue;

@@ -25,9 +25,35 @@ struct RefineScalars {
 
 struct RefineLayout {
     size_t u0, sL, sR, state0, state1, total, plane;
+    size_t tape_u0, tape_mask, mask_plane;  // keep_tape: u0 per warp, branch masks per iteration
 };
 
-RefineLayout refine_layout(const dm_shape& s);
+RefineLayout refine_layout(const dm_shape& s, const dm_refine_params* p);
+
+// Batched refinement: per-instance state, and the work tables of the launches.
+struct RefBatchInst {
+    const void* theta;
+    const int* labels;
+    const float* w_h;
+    const float* w_v;
+    float* u_out;
+    RefineState S[2];
+    rfloat* u0;
+    rfloat* sL;
+    rfloat* sR;
+    int W, H, K;
+};
+struct RefChunk {      // pixels [start, start + count) of one instance
+    int inst;
+    long long start;
+    int count;
+};
+struct RefTile {       // one 64 x 4 tile of one instance
+    int inst, bx, by;
+};
+void refine_tile_extent(int W, int H, int& nbx, int& nby);
+hipError_t launch_batched_refine(const RefBatchInst* insts, const RefChunk* chunks, int n_chunks, const RefTile* tiles,
+                                 int n_tiles, dm_dtype dt, const dm_refine_params& p, hipStream_t st);
 RefineState state_at(char* base, size_t plane);
 int validate_refine(const dm_shape& s, const dm_refine_params* p);
 RefineScalars refine_scalars(const dm_refine_params& p);

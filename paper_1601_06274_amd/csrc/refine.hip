@@ -1,4 +1,5 @@
-// refine.hip - continuous refinement by the non-linear primal-dual method on gfx950.
+// refine.hip - continuous refinement by the non-linear primal-dual method on gfx950,
+// and its adjoint.
 //
 // Paper: Sec. 2.4 (Valkonen's iteration, eq. cont_iterates; difference-of-convex split
 // eq. r-decompose; conjugate prox eq. pprox; the operator gradient) and Sec. 3.1 (two-slope
@@ -19,11 +20,20 @@
 //                      u+ on the tile plus a one-pixel halo to the right and below (the
 //                      halo values are recomputed, not exchanged), keeps u and u+ in LDS,
 //                      then updates q and p of the tile's edges.  State is double
-//                      buffered (every read sees the previous iterate).
+//                      buffered (every read sees the previous iterate).  Optionally records
+//                      the branch taken by every prox (16-bit mask per pixel) for the adjoint.
 // State and arithmetic are FP64 (rfloat); the cost volume and edge weights are read in
 // their storage types and widened.  The working set (about 11 doubles per pixel) stays
 // in L2 / MALL at these sizes, so the iteration is bound by on-chip bandwidth and
 // launch latency, not HBM.
+//
+// Adjoint (reverse mode).  Every map of the iteration is piecewise linear; given the
+// recorded branches, the adjoint of one iteration is a linear stencil with the same
+// tile / halo structure (pdhg_adjoint_kernel).  At the start of each warp (processed in
+// reverse) the accumulated adjoints of the slopes and of u0 are pushed through the
+// linearisation into the cost volume and into u (linearize_adjoint_kernel).  At kinks
+// (exact ties of a branch test) the derivative of the branch that the forward took is
+// used; on the interpolated data term at integer arguments the segment [k, k+1].
 #include "common.h"
 #include "refine.h"
 
@@ -34,14 +44,43 @@ __device__ __forceinline__ rfloat cost_at(const TT* __restrict__ th, long long p
     return (rfloat)(float)th[p * K + k];
 }
 
+// Linear interpolation of the cost along the label axis; also the segment used.
 template <typename TT>
-__device__ __forceinline__ rfloat interp(const TT* __restrict__ th, long long p, int K, rfloat v) {
+__device__ __forceinline__ rfloat interp(const TT* __restrict__ th, long long p, int K, rfloat v, int* k0_out = nullptr,
+                                         rfloat* t_out = nullptr) {
     v = fmin(fmax(v, 0.0), (rfloat)(K - 1));
     int k0 = (int)floor(v);
     k0 = k0 < K - 1 ? k0 : K - 1;
     const int k1 = k0 + 1 < K - 1 ? k0 + 1 : K - 1;
     const rfloat t = v - (rfloat)k0;
+    if (k0_out) *k0_out = k0;
+    if (t_out) *t_out = t;
     return (1.0 - t) * cost_at(th, p, K, k0) + t * cost_at(th, p, K, k1);
+}
+
+template <typename TT>
+__device__ __forceinline__ void linearize_px(const TT* __restrict__ th, const rfloat* __restrict__ u, long long p,
+                                             int K, rfloat h, rfloat* __restrict__ u0, rfloat* __restrict__ sL,
+                                             rfloat* __restrict__ sR) {
+    const rfloat c = u[p];
+    const rfloat Dc = interp(th, p, K, c);
+    const rfloat Dm = interp(th, p, K, c - h);
+    const rfloat Dp = interp(th, p, K, c + h);
+    rfloat l = (Dc - Dm) / h;
+    rfloat r = (Dp - Dc) / h;
+    const bool has_l = c - h >= 0.0;
+    const bool has_r = c + h <= (rfloat)(K - 1);
+    const rfloat l0 = l;
+    l = has_l ? l : (has_r ? r : 0.0);
+    r = has_r ? r : (has_l ? l0 : 0.0);
+    if (l > r) {
+        const rfloat m = 0.5 * (l + r);
+        l = m;
+        r = m;
+    }
+    u0[p] = c;
+    sL[p] = l;
+    sR[p] = r;
 }
 
 template <typename TT>
@@ -49,63 +88,90 @@ __global__ __launch_bounds__(256) void linearize_kernel(const TT* __restrict__ t
                                                         int H, int K, rfloat h, rfloat* __restrict__ u0,
                                                         rfloat* __restrict__ sL, rfloat* __restrict__ sR) {
     const long long n = (long long)W * H;
-    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
-        const rfloat c = u[p];
-        const rfloat Dc = interp(th, p, K, c);
-        const rfloat Dm = interp(th, p, K, c - h);
-        const rfloat Dp = interp(th, p, K, c + h);
-        rfloat l = (Dc - Dm) / h;
-        rfloat r = (Dp - Dc) / h;
-        const bool has_l = c - h >= 0.0;
-        const bool has_r = c + h <= (rfloat)(K - 1);
-        const rfloat l0 = l;
-        l = has_l ? l : (has_r ? r : 0.0);
-        r = has_r ? r : (has_l ? l0 : 0.0);
-        if (l > r) {
-            const rfloat m = 0.5 * (l + r);
-            l = m;
-            r = m;
-        }
-        u0[p] = c;
-        sL[p] = l;
-        sR[p] = r;
-    }
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x)
+        linearize_px(th, u, p, K, h, u0, sL, sR);
 }
 
-// prox of step * (w r_{alpha,beta})^* at t (eq. pprox), then the clamp to [-w, w].
-__device__ __forceinline__ rfloat prox_conj(rfloat t, rfloat w, rfloat alpha, rfloat beta, rfloat step) {
+// Branch codes of the conjugate prox (3 bits): 0 = identity slope in t, 1 / 2 = flat at
+// +alpha*w / -alpha*w, 3 / 4 = clamped at +w / -w.
+__device__ __forceinline__ rfloat prox_conj(rfloat t, rfloat w, rfloat alpha, rfloat beta, rfloat step, int& code) {
     const rfloat a = fabs(t);
     const rfloat aw = alpha * w;
-    rfloat r = (a <= aw) ? t : copysign(fmax(aw, a - beta * step), t);
-    return fmin(fmax(r, -w), w);
+    rfloat r;
+    code = 0;
+    if (a <= aw) {
+        r = t;
+    } else {
+        const rfloat sh = a - beta * step;
+        if (sh < aw) {
+            r = copysign(aw, t);
+            code = t > 0.0 ? 1 : 2;
+        } else {
+            r = copysign(sh, t);
+        }
+    }
+    if (r < -w) {
+        r = -w;
+        code = 4;
+    } else if (r > w) {
+        r = w;
+        code = 3;
+    }
+    return r;
 }
 
 // prox of tau * D~ (two-slope soft threshold) and the box [u0 - h, u0 + h] n [0, K-1].
-__device__ __forceinline__ rfloat prox_data(rfloat uh, rfloat u0, rfloat l, rfloat r, rfloat tau, rfloat h,
-                                            rfloat kmax) {
-    rfloat v = (uh > u0 + tau * r) ? uh - tau * r : ((uh < u0 + tau * l) ? uh - tau * l : u0);
+// code: bits 0-1 zone (0 middle, 1 right slope, 2 left slope), bits 2-3 clamp (0, 1 low, 2 high).
+__device__ __forceinline__ rfloat prox_data(rfloat uh, rfloat u0, rfloat l, rfloat r, rfloat tau, rfloat h, rfloat kmax,
+                                            int& code) {
+    rfloat v;
+    int zone;
+    if (uh > u0 + tau * r) {
+        v = uh - tau * r;
+        zone = 1;
+    } else if (uh < u0 + tau * l) {
+        v = uh - tau * l;
+        zone = 2;
+    } else {
+        v = u0;
+        zone = 0;
+    }
     const rfloat lo = fmax(u0 - h, 0.0);
     const rfloat hi = fmin(u0 + h, kmax);
-    return fmin(fmax(v, lo), hi);
+    int cl = 0;
+    if (v < lo) {
+        v = lo;
+        cl = 1;
+    } else if (v > hi) {
+        v = hi;
+        cl = 2;
+    }
+    code = zone | (cl << 2);
+    return v;
 }
 
 constexpr int kTX = 64, kTY = 4;
 
+// Mask layout (uint16 per pixel and iteration): [0,4) u-prox, [4,7) qh, [7,10) qv,
+// [10,13) ph, [13,16) pv.
+__device__ __forceinline__ int mfield(uint32_t m, int shift, int bits) { return (int)((m >> shift) & ((1u << bits) - 1u)); }
+
 // Edge arrays are stored per pixel: ph/qh at (x, y) belong to the edge (x, y)-(x+1, y)
 // (unused in the last column), pv/qv to (x, y)-(x, y+1) (unused in the last row).
-__global__ __launch_bounds__(256) void pdhg_kernel(const RefineState in, RefineState out, const rfloat* __restrict__ u0,
-                                                   const rfloat* __restrict__ sL, const rfloat* __restrict__ sR,
-                                                   const float* __restrict__ w_h, const float* __restrict__ w_v, int W,
-                                                   int H, int K, RefineScalars sc) {
+__device__ __forceinline__ void pdhg_tile(const RefineState& in, const RefineState& out, const rfloat* __restrict__ u0,
+                                          const rfloat* __restrict__ sL, const rfloat* __restrict__ sR,
+                                          const float* __restrict__ w_h, const float* __restrict__ w_v, int W, int H,
+                                          int K, const RefineScalars& sc, uint16_t* __restrict__ mask, int x0, int y0) {
     __shared__ rfloat s_uo[kTY + 1][kTX + 1];
     __shared__ rfloat s_un[kTY + 1][kTX + 1];
-    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY;
+    __shared__ int s_code[kTY][kTX];
     const rfloat kmax = (rfloat)(K - 1);
     // Phase A: u+ on the tile and its right / lower halo.
     for (int idx = threadIdx.x; idx < (kTX + 1) * (kTY + 1); idx += blockDim.x) {
         const int i = idx % (kTX + 1), j = idx / (kTX + 1);
         const int x = x0 + i, y = y0 + j;
         rfloat uo = 0.0, un = 0.0;
+        int code = 0;
         if (x < W && y < H) {
             const long long p = (long long)y * W + x;
             // (A^T z)_i = z_h(i) + z_v(i) - z_h(left) - z_v(up), z = p - q
@@ -115,10 +181,11 @@ __global__ __launch_bounds__(256) void pdhg_kernel(const RefineState in, RefineS
             if (x > 0) at -= in.ph[p - 1] - in.qh[p - 1];
             if (y > 0) at -= in.pv[p - W] - in.qv[p - W];
             uo = in.u[p];
-            un = prox_data(uo - sc.tau * at, u0[p], sL[p], sR[p], sc.tau, sc.h, kmax);
+            un = prox_data(uo - sc.tau * at, u0[p], sL[p], sR[p], sc.tau, sc.h, kmax, code);
         }
         s_uo[j][i] = uo;
         s_un[j][i] = un;
+        if (i < kTX && j < kTY) s_code[j][i] = code;
     }
     __syncthreads();
     // Phase B: q+ (old u) and p+ (extrapolated 2u+ - u) on the tile's edges.
@@ -128,19 +195,254 @@ __global__ __launch_bounds__(256) void pdhg_kernel(const RefineState in, RefineS
     const long long p = (long long)y * W + x;
     const rfloat uo = s_uo[j][i], un = s_un[j][i];
     out.u[p] = un;
+    uint32_t m = (uint32_t)s_code[j][i];
+    int c;
     if (x + 1 < W) {
         const rfloat w = (rfloat)w_h[(long long)y * (W - 1) + x];
         const rfloat gq = uo - s_uo[j][i + 1];
-        out.qh[p] = prox_conj(in.qh[p] + sc.tau * gq, w, 0.0, sc.beta_minus, sc.tau);
+        out.qh[p] = prox_conj(in.qh[p] + sc.tau * gq, w, 0.0, sc.beta_minus, sc.tau, c);
+        m |= (uint32_t)c << 4;
         const rfloat gp = (2.0 * un - uo) - (2.0 * s_un[j][i + 1] - s_uo[j][i + 1]);
-        out.ph[p] = prox_conj(in.ph[p] + sc.sigma * gp, w, sc.eps, sc.delta, sc.sigma);
+        out.ph[p] = prox_conj(in.ph[p] + sc.sigma * gp, w, sc.eps, sc.delta, sc.sigma, c);
+        m |= (uint32_t)c << 10;
     }
     if (y + 1 < H) {
         const rfloat w = (rfloat)w_v[p];
         const rfloat gq = uo - s_uo[j + 1][i];
-        out.qv[p] = prox_conj(in.qv[p] + sc.tau * gq, w, 0.0, sc.beta_minus, sc.tau);
+        out.qv[p] = prox_conj(in.qv[p] + sc.tau * gq, w, 0.0, sc.beta_minus, sc.tau, c);
+        m |= (uint32_t)c << 7;
         const rfloat gp = (2.0 * un - uo) - (2.0 * s_un[j + 1][i] - s_uo[j + 1][i]);
-        out.pv[p] = prox_conj(in.pv[p] + sc.sigma * gp, w, sc.eps, sc.delta, sc.sigma);
+        out.pv[p] = prox_conj(in.pv[p] + sc.sigma * gp, w, sc.eps, sc.delta, sc.sigma, c);
+        m |= (uint32_t)c << 13;
+    }
+    if (mask != nullptr) mask[p] = (uint16_t)m;
+}
+
+__global__ __launch_bounds__(256) void pdhg_kernel(const RefineState in, RefineState out, const rfloat* __restrict__ u0,
+                                                   const rfloat* __restrict__ sL, const rfloat* __restrict__ sR,
+                                                   const float* __restrict__ w_h, const float* __restrict__ w_v, int W,
+                                                   int H, int K, RefineScalars sc, uint16_t* __restrict__ mask) {
+    pdhg_tile(in, out, u0, sL, sR, w_h, w_v, W, H, K, sc, mask, blockIdx.x * kTX, blockIdx.y * kTY);
+}
+
+// ------------------------------------------------------------------ batched forms
+// Many instances of (possibly) different sizes: block b of a launch works on the
+// pixel chunk or tile listed at index b of a table built by the plan.
+__global__ __launch_bounds__(256) void batched_refine_init_kernel(const RefBatchInst* __restrict__ insts,
+                                                                  const RefChunk* __restrict__ chunks, int cur) {
+    const RefChunk c = chunks[blockIdx.x];
+    const RefBatchInst& in = insts[c.inst];
+    const RefineState s = in.S[cur];
+    for (long long p = c.start + threadIdx.x; p < c.start + c.count; p += blockDim.x) {
+        int l = in.labels[p];
+        l = l < 0 ? 0 : (l > in.K - 1 ? in.K - 1 : l);
+        s.u[p] = (rfloat)l;
+        s.ph[p] = 0.0;
+        s.pv[p] = 0.0;
+        s.qh[p] = 0.0;
+        s.qv[p] = 0.0;
+    }
+}
+
+template <typename TT>
+__global__ __launch_bounds__(256) void batched_linearize_kernel(const RefBatchInst* __restrict__ insts,
+                                                                const RefChunk* __restrict__ chunks, int cur,
+                                                                rfloat h) {
+    const RefChunk c = chunks[blockIdx.x];
+    const RefBatchInst& in = insts[c.inst];
+    for (long long p = c.start + threadIdx.x; p < c.start + c.count; p += blockDim.x)
+        linearize_px(static_cast<const TT*>(in.theta), in.S[cur].u, p, in.K, h, in.u0, in.sL, in.sR);
+}
+
+__global__ __launch_bounds__(256) void batched_pdhg_kernel(const RefBatchInst* __restrict__ insts,
+                                                           const RefTile* __restrict__ tiles, int cur,
+                                                           RefineScalars sc) {
+    const RefTile t = tiles[blockIdx.x];
+    const RefBatchInst& in = insts[t.inst];
+    pdhg_tile(in.S[cur], in.S[cur ^ 1], in.u0, in.sL, in.sR, in.w_h, in.w_v, in.W, in.H, in.K, sc, nullptr,
+              t.bx * kTX, t.by * kTY);
+}
+
+__global__ __launch_bounds__(256) void batched_narrow_kernel(const RefBatchInst* __restrict__ insts,
+                                                             const RefChunk* __restrict__ chunks, int cur) {
+    const RefChunk c = chunks[blockIdx.x];
+    const RefBatchInst& in = insts[c.inst];
+    for (long long p = c.start + threadIdx.x; p < c.start + c.count; p += blockDim.x) in.u_out[p] = (float)in.S[cur].u[p];
+}
+
+void refine_tile_extent(int W, int H, int& nbx, int& nby) {
+    nbx = (W + kTX - 1) / kTX;
+    nby = (H + kTY - 1) / kTY;
+}
+
+hipError_t launch_batched_refine(const RefBatchInst* insts, const RefChunk* chunks, int n_chunks, const RefTile* tiles,
+                                 int n_tiles, dm_dtype dt, const dm_refine_params& p, hipStream_t st) {
+    const RefineScalars sc = refine_scalars(p);
+    hipLaunchKernelGGL(batched_refine_init_kernel, dim3(n_chunks), dim3(256), 0, st, insts, chunks, 0);
+    int cur = 0;
+    for (int wp = 0; wp < p.n_warps; ++wp) {
+        if (dt == DM_F16)
+            hipLaunchKernelGGL(batched_linearize_kernel<_Float16>, dim3(n_chunks), dim3(256), 0, st, insts, chunks, cur,
+                               (rfloat)p.h);
+        else
+            hipLaunchKernelGGL(batched_linearize_kernel<float>, dim3(n_chunks), dim3(256), 0, st, insts, chunks, cur,
+                               (rfloat)p.h);
+        for (int it = 0; it < p.n_iters; ++it) {
+            hipLaunchKernelGGL(batched_pdhg_kernel, dim3(n_tiles), dim3(256), 0, st, insts, tiles, cur, sc);
+            cur ^= 1;
+        }
+    }
+    hipLaunchKernelGGL(batched_narrow_kernel, dim3(n_chunks), dim3(256), 0, st, insts, chunks, cur);
+    return hipGetLastError();
+}
+
+// d(prox)/dt for a conjugate-prox branch code, and d(prox)/dw.
+__device__ __forceinline__ rfloat conj_dt(int code) { return code == 0 ? 1.0 : 0.0; }
+__device__ __forceinline__ rfloat conj_dw(int code, rfloat alpha) {
+    switch (code) {
+        case 1: return alpha;
+        case 2: return -alpha;
+        case 3: return 1.0;
+        case 4: return -1.0;
+        default: return 0.0;
+    }
+}
+
+// Adjoint of one iteration.  nxt: adjoints of the iteration's outputs (u+, p+, q+);
+// prv: adjoints of its inputs (u, p, q).  Accumulates the adjoints of u0, s_L, s_R
+// (per pixel) and of the edge weights (per edge).
+__global__ __launch_bounds__(256) void pdhg_adjoint_kernel(const RefineState nxt, RefineState prv,
+                                                           const uint16_t* __restrict__ mask,
+                                                           const rfloat* __restrict__ u0, int W, int H, int K,
+                                                           RefineScalars sc, rfloat* __restrict__ acc_u0,
+                                                           rfloat* __restrict__ acc_sL, rfloat* __restrict__ acc_sR,
+                                                           rfloat* __restrict__ acc_wh, rfloat* __restrict__ acc_wv) {
+    __shared__ rfloat s_uhb[kTY + 1][kTX + 1];
+    __shared__ rfloat s_ubt[kTY][kTX];
+    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY;
+    const rfloat kmax = (rfloat)(K - 1);
+    // Phase A: adjoint of uh (before the u-prox) on the tile and its right / lower halo.
+    for (int idx = threadIdx.x; idx < (kTX + 1) * (kTY + 1); idx += blockDim.x) {
+        const int i = idx % (kTX + 1), j = idx / (kTX + 1);
+        const int x = x0 + i, y = y0 + j;
+        rfloat uhb = 0.0;
+        if (x < W && y < H) {
+            const long long p = (long long)y * W + x;
+            const uint32_t m = mask[p];
+            rfloat atp = 0.0;  // (A^T pbar_hat)_i
+            if (x + 1 < W) atp += nxt.ph[p] * conj_dt(mfield(m, 10, 3));
+            if (y + 1 < H) atp += nxt.pv[p] * conj_dt(mfield(m, 13, 3));
+            if (x > 0) atp -= nxt.ph[p - 1] * conj_dt(mfield(mask[p - 1], 10, 3));
+            if (y > 0) atp -= nxt.pv[p - W] * conj_dt(mfield(mask[p - W], 13, 3));
+            const rfloat ubt = nxt.u[p] + 2.0 * sc.sigma * atp;
+            const int zone = mfield(m, 0, 2), cl = mfield(m, 2, 2);
+            uhb = (cl == 0 && zone != 0) ? ubt : 0.0;
+            if (i < kTX && j < kTY) s_ubt[j][i] = ubt;
+        }
+        s_uhb[j][i] = uhb;
+    }
+    __syncthreads();
+    const int i = threadIdx.x % kTX, j = threadIdx.x / kTX;
+    const int x = x0 + i, y = y0 + j;
+    if (x >= W || y >= H) return;
+    const long long p = (long long)y * W + x;
+    const uint32_t m = mask[p];
+    const rfloat uhb = s_uhb[j][i];
+    const rfloat ubt = s_ubt[j][i];
+    rfloat atp = 0.0, atq = 0.0;
+    if (x + 1 < W) {
+        atp += nxt.ph[p] * conj_dt(mfield(m, 10, 3));
+        atq += nxt.qh[p] * conj_dt(mfield(m, 4, 3));
+    }
+    if (y + 1 < H) {
+        atp += nxt.pv[p] * conj_dt(mfield(m, 13, 3));
+        atq += nxt.qv[p] * conj_dt(mfield(m, 7, 3));
+    }
+    if (x > 0) {
+        const uint32_t ml = mask[p - 1];
+        atp -= nxt.ph[p - 1] * conj_dt(mfield(ml, 10, 3));
+        atq -= nxt.qh[p - 1] * conj_dt(mfield(ml, 4, 3));
+    }
+    if (y > 0) {
+        const uint32_t mu = mask[p - W];
+        atp -= nxt.pv[p - W] * conj_dt(mfield(mu, 13, 3));
+        atq -= nxt.qv[p - W] * conj_dt(mfield(mu, 7, 3));
+    }
+    prv.u[p] = uhb - sc.sigma * atp + sc.tau * atq;
+    if (x + 1 < W) {
+        const int cq = mfield(m, 4, 3), cp = mfield(m, 10, 3);
+        const rfloat du = uhb - s_uhb[j][i + 1];
+        prv.ph[p] = nxt.ph[p] * conj_dt(cp) - sc.tau * du;
+        prv.qh[p] = nxt.qh[p] * conj_dt(cq) + sc.tau * du;
+        acc_wh[p] += nxt.ph[p] * conj_dw(cp, sc.eps) + nxt.qh[p] * conj_dw(cq, 0.0);
+    }
+    if (y + 1 < H) {
+        const int cq = mfield(m, 7, 3), cp = mfield(m, 13, 3);
+        const rfloat du = uhb - s_uhb[j + 1][i];
+        prv.pv[p] = nxt.pv[p] * conj_dt(cp) - sc.tau * du;
+        prv.qv[p] = nxt.qv[p] * conj_dt(cq) + sc.tau * du;
+        acc_wv[p] += nxt.pv[p] * conj_dw(cp, sc.eps) + nxt.qv[p] * conj_dw(cq, 0.0);
+    }
+    // u-prox adjoint into u0 and the slopes
+    const int zone = mfield(m, 0, 2), cl = mfield(m, 2, 2);
+    const rfloat c0 = u0[p];
+    rfloat d_u0 = 0.0;
+    if (cl == 0) d_u0 = zone == 0 ? 1.0 : 0.0;
+    else if (cl == 1) d_u0 = (c0 - sc.h >= 0.0) ? 1.0 : 0.0;
+    else d_u0 = (c0 + sc.h <= kmax) ? 1.0 : 0.0;
+    acc_u0[p] += ubt * d_u0;
+    if (cl == 0 && zone == 1) acc_sR[p] -= sc.tau * ubt;
+    if (cl == 0 && zone == 2) acc_sL[p] -= sc.tau * ubt;
+}
+
+// Adjoint of the per-warp linearisation at u0: pushes the accumulated slope / u0
+// adjoints into the cost volume gradient and into the adjoint of u at the warp start
+// (only when that u is a variable, i.e. not the first warp).  Clears the accumulators.
+template <typename TT>
+__global__ __launch_bounds__(256) void linearize_adjoint_kernel(const TT* __restrict__ th, const rfloat* __restrict__ u0w,
+                                                                int W, int H, int K, rfloat h, rfloat* __restrict__ acc_u0,
+                                                                rfloat* __restrict__ acc_sL,
+                                                                rfloat* __restrict__ acc_sR, rfloat* __restrict__ ubar,
+                                                                int add_to_u, float* __restrict__ grad_cost) {
+    const long long n = (long long)W * H;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
+        const rfloat c = u0w[p];
+        const rfloat lb = acc_sL[p], rb = acc_sR[p];
+        rfloat u0b = acc_u0[p];
+        acc_u0[p] = 0.0;
+        acc_sL[p] = 0.0;
+        acc_sR[p] = 0.0;
+        const rfloat Dc = interp(th, p, K, c);
+        const rfloat Dm = interp(th, p, K, c - h);
+        const rfloat Dp = interp(th, p, K, c + h);
+        const rfloat l_raw = (Dc - Dm) / h, r_raw = (Dp - Dc) / h;
+        const bool has_l = c - h >= 0.0;
+        const bool has_r = c + h <= (rfloat)(K - 1);
+        const rfloat l1 = has_l ? l_raw : (has_r ? r_raw : 0.0);
+        const rfloat r1 = has_r ? r_raw : (has_l ? l_raw : 0.0);
+        rfloat l1b = lb, r1b = rb;
+        if (l1 > r1) {
+            l1b = 0.5 * (lb + rb);
+            r1b = l1b;
+        }
+        const rfloat lrb = (has_l ? l1b : 0.0) + ((!has_r && has_l) ? r1b : 0.0);
+        const rfloat rrb = (has_r ? r1b : 0.0) + ((!has_l && has_r) ? l1b : 0.0);
+        const rfloat Dcb = (lrb - rrb) / h, Dmb = -lrb / h, Dpb = rrb / h;
+        const rfloat vs[3] = {c, c - h, c + h};
+        const rfloat Db[3] = {Dcb, Dmb, Dpb};
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            if (Db[e] == 0.0) continue;
+            int k0;
+            rfloat t;
+            interp(th, p, K, vs[e], &k0, &t);
+            const int k1 = k0 + 1 < K - 1 ? k0 + 1 : K - 1;
+            grad_cost[p * K + k0] += (float)((1.0 - t) * Db[e]);
+            grad_cost[p * K + k1] += (float)(t * Db[e]);
+            const bool inside = vs[e] >= 0.0 && vs[e] <= (rfloat)(K - 1);
+            if (inside) u0b += Db[e] * (cost_at(th, p, K, k1) - cost_at(th, p, K, k0));
+        }
+        if (add_to_u) ubar[p] += u0b;
     }
 }
 
@@ -157,16 +459,54 @@ __global__ __launch_bounds__(256) void refine_init_kernel(const int* __restrict_
     }
 }
 
+__global__ __launch_bounds__(256) void adjoint_init_kernel(const float* __restrict__ grad_u, long long n, RefineState s,
+                                                           rfloat* __restrict__ a0, rfloat* __restrict__ a1,
+                                                           rfloat* __restrict__ a2, rfloat* __restrict__ a3,
+                                                           rfloat* __restrict__ a4) {
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
+        s.u[p] = (rfloat)grad_u[p];
+        s.ph[p] = 0.0;
+        s.pv[p] = 0.0;
+        s.qh[p] = 0.0;
+        s.qv[p] = 0.0;
+        a0[p] = 0.0;
+        a1[p] = 0.0;
+        a2[p] = 0.0;
+        a3[p] = 0.0;
+        a4[p] = 0.0;
+    }
+}
+
 __global__ __launch_bounds__(256) void narrow_kernel(const rfloat* __restrict__ a, float* __restrict__ b, long long n) {
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x)
         b[p] = (float)a[p];
 }
 
+// Edge-weight gradients from the per-pixel FP64 accumulators (overwrite or add).
+__global__ __launch_bounds__(256) void edge_grad_kernel(const rfloat* __restrict__ acc_wh,
+                                                        const rfloat* __restrict__ acc_wv, int W, int H, int accumulate,
+                                                        float* __restrict__ gw_h, float* __restrict__ gw_v) {
+    const long long n = (long long)W * H;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(p % W), y = (int)(p / W);
+        if (gw_h != nullptr && x + 1 < W) {
+            const long long e = (long long)y * (W - 1) + x;
+            gw_h[e] = (accumulate ? gw_h[e] : 0.0f) + (float)acc_wh[p];
+        }
+        if (gw_v != nullptr && y + 1 < H) gw_v[p] = (accumulate ? gw_v[p] : 0.0f) + (float)acc_wv[p];
+    }
+}
+
+__global__ void fill_zero_f32_kernel(float* __restrict__ p, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
 // ------------------------------------------------------------------ host
-RefineLayout refine_layout(const dm_shape& s) {
+RefineLayout refine_layout(const dm_shape& s, const dm_refine_params* p) {
     RefineLayout L{};
-    const size_t px = (size_t)s.W * s.H * sizeof(rfloat);
-    const size_t a = align_up(px, 256);
+    const size_t px = (size_t)s.W * s.H;
+    const size_t a = align_up(px * sizeof(rfloat), 256);
     L.u0 = 0;
     L.sL = L.u0 + a;
     L.sR = L.sL + a;
@@ -174,6 +514,14 @@ RefineLayout refine_layout(const dm_shape& s) {
     L.state1 = L.state0 + 5 * a;     // 5 arrays
     L.total = L.state1 + 5 * a;
     L.plane = a;
+    L.tape_u0 = L.tape_mask = 0;
+    if (p != nullptr && p->keep_tape) {
+        L.tape_u0 = L.total;
+        L.total += (size_t)p->n_warps * a;
+        L.tape_mask = L.total;
+        L.mask_plane = align_up(px * sizeof(uint16_t), 256);
+        L.total += (size_t)p->n_warps * p->n_iters * L.mask_plane;
+    }
     return L;
 }
 
@@ -197,6 +545,7 @@ int validate_refine(const dm_shape& s, const dm_refine_params* p) {
     DM_REQUIRE(p->h > 0.0f, DM_ERR_PARAM, "h must be > 0");
     DM_REQUIRE(p->tau > 0.0f && p->sigma > 0.0f, DM_ERR_PARAM, "tau and sigma must be > 0");
     DM_REQUIRE(p->n_warps >= 0 && p->n_iters >= 0, DM_ERR_PARAM, "n_warps and n_iters must be >= 0");
+    DM_REQUIRE(p->keep_tape == 0 || p->keep_tape == 1, DM_ERR_PARAM, "keep_tape must be 0 or 1");
     return DM_OK;
 }
 
@@ -211,13 +560,37 @@ RefineScalars refine_scalars(const dm_refine_params& p) {
     return sc;
 }
 
+struct RefineBwdLayout {
+    size_t state0, state1, acc, total, plane;
+};
+
+RefineBwdLayout refine_bwd_layout(const dm_shape& s) {
+    RefineBwdLayout L{};
+    const size_t a = align_up((size_t)s.W * s.H * sizeof(rfloat), 256);
+    L.plane = a;
+    L.state0 = 0;
+    L.state1 = 5 * a;
+    L.acc = 10 * a;  // acc_u0, acc_sL, acc_sR, acc_wh, acc_wv
+    L.total = 15 * a;
+    return L;
+}
+
+int pending_hip(const char* where) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("pending HIP error before %s: %s", where, hipGetErrorString(e));
+        return DM_ERR_HIP;
+    }
+    return DM_OK;
+}
+
 }  // namespace dm
 
 using namespace dm;
 
 extern "C" size_t dm_refine_continuous_workspace(dm_shape s, const dm_refine_params* p) {
     if (validate_refine(s, p) != DM_OK) return 0;
-    return refine_layout(s).total;
+    return refine_layout(s, p).total;
 }
 
 extern "C" int dm_refine_continuous(const void* cost, dm_dtype cost_dtype, const int32_t* labels, const float* w_h,
@@ -231,19 +604,12 @@ extern "C" int dm_refine_continuous(const void* cost, dm_dtype cost_dtype, const
                "cost, labels and u_out are required");
     DM_REQUIRE(s.W == 1 || w_h != nullptr, DM_ERR_NULL, "w_h is required when W > 1");
     DM_REQUIRE(s.H == 1 || w_v != nullptr, DM_ERR_NULL, "w_v is required when H > 1");
-    const RefineLayout L = refine_layout(s);
+    const RefineLayout L = refine_layout(s, p);
     DM_REQUIRE(workspace != nullptr && workspace_bytes >= L.total, DM_ERR_WORKSPACE, "workspace %zu bytes, need %zu",
                workspace_bytes, L.total);
-    {
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) {
-            set_error("pending HIP error before dm_refine_continuous: %s", hipGetErrorString(e));
-            return DM_ERR_HIP;
-        }
-    }
+    if ((st = pending_hip("dm_refine_continuous")) != DM_OK) return st;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     char* ws = static_cast<char*>(workspace);
-    rfloat* u0 = reinterpret_cast<rfloat*>(ws + L.u0);
     rfloat* sL = reinterpret_cast<rfloat*>(ws + L.sL);
     rfloat* sR = reinterpret_cast<rfloat*>(ws + L.sR);
     RefineState S[2] = {state_at(ws + L.state0, L.plane), state_at(ws + L.state1, L.plane)};
@@ -257,6 +623,9 @@ extern "C" int dm_refine_continuous(const void* cost, dm_dtype cost_dtype, const
     const dim3 grid((s.W + kTX - 1) / kTX, (s.H + kTY - 1) / kTY);
     int cur = 0;
     for (int wp = 0; wp < p->n_warps; ++wp) {
+        // with a tape, every warp keeps its own u0 (the adjoint needs it)
+        rfloat* u0 = p->keep_tape ? reinterpret_cast<rfloat*>(ws + L.tape_u0 + (size_t)wp * L.plane)
+                                  : reinterpret_cast<rfloat*>(ws + L.u0);
         ProfScope ps1(DM_PROF_REFINE_LINEARIZE, npx * (4.0 + 4.0 * (cost_dtype == DM_F16 ? 2 : 4) + 12.0), stream);
         if (cost_dtype == DM_F16)
             hipLaunchKernelGGL(linearize_kernel<_Float16>, dim3(eb), dim3(256), 0, stream,
@@ -267,10 +636,13 @@ extern "C" int dm_refine_continuous(const void* cost, dm_dtype cost_dtype, const
         ps1.stop();
         DM_HIP_TRY(hipGetLastError(), "linearize");
         for (int it = 0; it < p->n_iters; ++it) {
+            uint16_t* mask = p->keep_tape ? reinterpret_cast<uint16_t*>(
+                                                ws + L.tape_mask + ((size_t)wp * p->n_iters + it) * L.mask_plane)
+                                          : nullptr;
             // per pixel: reads u, u0, sL, sR, 4 duals, 2 weights; writes u and 4 duals
             ProfScope ps2(DM_PROF_REFINE_ITER, npx * (8.0 * 13.0 + 8.0), stream);
             hipLaunchKernelGGL(pdhg_kernel, grid, dim3(256), 0, stream, S[cur], S[cur ^ 1], u0, sL, sR, w_h, w_v, s.W,
-                               s.H, s.K, sc);
+                               s.H, s.K, sc, mask);
             cur ^= 1;
         }
         DM_HIP_TRY(hipGetLastError(), "pdhg");
@@ -278,5 +650,82 @@ extern "C" int dm_refine_continuous(const void* cost, dm_dtype cost_dtype, const
     ProfScope ps3(DM_PROF_OTHER, 12.0 * npx, stream);
     hipLaunchKernelGGL(narrow_kernel, dim3(eb), dim3(256), 0, stream, S[cur].u, u_out, npx);
     DM_HIP_TRY(hipGetLastError(), "copy u");
+    return DM_OK;
+}
+
+extern "C" size_t dm_refine_continuous_backward_workspace(dm_shape s, const dm_refine_params* p) {
+    if (validate_refine(s, p) != DM_OK) return 0;
+    return refine_bwd_layout(s).total;
+}
+
+extern "C" int dm_refine_continuous_backward(const float* grad_u, const void* cost, dm_dtype cost_dtype,
+                                             const float* w_h, const float* w_v, dm_shape s,
+                                             const dm_refine_params* p, const void* fwd_workspace,
+                                             size_t fwd_workspace_bytes, float* grad_cost, float* grad_w_h,
+                                             float* grad_w_v, int accumulate, void* workspace, size_t workspace_bytes,
+                                             void* hip_stream) {
+    clear_error();
+    int st = validate_refine(s, p);
+    if (st != DM_OK) return st;
+    DM_REQUIRE(p->keep_tape == 1, DM_ERR_PARAM, "the forward must have been run with keep_tape = 1");
+    DM_REQUIRE(cost_dtype == DM_F32 || cost_dtype == DM_F16, DM_ERR_DTYPE, "unknown cost dtype %d", (int)cost_dtype);
+    DM_REQUIRE(grad_u != nullptr && cost != nullptr && grad_cost != nullptr && fwd_workspace != nullptr, DM_ERR_NULL,
+               "grad_u, cost, grad_cost and the forward workspace are required");
+    DM_REQUIRE(accumulate == 0 || accumulate == 1, DM_ERR_PARAM, "accumulate must be 0 or 1");
+    const RefineLayout LF = refine_layout(s, p);
+    DM_REQUIRE(fwd_workspace_bytes >= LF.total, DM_ERR_WORKSPACE, "forward workspace %zu bytes, need %zu",
+               fwd_workspace_bytes, LF.total);
+    const RefineBwdLayout LB = refine_bwd_layout(s);
+    DM_REQUIRE(workspace != nullptr && workspace_bytes >= LB.total, DM_ERR_WORKSPACE, "workspace %zu bytes, need %zu",
+               workspace_bytes, LB.total);
+    if ((st = pending_hip("dm_refine_continuous_backward")) != DM_OK) return st;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const char* fws = static_cast<const char*>(fwd_workspace);
+    char* ws = static_cast<char*>(workspace);
+    RefineState A[2] = {state_at(ws + LB.state0, LB.plane), state_at(ws + LB.state1, LB.plane)};
+    rfloat* acc = reinterpret_cast<rfloat*>(ws + LB.acc);
+    rfloat* acc_u0 = acc;
+    rfloat* acc_sL = reinterpret_cast<rfloat*>(ws + LB.acc + LB.plane);
+    rfloat* acc_sR = reinterpret_cast<rfloat*>(ws + LB.acc + 2 * LB.plane);
+    rfloat* acc_wh = reinterpret_cast<rfloat*>(ws + LB.acc + 3 * LB.plane);
+    rfloat* acc_wv = reinterpret_cast<rfloat*>(ws + LB.acc + 4 * LB.plane);
+    const long long npx = (long long)s.W * s.H;
+    const unsigned eb = (unsigned)std::min<long long>((npx + 255) / 256, 4096);
+    if (!accumulate) {
+        const long long vol = npx * s.K;
+        hipLaunchKernelGGL(fill_zero_f32_kernel, dim3(2048), dim3(256), 0, stream, grad_cost, vol);
+        DM_HIP_TRY(hipGetLastError(), "zero grad");
+    }
+    hipLaunchKernelGGL(adjoint_init_kernel, dim3(eb), dim3(256), 0, stream, grad_u, npx, A[0], acc_u0, acc_sL, acc_sR,
+                       acc_wh, acc_wv);
+    DM_HIP_TRY(hipGetLastError(), "adjoint init");
+    const RefineScalars sc = refine_scalars(*p);
+    const dim3 grid((s.W + kTX - 1) / kTX, (s.H + kTY - 1) / kTY);
+    int cur = 0;
+    for (int wp = p->n_warps - 1; wp >= 0; --wp) {
+        const rfloat* u0 = reinterpret_cast<const rfloat*>(fws + LF.tape_u0 + (size_t)wp * LF.plane);
+        for (int it = p->n_iters - 1; it >= 0; --it) {
+            const uint16_t* mask = reinterpret_cast<const uint16_t*>(
+                fws + LF.tape_mask + ((size_t)wp * p->n_iters + it) * LF.mask_plane);
+            hipLaunchKernelGGL(pdhg_adjoint_kernel, grid, dim3(256), 0, stream, A[cur], A[cur ^ 1], mask, u0, s.W, s.H,
+                               s.K, sc, acc_u0, acc_sL, acc_sR, acc_wh, acc_wv);
+            cur ^= 1;
+        }
+        DM_HIP_TRY(hipGetLastError(), "pdhg adjoint");
+        if (cost_dtype == DM_F16)
+            hipLaunchKernelGGL(linearize_adjoint_kernel<_Float16>, dim3(eb), dim3(256), 0, stream,
+                               static_cast<const _Float16*>(cost), u0, s.W, s.H, s.K, (rfloat)p->h, acc_u0, acc_sL,
+                               acc_sR, A[cur].u, wp > 0 ? 1 : 0, grad_cost);
+        else
+            hipLaunchKernelGGL(linearize_adjoint_kernel<float>, dim3(eb), dim3(256), 0, stream,
+                               static_cast<const float*>(cost), u0, s.W, s.H, s.K, (rfloat)p->h, acc_u0, acc_sL,
+                               acc_sR, A[cur].u, wp > 0 ? 1 : 0, grad_cost);
+        DM_HIP_TRY(hipGetLastError(), "linearize adjoint");
+    }
+    if (grad_w_h != nullptr || grad_w_v != nullptr) {
+        hipLaunchKernelGGL(edge_grad_kernel, dim3(eb), dim3(256), 0, stream, acc_wh, acc_wv, s.W, s.H, accumulate,
+                           grad_w_h, grad_w_v);
+        DM_HIP_TRY(hipGetLastError(), "edge grads");
+    }
     return DM_OK;
 }

@@ -48,7 +48,7 @@ def _cost_dtype(cost):
 
 
 def discrete_params(T=3, n_iters=10, n_half_steps=0, minorant="iterative", gammas=(0.25, 0.25, 1.0),
-                    warm_start=False, tile=None) -> L.DmDiscreteParams:
+                    warm_start=False, tile=None, keep_checkpoints=False) -> L.DmDiscreteParams:
     p = L.DmDiscreteParams()
     p.n_iters = int(n_iters)
     p.n_half_steps = int(n_half_steps)
@@ -60,7 +60,12 @@ def discrete_params(T=3, n_iters=10, n_half_steps=0, minorant="iterative", gamma
         p.gamma[i] = float(g)
     p.warm_start = 1 if warm_start else 0
     if tile is not None:
-        p.tile_lanes, p.labels_per_lane = int(tile[0]), int(tile[1])
+        # (lanes, labels per lane) for both families, or ((rows), (columns))
+        if isinstance(tile[0], (tuple, list)):
+            (p.tile_lanes, p.labels_per_lane), (p.tile_lanes_v, p.labels_per_lane_v) = tile
+        else:
+            p.tile_lanes, p.labels_per_lane = int(tile[0]), int(tile[1])
+    p.keep_checkpoints = 1 if keep_checkpoints else 0
     return p
 
 
@@ -71,6 +76,7 @@ class DiscreteResult:
     dual: torch.Tensor              # [H][W][K] float32
     bounds: torch.Tensor | None     # [2] float64: LB, E(labels)
     lb_trace: torch.Tensor | None   # [half-steps] float64
+    workspace: torch.Tensor | None = None  # holds the checkpoints when keep_checkpoints
 
 
 def tile_for(K: int):
@@ -89,15 +95,16 @@ def tile_for(K: int):
 def solve_discrete(cost, w_h, w_v, *, T=3, n_iters=10, n_half_steps=0, minorant="iterative",
                    gammas=(0.25, 0.25, 1.0), dual=None, warm_start=False, want_minmarg=True,
                    want_bounds=True, want_trace=False, tile=None, stream=None, workspace=None,
-                   labels=None, minmarg=None) -> DiscreteResult:
-    """Dual_MM on the GPU (dm_solve_discrete)."""
+                   labels=None, minmarg=None, keep_checkpoints=False) -> DiscreteResult:
+    """Dual_MM on the GPU (dm_solve_discrete).  With keep_checkpoints the returned
+    workspace holds what solve_discrete_backward needs."""
     H, W, K = cost.shape
     dev = cost.device
     _check_dev("cost", cost)
     _check_dev("w_h", w_h, torch.float32, (H, W - 1))
     _check_dev("w_v", w_v, torch.float32, (H - 1, W))
     dt = _cost_dtype(cost)
-    p = discrete_params(T, n_iters, n_half_steps, minorant, gammas, warm_start, tile)
+    p = discrete_params(T, n_iters, n_half_steps, minorant, gammas, warm_start, tile, keep_checkpoints)
     shape = L.DmShape(W, H, K)
     lib = L.lib()
     ws_bytes = lib.dm_solve_discrete_workspace(shape, dt, ctypes.byref(p))
@@ -125,23 +132,56 @@ def solve_discrete(cost, w_h, w_v, *, T=3, n_iters=10, n_half_steps=0, minorant=
                                ctypes.c_size_t(workspace.numel()), _stream(stream))
     L.check("dm_solve_discrete", st)
     return DiscreteResult(labels=labels, minmarg=minmarg, dual=dual, bounds=bounds,
-                          lb_trace=None if trace is None else trace[:S])
+                          lb_trace=None if trace is None else trace[:S], workspace=workspace)
 
 
-def refine_params(C=3.0, eps=1.0, delta=0.0, h=1.0, tau=0.3, sigma=0.3, n_warps=5, n_iters=40) -> L.DmRefineParams:
+def solve_discrete_backward(cost, w_h, w_v, dual, fwd_workspace, *, grad_minmarg=None, grad_lb=0.0, T=3,
+                            n_iters=10, n_half_steps=0, minorant="iterative", gammas=(0.25, 0.25, 1.0), tile=None,
+                            grad_cost=None, grad_w_h=None, grad_w_v=None, accumulate=False, workspace=None,
+                            stream=None):
+    """Adjoint of solve_discrete (dm_solve_discrete_backward); the forward must have run with
+    keep_checkpoints=True and the same parameters.  Returns (grad_cost, grad_w_h, grad_w_v)."""
+    H, W, K = cost.shape
+    dev = cost.device
+    _check_dev("dual", dual, torch.float32, (H, W, K))
+    _check_dev("grad_minmarg", grad_minmarg, torch.float32, (H, W, K))
+    p = discrete_params(T, n_iters, n_half_steps, minorant, gammas, False, tile, True)
+    shape = L.DmShape(W, H, K)
+    lib = L.lib()
+    ws_bytes = max(int(lib.dm_solve_discrete_backward_workspace(shape, ctypes.byref(p))), 256)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    if grad_cost is None:
+        grad_cost = torch.empty((H, W, K), dtype=torch.float32, device=dev)
+    if grad_w_h is None:
+        grad_w_h = torch.empty((H, W - 1), dtype=torch.float32, device=dev)
+    if grad_w_v is None:
+        grad_w_v = torch.empty((H - 1, W), dtype=torch.float32, device=dev)
+    st = lib.dm_solve_discrete_backward(_ptr(grad_minmarg), ctypes.c_double(float(grad_lb)), _ptr(cost),
+                                        _cost_dtype(cost), _ptr(w_h), _ptr(w_v), shape, ctypes.byref(p), _ptr(dual),
+                                        _ptr(fwd_workspace), ctypes.c_size_t(fwd_workspace.numel()), _ptr(grad_cost),
+                                        _ptr(grad_w_h), _ptr(grad_w_v), 1 if accumulate else 0, _ptr(workspace),
+                                        ctypes.c_size_t(workspace.numel()), _stream(stream))
+    L.check("dm_solve_discrete_backward", st)
+    return grad_cost, grad_w_h, grad_w_v
+
+
+def refine_params(C=3.0, eps=1.0, delta=0.0, h=1.0, tau=0.3, sigma=0.3, n_warps=5, n_iters=40,
+                  keep_tape=False) -> L.DmRefineParams:
     return L.DmRefineParams(float(C), float(eps), float(delta), float(h), float(tau), float(sigma), int(n_warps),
-                            int(n_iters))
+                            int(n_iters), 1 if keep_tape else 0)
 
 
 def refine_continuous(cost, labels, w_h, w_v, *, C=3.0, eps=1.0, delta=0.0, h=1.0, tau=0.3, sigma=0.3, n_warps=5,
-                      n_iters=40, stream=None, workspace=None, u_out=None):
-    """Warped non-linear primal-dual refinement (dm_refine_continuous); returns u [H][W] float32."""
+                      n_iters=40, stream=None, workspace=None, u_out=None, keep_tape=False):
+    """Warped non-linear primal-dual refinement (dm_refine_continuous); returns u [H][W] float32.
+    With keep_tape the workspace (pass your own tensor) holds what the backward call needs."""
     H, W, K = cost.shape
     _check_dev("cost", cost)
     _check_dev("labels", labels, torch.int32, (H, W))
     _check_dev("w_h", w_h, torch.float32, (H, W - 1))
     _check_dev("w_v", w_v, torch.float32, (H - 1, W))
-    p = refine_params(C, eps, delta, h, tau, sigma, n_warps, n_iters)
+    p = refine_params(C, eps, delta, h, tau, sigma, n_warps, n_iters, keep_tape)
     shape = L.DmShape(W, H, K)
     lib = L.lib()
     ws_bytes = max(int(lib.dm_refine_continuous_workspace(shape, ctypes.byref(p))), 256)
@@ -195,3 +235,107 @@ def profiler_query(kind: str):
     L.check("dm_profiler_query", L.lib().dm_profiler_query(L.PROF_KINDS[kind], ctypes.byref(n), ctypes.byref(ms),
                                                           ctypes.byref(by)))
     return int(n.value), float(ms.value), float(by.value)
+
+
+def refine_workspace_bytes(shape_hwk, keep_tape=False, **params):
+    H, W, K = shape_hwk
+    p = refine_params(keep_tape=keep_tape, **params)
+    return int(L.lib().dm_refine_continuous_workspace(L.DmShape(W, H, K), ctypes.byref(p)))
+
+
+def refine_continuous_backward(grad_u, cost, w_h, w_v, fwd_workspace, *, C=3.0, eps=1.0, delta=0.0, h=1.0, tau=0.3,
+                               sigma=0.3, n_warps=5, n_iters=40, grad_cost=None, grad_w_h=None, grad_w_v=None,
+                               accumulate=False, workspace=None, stream=None):
+    """Adjoint of refine_continuous (dm_refine_continuous_backward).  ``fwd_workspace`` is the
+    workspace tensor of a forward call made with keep_tape=True and the same parameters."""
+    H, W, K = cost.shape
+    _check_dev("grad_u", grad_u, torch.float32, (H, W))
+    p = refine_params(C, eps, delta, h, tau, sigma, n_warps, n_iters, True)
+    shape = L.DmShape(W, H, K)
+    lib = L.lib()
+    dev = cost.device
+    ws_bytes = max(int(lib.dm_refine_continuous_backward_workspace(shape, ctypes.byref(p))), 256)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    if grad_cost is None:
+        grad_cost = torch.empty((H, W, K), dtype=torch.float32, device=dev)
+    if grad_w_h is None:
+        grad_w_h = torch.empty((H, W - 1), dtype=torch.float32, device=dev)
+    if grad_w_v is None:
+        grad_w_v = torch.empty((H - 1, W), dtype=torch.float32, device=dev)
+    st = lib.dm_refine_continuous_backward(_ptr(grad_u), _ptr(cost), _cost_dtype(cost), _ptr(w_h), _ptr(w_v), shape,
+                                           ctypes.byref(p), _ptr(fwd_workspace), ctypes.c_size_t(fwd_workspace.numel()),
+                                           _ptr(grad_cost), _ptr(grad_w_h), _ptr(grad_w_v), 1 if accumulate else 0,
+                                           _ptr(workspace), ctypes.c_size_t(workspace.numel()), _stream(stream))
+    L.check("dm_refine_continuous_backward", st)
+    return grad_cost, grad_w_h, grad_w_v
+
+
+def autotune_tiles(shape_hwk, cost_dtype=torch.float16, *, T=3, minorant="iterative", gammas=(0.25, 0.25, 1.0),
+                   stream=None):
+    """Fastest compiled tile for row and column chains of this shape (dm_autotune_tiles).
+    Returns ((lanes, labels per lane) rows, (lanes, labels per lane) columns)."""
+    H, W, K = shape_hwk
+    p = discrete_params(T=T, n_iters=1, minorant=minorant, gammas=gammas)
+    dt = L.DM_F16 if cost_dtype == torch.float16 else L.DM_F32
+    st = L.lib().dm_autotune_tiles(L.DmShape(W, H, K), dt, ctypes.byref(p), _stream(stream))
+    L.check("dm_autotune_tiles", st)
+    return (p.tile_lanes, p.labels_per_lane), (p.tile_lanes_v, p.labels_per_lane_v)
+
+
+class BatchedPlan:
+    """Many uneven instances solved by one hipGraph launch (dm_plan_batched / dm_run_batched).
+
+    ``instances``: list of dicts with GPU tensors ``cost`` [H][W][K] (all float32 or all
+    float16), ``w_h``, ``w_v``; the plan allocates ``labels``, ``dual`` and (with
+    refinement) ``u`` for each instance unless given.  Keep the object alive while
+    running; call ``close()`` (or drop it) to free the plan's device memory.
+    """
+
+    def __init__(self, instances, *, T=3, n_iters=20, n_half_steps=0, minorant="iterative",
+                 gammas=(0.25, 0.25, 1.0), tile=None, refine=None):
+        self.instances = []
+        arr = (L.DmInstance * len(instances))()
+        dtype = instances[0]["cost"].dtype
+        for i, inst in enumerate(instances):
+            cost = inst["cost"]
+            if cost.dtype != dtype:
+                raise ValueError("all instances must share the cost dtype")
+            H, W, K = cost.shape
+            d = dict(inst)
+            dev = cost.device
+            d.setdefault("labels", torch.empty((H, W), dtype=torch.int32, device=dev))
+            d.setdefault("dual", torch.empty((H, W, K), dtype=torch.float32, device=dev))
+            if refine is not None:
+                d.setdefault("u", torch.empty((H, W), dtype=torch.float32, device=dev))
+            for k in ("cost", "w_h", "w_v", "labels", "dual"):
+                _check_dev(k, d[k])
+            arr[i] = L.DmInstance(L.DmShape(W, H, K), _ptr(cost), _ptr(d["w_h"]), _ptr(d["w_v"]), _ptr(d["labels"]),
+                                  _ptr(d["dual"]), _ptr(d.get("u")))
+            self.instances.append(d)
+        p = discrete_params(T, n_iters, n_half_steps, minorant, gammas, False, tile, False)
+        rp = None if refine is None else refine_params(**refine)
+        handle = ctypes.c_void_p()
+        self._lib = L.lib()
+        st = self._lib.dm_plan_batched(arr, len(instances), _cost_dtype(instances[0]["cost"]), ctypes.byref(p),
+                                       None if rp is None else ctypes.byref(rp), ctypes.byref(handle))
+        L.check("dm_plan_batched", st)
+        self.handle = handle
+
+    @property
+    def device_bytes(self):
+        return int(self._lib.dm_plan_device_bytes(self.handle))
+
+    def run(self, stream=None):
+        L.check("dm_run_batched", self._lib.dm_run_batched(self.handle, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.dm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,124 @@
+"""GPU tests of the batched form (dm_plan_batched / dm_run_batched) and the autotuner.
+
+Every instance of a batch must equal its single-instance solve bit for bit when both
+use the same chain tiles (same arithmetic per chain), on every replay of the graph,
+with eager work and synchronisations between replays; and the oracle within the
+parity tolerances.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dmm as odmm, refine as oref
+from tests.parity import MM_RTOL, check_labels
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _need():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1601_06274_amd import ops
+    return ops
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def _instances(specs, dtype=torch.float32):
+    out = []
+    for (H, W, K, seed) in specs:
+        theta, w_h, w_v = synth.tiny_instance(H, W, K, seed=seed, w_max=0.4)
+        out.append(dict(cost=_dev(theta, dtype), w_h=_dev(w_h), w_v=_dev(w_v), theta=theta, wh=w_h, wv=w_v))
+    return out
+
+
+SPECS = [(7, 11, 8, 1), (12, 5, 32, 2), (3, 30, 20, 3), (16, 16, 64, 4), (9, 23, 8, 5), (1, 17, 5, 6), (13, 1, 4, 7)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
+def test_batched_equals_single_instance_bitwise(dtype):
+    ops = _need()
+    insts = _instances(SPECS, dtype)
+    print(f"[case] batched {len(insts)} instances {dtype}", flush=True)
+    tiles = {}
+    for d in insts:
+        K = d["cost"].shape[2]
+        tiles[K] = ops.tile_for(K)
+    # one fixed tile per K: give the plan the per-K default through single-K batches
+    plan = ops.BatchedPlan([{k: d[k] for k in ("cost", "w_h", "w_v")} for d in insts], T=3, n_iters=3,
+                           tile=None)
+    try:
+        singles = []
+        for d in insts:
+            K = d["cost"].shape[2]
+            tr, tc = ops.autotune_tiles(tuple(d["cost"].shape), dtype, T=3)
+            singles.append(ops.solve_discrete(d["cost"], d["w_h"], d["w_v"], T=3, n_iters=3, tile=(tr, tc)))
+        torch.cuda.synchronize()
+        for rep in range(3):
+            plan.run()
+            torch.cuda.synchronize()
+            _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+            for i, (pi, s) in enumerate(zip(plan.instances, singles)):
+                assert torch.equal(pi["labels"], s.labels), f"replay {rep} instance {i} labels"
+                assert torch.equal(pi["dual"], s.dual), f"replay {rep} instance {i} dual"
+    finally:
+        plan.close()
+
+
+def test_batched_oracle_parity_and_refinement():
+    ops = _need()
+    specs = [(6, 9, 8, 11), (10, 7, 16, 12), (5, 14, 12, 13)]
+    insts = _instances(specs)
+    plan = ops.BatchedPlan([{k: d[k] for k in ("cost", "w_h", "w_v")} for d in insts], T=2, n_iters=2,
+                           refine=dict(C=2.0, n_warps=2, n_iters=10))
+    try:
+        plan.run()
+        torch.cuda.synchronize()
+        for d, pi in zip(insts, plan.instances):
+            th = d["theta"].astype(np.float64)
+            ref = odmm.solve_discrete(th, d["wh"], d["wv"], 2, 2)
+            lab = pi["labels"].cpu().numpy()
+            ndiff, nbad = check_labels(lab, ref.labels, ref.minmarg, th)
+            assert nbad == 0
+            np.testing.assert_allclose(pi["dual"].cpu().numpy(), ref.lam, atol=1e-4)
+            P32 = oref.RefineParams(C=2.0, tau=float(np.float32(0.3)), sigma=float(np.float32(0.3)), n_warps=2,
+                                    n_iters=10)
+            u_ref = oref.refine_continuous(th, d["wh"], d["wv"], lab, P32)
+            assert np.abs(pi["u"].cpu().numpy() - u_ref).max() <= 1e-4
+    finally:
+        plan.close()
+
+
+def test_batched_uneven_random_sizes():
+    """A small draw of the uneven-size recipe (sizes scaled down): plan, two replays, checks."""
+    ops = _need()
+    specs = synth.batch_specs(6, seed=4000, w_range=(20, 90), h_range=(12, 50), k_choices=(8, 16, 32))
+    insts = []
+    for sp in specs:
+        pair = synth.stereo_pair(sp.W, sp.H, sp.K, seed=sp.seed)
+        from oracle import cost_volume as ocv
+        th = ocv.sad_cost_volume(pair.left, pair.right, sp.K).astype(np.float16)
+        wh, wv = ocv.contrast_weights(pair.left)
+        insts.append(dict(cost=_dev(th, torch.float16), w_h=_dev(wh), w_v=_dev(wv), theta=th, wh=wh, wv=wv))
+    plan = ops.BatchedPlan([{k: d[k] for k in ("cost", "w_h", "w_v")} for d in insts], T=3, n_iters=3)
+    try:
+        for _ in range(2):
+            plan.run()
+            torch.cuda.synchronize()
+            for d, pi in zip(insts, plan.instances):
+                ref = odmm.solve_discrete(d["theta"].astype(np.float64), d["wh"], d["wv"], 3, 3)
+                lab = pi["labels"].cpu().numpy()
+                _, nbad = check_labels(lab, ref.labels, ref.minmarg, d["theta"].astype(np.float64))
+                assert nbad == 0
+    finally:
+        plan.close()
+
+
+def test_autotuner_returns_valid_tiles():
+    ops = _need()
+    for shape in [(20, 40, 32), (30, 25, 192), (9, 9, 5)]:
+        (gr, lr), (gc, lc) = ops.autotune_tiles(shape, torch.float16)
+        assert gr * lr >= shape[2] and gc * lc >= shape[2]

@@ -1,0 +1,220 @@
+"""GPU reverse-mode gradients (dm_solve_discrete_backward, dm_refine_continuous_backward)
+against the FP64 oracle's forward-mode derivatives and against central finite differences.
+
+For a loss L = <G_m, minmarg> + g_lb * LB + <G_u, u> with fixed random G, the GPU returns
+dL/dcost and dL/dw.  For random directions v, <grad_gpu, v> must match the oracle's
+directional derivative within 1e-4 of the sum of |grad_i v_i| (FP32 adjoint vs FP64).
+Inputs are generic (U[0,1) costs, random weights) so that no argmin is tied.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import grad as ograd, refine as oref, dmm as odmm
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+REL = 1e-4
+
+
+def _need():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1601_06274_amd import ops
+    return ops
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def _discrete_case(H, W, K, T, n_iters, seed, *, minorant="iterative", gammas=(0.25, 0.25, 1.0), g_lb=0.7,
+                   n_half=0, tile=None, dirs=4, cost_dtype=torch.float32):
+    ops = _need()
+    theta, w_h, w_v = synth.tiny_instance(H, W, K, seed=seed, w_max=0.5)
+    th = _dev(theta, cost_dtype)
+    th64 = th.float().cpu().numpy().astype(np.float64)
+    g = np.random.default_rng(seed + 1)
+    Gm = g.normal(size=(H, W, K)).astype(np.float32)
+    print(f"[case] discrete grad {H}x{W}x{K} T={T} iters={n_iters} half={n_half} {minorant} tile={tile} "
+          f"{cost_dtype}", flush=True)
+    kw = dict(T=T, n_iters=n_iters, n_half_steps=n_half, minorant=minorant, gammas=gammas, tile=tile)
+    res = ops.solve_discrete(th, _dev(w_h), _dev(w_v), keep_checkpoints=True, **kw)
+    gc, gwh, gwv = ops.solve_discrete_backward(th, _dev(w_h), _dev(w_v), res.dual, res.workspace,
+                                               grad_minmarg=_dev(Gm), grad_lb=g_lb, **kw)
+    torch.cuda.synchronize()
+    gc, gwh, gwv = gc.cpu().numpy().astype(np.float64), gwh.cpu().numpy().astype(np.float64), \
+        gwv.cpu().numpy().astype(np.float64)
+    worst = 0.0
+    for d in range(dirs):
+        gd = np.random.default_rng(100 * seed + d)
+        td, whd, wvd = gd.normal(size=theta.shape), gd.normal(size=w_h.shape), gd.normal(size=w_v.shape)
+        _, mmd, _, lbd, _ = ograd.solve_discrete_jvp(th64, td, w_h.astype(np.float64), whd, w_v.astype(np.float64),
+                                                     wvd, T, n_iters, minorant=minorant, gammas=gammas,
+                                                     n_half_steps=n_half or None)
+        ref = float((Gm.astype(np.float64) * mmd).sum() + g_lb * lbd)
+        terms = np.concatenate([(gc * td).ravel(), (gwh * whd).ravel(), (gwv * wvd).ravel()])
+        got = float(terms.sum())
+        scale = float(np.abs(terms).sum()) + 1e-12
+        worst = max(worst, abs(got - ref) / scale)
+    print(f"[parity] discrete grad: worst rel err {worst:.3e}", flush=True)
+    return worst
+
+
+def test_discrete_grad_small():
+    assert _discrete_case(6, 7, 5, 2, 2, seed=1) <= REL
+
+
+def test_discrete_grad_config_fd_size():
+    """16x16 grid, K=8 (the finite-difference workload), 3 dual iterations."""
+    assert _discrete_case(16, 16, 8, 3, 3, seed=2, dirs=3) <= REL
+
+
+@pytest.mark.parametrize("tile", [(4, 2), (8, 4), (32, 3), (64, 3)])
+def test_discrete_grad_tiles(tile):
+    K = min(tile[0] * tile[1], 12)
+    assert _discrete_case(5, 8, K, 3, 1, seed=K + tile[0], tile=tile, dirs=2) <= REL
+
+
+@pytest.mark.parametrize("T", [1, 5])
+def test_discrete_grad_truncations(T):
+    assert _discrete_case(5, 6, 9, T, 2, seed=10 + T, dirs=2) <= REL
+
+
+def test_discrete_grad_naive_and_odd_half_steps():
+    assert _discrete_case(6, 6, 4, 2, 0, seed=5, minorant="naive", n_half=3, dirs=2) <= REL
+    assert _discrete_case(6, 6, 4, 2, 0, seed=6, n_half=1, dirs=2) <= REL
+
+
+def test_discrete_grad_gamma_schedules():
+    assert _discrete_case(5, 7, 6, 2, 2, seed=8, gammas=(0.5, 1.0), dirs=2) <= REL
+    assert _discrete_case(5, 7, 6, 2, 1, seed=9, gammas=(0.25, 0.25, 0.25, 0.25, 1.0), dirs=2) <= REL
+
+
+def test_discrete_grad_fp16_cost():
+    assert _discrete_case(6, 8, 8, 3, 2, seed=12, cost_dtype=torch.float16, dirs=2) <= REL
+
+
+def test_discrete_grad_finite_difference():
+    """Third opinion: central differences of the FP64 oracle's loss (smooth directions only)."""
+    ops = _need()
+    H, W, K, T, it = 16, 16, 8, 3, 2
+    theta, w_h, w_v = synth.tiny_instance(H, W, K, seed=21, w_max=0.5)
+    g = np.random.default_rng(3)
+    Gm = g.normal(size=(H, W, K))
+    res = ops.solve_discrete(_dev(theta), _dev(w_h), _dev(w_v), T=T, n_iters=it, keep_checkpoints=True)
+    gc, gwh, gwv = ops.solve_discrete_backward(_dev(theta), _dev(w_h), _dev(w_v), res.dual, res.workspace,
+                                               grad_minmarg=_dev(Gm), grad_lb=0.0, T=T, n_iters=it)
+    gc = gc.cpu().numpy().astype(np.float64)
+    th64, wh64, wv64 = theta.astype(np.float64), w_h.astype(np.float64), w_v.astype(np.float64)
+
+    def loss(t, v):
+        r = odmm.solve_discrete(th64 + t * v, wh64, wv64, T, it)
+        return float((Gm * r.minmarg).sum())
+    checked = 0
+    for d in range(4):
+        v = np.random.default_rng(50 + d).normal(size=theta.shape)
+        eps = 1e-6
+        fp, f0, fm = loss(eps, v), loss(0.0, v), loss(-eps, v)
+        if abs((fp - f0) - (f0 - fm)) > 1e-6 * max(1.0, abs(fp - fm)):
+            continue  # a kink between the evaluation points
+        fd = (fp - fm) / (2 * eps)
+        got = float((gc * v).sum())
+        scale = float(np.abs(gc * v).sum())
+        print(f"[parity] discrete FD dir {d}: fd={fd:.6e} gpu={got:.6e}", flush=True)
+        assert abs(got - fd) <= REL * scale + 1e-6
+        checked += 1
+    assert checked >= 2
+
+
+def _refine_case(H, W, K, warps, iters, seed, cost_dtype=torch.float32, dirs=3, C=2.0, eps=1.0, delta=0.0):
+    ops = _need()
+    theta, w_h, w_v = synth.tiny_instance(H, W, K, seed=seed, w_max=0.5)
+    th = _dev(theta, cost_dtype)
+    th64 = th.float().cpu().numpy().astype(np.float64)
+    labels = np.random.default_rng(seed).integers(1, K - 1, (H, W))
+    Gu = np.random.default_rng(seed + 7).normal(size=(H, W)).astype(np.float32)
+    print(f"[case] refine grad {H}x{W}x{K} warps={warps} iters={iters} {cost_dtype}", flush=True)
+    kw = dict(C=C, eps=eps, delta=delta, n_warps=warps, n_iters=iters)
+    nbytes = ops.refine_workspace_bytes((H, W, K), keep_tape=True, **kw)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    ops.refine_continuous(th, _dev(labels, torch.int32), _dev(w_h), _dev(w_v), workspace=ws, keep_tape=True, **kw)
+    gc, gwh, gwv = ops.refine_continuous_backward(_dev(Gu), th, _dev(w_h), _dev(w_v), ws, **kw)
+    torch.cuda.synchronize()
+    gc, gwh, gwv = (x.cpu().numpy().astype(np.float64) for x in (gc, gwh, gwv))
+    P32 = oref.RefineParams(C=C, eps=eps, delta=delta, tau=float(np.float32(0.3)), sigma=float(np.float32(0.3)),
+                            n_warps=warps, n_iters=iters)
+    worst = 0.0
+    for d in range(dirs):
+        gd = np.random.default_rng(1000 * seed + d)
+        td, whd, wvd = gd.normal(size=theta.shape), gd.normal(size=w_h.shape), gd.normal(size=w_v.shape)
+        _, ud = ograd.refine_continuous_jvp(th64, td, w_h.astype(np.float64), whd, w_v.astype(np.float64), wvd,
+                                            labels, P32)
+        ref = float((Gu.astype(np.float64) * ud).sum())
+        terms = np.concatenate([(gc * td).ravel(), (gwh * whd).ravel(), (gwv * wvd).ravel()])
+        scale = float(np.abs(terms).sum()) + 1e-12
+        worst = max(worst, abs(float(terms.sum()) - ref) / scale)
+    print(f"[parity] refine grad: worst rel err {worst:.3e}", flush=True)
+    return worst
+
+
+def test_refine_grad_single_warp():
+    assert _refine_case(7, 9, 8, 1, 20, seed=1) <= REL
+
+
+def test_refine_grad_multi_warp():
+    assert _refine_case(12, 10, 10, 3, 15, seed=2) <= REL
+
+
+def test_refine_grad_dc_params_fp16():
+    assert _refine_case(8, 8, 8, 2, 10, seed=3, cost_dtype=torch.float16, eps=0.5, delta=0.5) <= REL
+
+
+def test_refine_grad_ragged_tiles():
+    assert _refine_case(5, 70, 6, 2, 8, seed=4, dirs=2) <= REL
+
+
+def test_autograd_end_to_end():
+    """torch.autograd through both stages equals the sum of the two backward calls."""
+    _need()
+    from paper_1601_06274_amd.autograd import refine_continuous_ad, solve_discrete_ad
+    H, W, K = 10, 12, 8
+    theta, w_h, w_v = synth.tiny_instance(H, W, K, seed=31, w_max=0.4)
+    lam_pw = torch.tensor(1.3, device="cuda", requires_grad=True)
+    th = _dev(theta).requires_grad_(True)
+    wh0, wv0 = _dev(w_h), _dev(w_v)
+    wh, wv = lam_pw * wh0, lam_pw * wv0
+    mm, lb, lab = solve_discrete_ad(th, wh, wv, T=3, n_iters=2)
+    u = refine_continuous_ad(th, lab, wh, wv, C=3.0, n_warps=2, n_iters=10)
+    g = np.random.default_rng(0)
+    Gm, Gu = _dev(g.normal(size=(H, W, K))), _dev(g.normal(size=(H, W)))
+    loss = (Gm * mm).sum() + 0.5 * lb.sum() + (Gu * u).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    assert th.grad is not None and lam_pw.grad is not None
+    # compare d loss / d lam_pw with the chain rule through the weights
+    from paper_1601_06274_amd import ops
+    res = ops.solve_discrete(th.detach(), wh.detach(), wv.detach(), T=3, n_iters=2, keep_checkpoints=True)
+    _, gwh1, gwv1 = ops.solve_discrete_backward(th.detach(), wh.detach(), wv.detach(), res.dual, res.workspace,
+                                                grad_minmarg=Gm, grad_lb=0.5, T=3, n_iters=2)
+    nb = ops.refine_workspace_bytes((H, W, K), keep_tape=True, C=3.0, n_warps=2, n_iters=10)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    ops.refine_continuous(th.detach(), res.labels, wh.detach(), wv.detach(), workspace=ws, keep_tape=True, C=3.0,
+                          n_warps=2, n_iters=10)
+    _, gwh2, gwv2 = ops.refine_continuous_backward(Gu, th.detach(), wh.detach(), wv.detach(), ws, C=3.0, n_warps=2,
+                                                   n_iters=10)
+    want = float(((gwh1 + gwh2) * wh0).sum() + ((gwv1 + gwv2) * wv0).sum())
+    assert float(lam_pw.grad) == pytest.approx(want, rel=1e-5, abs=1e-6)
+
+
+def test_backward_deterministic():
+    ops = _need()
+    theta, w_h, w_v = synth.uniform_unaries(20, 30, 16, seed=4)
+    th, wh, wv = _dev(theta), _dev(w_h), _dev(w_v)
+    res = ops.solve_discrete(th, wh, wv, T=3, n_iters=2, keep_checkpoints=True)
+    Gm = _dev(np.random.default_rng(1).normal(size=theta.shape))
+    a = ops.solve_discrete_backward(th, wh, wv, res.dual, res.workspace, grad_minmarg=Gm, grad_lb=1.0, T=3, n_iters=2)
+    b = ops.solve_discrete_backward(th, wh, wv, res.dual, res.workspace, grad_minmarg=Gm, grad_lb=1.0, T=3, n_iters=2)
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
