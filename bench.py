@@ -9,10 +9,14 @@ frames of that size).  One step is
     build_cost_volume (3x3 SAD, truncated at 0.3, stored FP16; contrast weights)
     -> solve_discrete  (Dual_MM, 20 dual iterations, iterative minorant, T = 3)
     -> refine_continuous (5 warps x 40 primal-dual iterations)
+    -> refine_continuous_backward -> solve_discrete_backward
+       (dL/dcost and dL/dw for L = <G_m, min-marginals> + LB + <G_u, u>, seeded G)
 
-on images already resident in HBM.  ``value`` is the whole-step throughput in
-chain-DP label-node updates per second: every dual iteration visits every
-label-node in 8 chain sweeps (4 per half-step), the final labeling in 2 more.
+on images already resident in HBM.  ``ms_per_step`` is forward + backward per frame;
+``value`` is the forward's chain-DP label-node updates per frame (every dual
+iteration visits every label-node in 8 chain sweeps, 4 per half-step, the final
+labeling in 2 more) times frames per second of that step.  A forward-only loop is
+timed first (reported under "forward_only"; the sweep roofline comes from it).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 Prints one JSON line.
@@ -107,35 +111,67 @@ def main():
     u = torch.empty((H, W), dtype=torch.float32, device=dev)
     import ctypes
     lib = P.lib()
-    dp = ops.discrete_params(T=wl["T"], n_iters=wl["n_iters"], gammas=wl["gammas"])
-    ws_d = torch.empty(lib.dm_solve_discrete_workspace(P._lib.DmShape(W, H, K), P._lib.DM_F16, ctypes.byref(dp)),
-                       dtype=torch.uint8, device=dev)
-    rp = ops.refine_params(C=wl["C"], n_warps=wl["n_warps"], n_iters=wl["refine_iters"])
-    ws_r = torch.empty(lib.dm_refine_continuous_workspace(P._lib.DmShape(W, H, K), ctypes.byref(rp)),
-                       dtype=torch.uint8, device=dev)
+    shp = P._lib.DmShape(W, H, K)
+    dkw = dict(T=wl["T"], n_iters=wl["n_iters"], gammas=wl["gammas"])
+    rkw = dict(C=wl["C"], n_warps=wl["n_warps"], n_iters=wl["refine_iters"])
+    dp = ops.discrete_params(T=wl["T"], n_iters=wl["n_iters"], gammas=wl["gammas"], keep_checkpoints=True)
+    ws_d = torch.empty(lib.dm_solve_discrete_workspace(shp, P._lib.DM_F16, ctypes.byref(dp)), dtype=torch.uint8,
+                       device=dev)
+    ws_db = torch.empty(lib.dm_solve_discrete_backward_workspace(shp, ctypes.byref(dp)), dtype=torch.uint8, device=dev)
+    rp = ops.refine_params(keep_tape=True, **rkw)
+    ws_r = torch.empty(lib.dm_refine_continuous_workspace(shp, ctypes.byref(rp)), dtype=torch.uint8, device=dev)
+    ws_rb = torch.empty(lib.dm_refine_continuous_backward_workspace(shp, ctypes.byref(rp)), dtype=torch.uint8,
+                        device=dev)
+    # loss L = <G_m, normalized min-marginals> + g_lb * LB + <G_u, u>, fixed seeded G
+    gen = torch.Generator(device=dev).manual_seed(wl["seed"] + 1)
+    G_m = torch.randn((H, W, K), generator=gen, device=dev, dtype=torch.float32)
+    G_u = torch.randn((H, W), generator=gen, device=dev, dtype=torch.float32)
+    g_lb = 1.0
+    grad_cost = torch.empty((H, W, K), dtype=torch.float32, device=dev)
+    grad_wh = torch.empty((H, W - 1), dtype=torch.float32, device=dev)
+    grad_wv = torch.empty((H - 1, W), dtype=torch.float32, device=dev)
+
+    def forward():
+        ops.build_cost_volume(IL, IR, K, dtype=torch.float16, cost_out=cost, w_h=w_h, w_v=w_v)
+        res = ops.solve_discrete(cost, w_h, w_v, dual=dual, workspace=ws_d, labels=labels, minmarg=minmarg,
+                                 want_bounds=True, keep_checkpoints=True, **dkw)
+        ops.refine_continuous(cost, labels, w_h, w_v, workspace=ws_r, u_out=u, keep_tape=True, **rkw)
+        return res
+
+    def backward():
+        ops.refine_continuous_backward(G_u, cost, w_h, w_v, ws_r, grad_cost=grad_cost, grad_w_h=grad_wh,
+                                       grad_w_v=grad_wv, accumulate=False, workspace=ws_rb, **rkw)
+        ops.solve_discrete_backward(cost, w_h, w_v, dual, ws_d, grad_minmarg=G_m, grad_lb=g_lb, grad_cost=grad_cost,
+                                    grad_w_h=grad_wh, grad_w_v=grad_wv, accumulate=True, workspace=ws_db, **dkw)
 
     def step():
-        ops.build_cost_volume(IL, IR, K, dtype=torch.float16, cost_out=cost, w_h=w_h, w_v=w_v)
-        res = ops.solve_discrete(cost, w_h, w_v, T=wl["T"], n_iters=wl["n_iters"], gammas=wl["gammas"], dual=dual,
-                                 workspace=ws_d, labels=labels, minmarg=minmarg, want_bounds=True)
-        ops.refine_continuous(cost, labels, w_h, w_v, C=wl["C"], n_warps=wl["n_warps"], n_iters=wl["refine_iters"],
-                              workspace=ws_r, u_out=u)
+        res = forward()
+        backward()
         return res
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
 
-    # Timed region: the sweep kernels are bracketed by HIP events on their stream.
+    # Forward-only frames; the sweep kernels are bracketed by HIP events on their stream.
     ops.profiler_enable(["sweep_h", "sweep_v", "sweep_final", "cost_volume"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = forward()
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ops.profiler_disable()
+
+    # Timed steps: forward + backward of the whole frame.
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         res = step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    ops.profiler_disable()
     ms_per_step = el * 1e3 / args.steps
+    grad_finite = bool(torch.isfinite(grad_cost).all().item() and torch.isfinite(grad_wh).all().item())
 
     prof = {k: ops.profiler_query(k) for k in ["sweep_h", "sweep_v", "sweep_final", "cost_volume"]}
     n_h, ms_h, by_h = prof["sweep_h"]
@@ -155,12 +191,12 @@ def main():
             traffic = None
 
     N = H * W * K
-    updates = N * (8 * wl["n_iters"] + 2)
+    updates = N * (8 * wl["n_iters"] + 2)  # forward label-node updates per frame
     bounds = res.bounds.cpu().numpy()
 
     out = {
         "metric": "chain-DP label-node updates/s + HBM GB/s; fwd+bwd ms/frame at 1242x375x192",
-        "value": updates / (ms_per_step * 1e-3),
+        "value": updates / (ms_per_step * 1e-3),  # forward updates per frame x frames/s of fwd+bwd
         "unit": "label-node updates/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -173,11 +209,16 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "stereo 1242x375, K=192 disparities, FP16 cost volume (3x3 SAD), Dual_MM 20 dual its "
-                        "(iterative minorant 1/4,1/4,1, T=3) + refinement 5 warps x 40 its; forward only "
-                        "(backward not yet in the step)",
+                        "(iterative minorant 1/4,1/4,1, T=3) + refinement 5 warps x 40 its; step = forward + "
+                        "backward (dL/dcost, dL/dw for L = <G_m, min-marginals> + LB + <G_u, u>); value counts "
+                        "the forward's label-node updates per frame",
             "W": W, "H": H, "K": K, "cost_storage": "f16", "state": "f32",
-            "stages": ["build_cost_volume", "solve_discrete", "refine_continuous"],
+            "stages": ["build_cost_volume", "solve_discrete", "refine_continuous", "refine_continuous_backward",
+                       "solve_discrete_backward"],
         },
+        "fwd_bwd_ms_per_frame": ms_per_step,
+        "forward_only": {"ms_per_frame": fwd_ms, "label_node_updates_per_s": updates / (fwd_ms * 1e-3)},
+        "grad_finite": grad_finite,
         "roofline": {
             "bound": "hbm",
             "kernel": "horizontal half-step chain sweep (R0 + 3 update passes, FP16 cost)",

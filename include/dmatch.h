@@ -49,7 +49,9 @@ typedef enum { DM_F32 = 0, DM_F16 = 1 } dm_dtype;   /* storage type of the cost 
 
 typedef enum { DM_MINORANT_ITERATIVE = 0, DM_MINORANT_NAIVE = 1 } dm_minorant;
 
-/* Grid of W x H pixels with K labels; 1 <= W, H <= 16384, 1 <= K <= 256. */
+/* Grid of W x H pixels with K labels; 1 <= W, H <= 16384, 1 <= K <= 256, and one FP32
+ * volume (W*H*K*4 bytes) at most 0xFFFFFF00 bytes: the kernels address volumes with
+ * 32-bit byte offsets.  Larger shapes fail with DM_ERR_SHAPE. */
 typedef struct { int W, H, K; } dm_shape;
 
 /* ---------------------------------------------------------------------------------
@@ -138,8 +140,12 @@ int dm_autotune_tiles(dm_shape s, dm_dtype cost_dtype, dm_discrete_params* p, vo
  * the exact derivative of the piecewise-linear Dual_MM map as computed: minimisations
  * route the adjoint to the selected candidate, lowest label on exact ties).
  * Loss inputs: grad_minmarg [H][W][K] = dL/d(normalized row min-marginals) (may be NULL)
- * and grad_lb = dL/d(lower bound) (the bound's derivative is the one-hot of the row and
- * column optima, unique optima assumed).  Labels carry no gradient.
+ * and grad_lb = dL/d(lower bound).  A half-step leaves its own family's chain optima
+ * unchanged as functions of the inputs (the subtracted minorant vanishes on the optimal
+ * labeling) but leaves that family's min-marginals tied; so the bound's derivative is the
+ * one-hot of the optimal labelings of the family of the last half-step taken at the dual
+ * before that half-step, and of the other family at the final dual (unique optima there
+ * assumed).  Labels carry no gradient.
  *   dual          [H][W][K] the final dual of the forward call.
  *   fwd_workspace the forward's workspace, run with keep_checkpoints = 1 and the same
  *                 parameters, unchanged since.

@@ -39,17 +39,29 @@ __global__ void copy_f32_kernel(const float* __restrict__ a, float* __restrict__
     for (; i < n; i += stride) b[i] = a[i];
 }
 
-// Lower-bound adjoint of the column optima of G (unaries lambda): one-hot at the column
-// optimum labels, and the pairwise terms of the column optima for the vertical weights.
-__global__ void lb_col_adjoint_kernel(const int* __restrict__ lab, int W, int H, int K, int T, double g,
-                                      float* __restrict__ lbar, double* __restrict__ gw_v) {
+// Lower-bound adjoint of one chain family's optima at a dual lambda: the derivative of a
+// chain optimum with respect to its unaries is the one-hot of its (unique) optimal
+// labeling `lab`, and with respect to an edge weight the truncated distance of the two
+// labels.  Rows have unaries cost - lambda (cost gets +g, dual -g), columns lambda (+g).
+__global__ void lb_inject_kernel(const int* __restrict__ lab, int W, int H, int K, int T, double g, int rows,
+                                 float* __restrict__ lbar, float* __restrict__ gcost, double* __restrict__ gw) {
     const long long n = (long long)W * H;
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
         const int l = min(max(lab[p], 0), K - 1);
-        lbar[p * K + l] += (float)g;
-        if (p / W + 1 < H) {
-            const int d = abs(l - min(max(lab[p + W], 0), K - 1));
-            gw_v[p] += g * (double)(d < T ? d : T);
+        const int x = (int)(p % W), y = (int)(p / W);
+        if (rows) {
+            lbar[p * K + l] -= (float)g;
+            gcost[p * K + l] += (float)g;
+            if (x + 1 < W) {
+                const int d = abs(l - min(max(lab[p + 1], 0), K - 1));
+                gw[(long long)y * (W - 1) + x] += g * (double)(d < T ? d : T);
+            }
+        } else {
+            lbar[p * K + l] += (float)g;
+            if (y + 1 < H) {
+                const int d = abs(l - min(max(lab[p + W], 0), K - 1));
+                gw[p] += g * (double)(d < T ? d : T);
+            }
         }
     }
 }
@@ -631,7 +643,32 @@ extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad
         return b;
     };
 
-    // 1. final row pass: dL/dminmarg and the row part of dL/dLB -> dL/dcost, dL/d(final dual)
+    // Lower bound LB = sum of row optima + sum of column optima at the final dual.  A
+    // half-step leaves the optimum of its own family unchanged as a function of the
+    // inputs (it subtracts a minorant that vanishes on the family's optimal labeling),
+    // while that family's chains are left with tied min-marginals (all of them for the
+    // maximal iterative minorant), where no labeling gives the derivative.  So the
+    // family X of the last half-step contributes the one-hot of its optimum at the dual
+    // before that half-step; the other family at the final dual.
+    const int lb_last = S >= 1 ? ((S - 1) % 2 == 0 ? 0 : 1) : -1;  // 0 rows, 1 columns, -1 none
+    auto lb_inject = [&](bool rows_family, const float* lam_k) -> int {
+        SweepArgs a = rows_family ? rows : cols;
+        a.mode = kModeFinal;
+        a.lam = const_cast<float*>(lam_k);
+        a.lam_in = lam_k;
+        a.msg = vol_at(LB.msg, 0);
+        a.minmarg = nullptr;
+        a.labels = lab;
+        a.opt = nullptr;
+        DM_HIP_TRY(launch_sweep(rows_family ? tile : tile_v, a, cost_dtype, stream), "optimum labels");
+        hipLaunchKernelGGL(lb_inject_kernel, dim3(1024), dim3(256), 0, stream, lab, s.W, s.H, s.K, p->trunc_T, grad_lb,
+                           rows_family ? 1 : 0, lbar, grad_cost, rows_family ? gwh : gwv);
+        DM_HIP_TRY(hipGetLastError(), "bound adjoint");
+        return DM_OK;
+    };
+
+    // 1. final row pass: dL/dminmarg (and the row part of dL/dLB when the rows are taken
+    //    at the final dual) -> dL/dcost, dL/d(final dual)
     {
         SweepArgs a = rows;
         a.mode = kModeFinal | kRecordFlag;
@@ -642,23 +679,13 @@ extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad
         b.mode = kModeFinal;
         b.lam0 = dual;
         b.grad_mm = grad_minmarg;
-        b.g_lb = grad_lb;
+        b.g_lb = lb_last == 0 ? 0.0 : grad_lb;
         DM_HIP_TRY(launch_adjoint(tile, b, cost_dtype, stream), "final adjoint");
     }
-    // 2. column part of dL/dLB: one-hot at the column optima of G
-    if (grad_lb != 0.0) {
-        SweepArgs a = cols;
-        a.mode = kModeFinal;
-        a.lam = const_cast<float*>(dual);
-        a.lam_in = dual;
-        a.msg = vol_at(LB.msg, 0);
-        a.minmarg = nullptr;
-        a.labels = lab;
-        a.opt = nullptr;
-        DM_HIP_TRY(launch_sweep(tile_v, a, cost_dtype, stream), "column optimum labels");
-        hipLaunchKernelGGL(lb_col_adjoint_kernel, dim3(1024), dim3(256), 0, stream, lab, s.W, s.H, s.K, p->trunc_T,
-                           grad_lb, lbar, gwv);
-        DM_HIP_TRY(hipGetLastError(), "column bound adjoint");
+    // 2. column part of dL/dLB at the final dual
+    if (grad_lb != 0.0 && lb_last != 1) {
+        st = lb_inject(false, dual);
+        if (st != DM_OK) return st;
     }
     // 3. half-steps in reverse: recompute from the checkpoint, then differentiate
     for (int k = S - 1; k >= 0; --k) {
@@ -672,6 +699,11 @@ extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad
         AdjArgs b = adj_from(h ? rows : cols, h ? gwh : gwv);
         b.lam0 = ck;
         DM_HIP_TRY(launch_adjoint(h ? tile : tile_v, b, cost_dtype, stream), "half-step adjoint");
+        // the last half-step's family enters dL/dLB at the dual before that half-step
+        if (k == S - 1 && grad_lb != 0.0) {
+            st = lb_inject(h, ck);
+            if (st != DM_OK) return st;
+        }
     }
     if (grad_w_h != nullptr && n_wh > 0)
         hipLaunchKernelGGL(edge_out_kernel, dim3(512), dim3(256), 0, stream, gwh, n_wh, accumulate, grad_w_h);

@@ -169,6 +169,7 @@ __device__ __forceinline__ void store_f32(__amdgpu_buffer_rsrc_t r, unsigned off
 // ------------------------------------------------------------------ chain walker
 template <int G, int LPL, int PF, typename TT, bool FULL, bool HAS_THETA>
 struct Walker {
+    static constexpr int ES = (int)sizeof(TT);
     // One prefetched node: raw cost words, dual, reverse message, edge weight.
     struct Node {
         RawVec<TT, LPL, FULL> th;
@@ -176,25 +177,42 @@ struct Walker {
         RawVec<float, LPL, FULL> rev;
         float w;
     };
+    // Byte offsets of the node a load stream is at.
+    struct Cursor {
+        unsigned th, f, w;
+    };
 
-    __amdgpu_buffer_rsrc_t r_theta, r_w, r_mm;
+    __amdgpu_buffer_rsrc_t r_theta, r_w, r_mm, r_lab;
     // buffers of the current pass: dual loads / stores, reverse-message loads, message stores
     __amdgpu_buffer_rsrc_t r_lam_ld, r_lam_st, r_msg_ld, r_msg_st;
     unsigned vol_bytes;
-    int* __restrict__ labels;
-    long long base_px, wbase, node_px, w_node;
+    // Offsets (bytes) of this lane's first label at node 0, of the edge (0, 1) and of the
+    // node's label slot, and their per-node steps.  Lanes whose chain does not exist sit
+    // at kOOB with step 0, so every access of theirs is out of range.
+    unsigned th0, f0, w0, lab0, th_step, f_step, w_step, lab_step;
     int sub, n, K, T;
-    float sign, inv_n;
+    float sign, inv_n, Tf;
     bool ok;          // this group's chain exists
-    bool lv[LPL];     // label valid
+    bool lv[LPL];     // label exists (and the chain exists)
     int dt_steps;     // lanes the distance transform must reach across
+    float dl, dr;     // distance-transform lane shifts; lanes without a source keep kBig
 
     __device__ Walker(SweepArgs args, int chain, int sub_)
-        : labels(args.labels), node_px(args.node_px), w_node(args.w_node), sub(sub_), n(args.n), K(args.K),
-          T(args.T), sign(args.sign), inv_n(args.inv_n) {
+        : sub(sub_), n(args.n), K(args.K), T(args.T), sign(args.sign), inv_n(args.inv_n) {
         ok = chain < args.n_chains;
-        base_px = (long long)(ok ? chain : 0) * args.chain_px;
-        wbase = (long long)(ok ? chain : 0) * args.w_chain;
+        Tf = (float)args.T;
+        const unsigned long long cpx = (unsigned long long)(ok ? chain : 0) * (unsigned long long)args.chain_px;
+        const unsigned long long e0 = cpx * (unsigned long long)args.K + (unsigned long long)(sub * LPL);
+        const unsigned long long nk = (unsigned long long)args.node_px * (unsigned long long)args.K;
+        f0 = ok ? (unsigned)(e0 * 4ull) : kOOB;
+        th0 = ok ? (unsigned)(e0 * (unsigned long long)ES) : kOOB;
+        f_step = ok ? (unsigned)(nk * 4ull) : 0u;
+        th_step = ok ? (unsigned)(nk * (unsigned long long)ES) : 0u;
+        w0 = ok ? (unsigned)((unsigned long long)chain * (unsigned long long)args.w_chain * 4ull) : kOOB;
+        w_step = ok ? (unsigned)(args.w_node * 4) : 0u;
+        const bool lab_lane = ok && sub == 0;
+        lab0 = lab_lane ? (unsigned)(cpx * 4ull) : kOOB;
+        lab_step = lab_lane ? (unsigned)(args.node_px * 4) : 0u;
         r_theta = make_rsrc(args.theta, HAS_THETA ? args.vol_bytes_theta : 0u);
         vol_bytes = args.vol_bytes_f32;
         r_lam_ld = make_rsrc(args.lam_in != nullptr ? args.lam_in : args.lam, vol_bytes);
@@ -202,48 +220,96 @@ struct Walker {
         r_msg_ld = make_rsrc(args.msg, vol_bytes);
         r_msg_st = r_msg_ld;
         r_w = make_rsrc(args.w, args.w_bytes);
-        r_mm = make_rsrc(args.minmarg, args.minmarg != nullptr ? args.vol_bytes_f32 : 0u);
+        r_mm = make_rsrc(args.minmarg, args.minmarg != nullptr ? vol_bytes : 0u);
+        r_lab = make_rsrc(args.labels, args.labels != nullptr ? vol_bytes / (unsigned)args.K : 0u);
 #pragma unroll
-        for (int i = 0; i < LPL; ++i) lv[i] = FULL ? true : (sub * LPL + i < K);
+        for (int i = 0; i < LPL; ++i) lv[i] = FULL ? true : (ok && sub * LPL + i < K);
         const int need = (args.T - 1 + LPL - 1) / LPL;
         dt_steps = need < G - 1 ? need : G - 1;
     }
 
-    // Element index of this lane's first label at node j.
-    __device__ __forceinline__ long long elem(int j) const { return (base_px + (long long)j * node_px) * K + sub * LPL; }
-
-    // Byte offsets (element size ES) of this lane's labels at node j; out of range when
-    // `valid` is false or the label does not exist.
-    template <int ES>
-    __device__ __forceinline__ void offsets(int j, bool valid, unsigned& off0, unsigned (&offs)[LPL]) const {
-        const unsigned base = (unsigned)(elem(j) * ES);
-        off0 = (valid && ok) ? base : kOOB;
+    // Per-label byte offsets of an access at `off` (element size E).  A full tile uses
+    // `off` alone (vector access); otherwise labels that do not exist are out of range.
+    template <int E>
+    __device__ __forceinline__ void label_offsets(unsigned off, unsigned (&o)[LPL]) const {
 #pragma unroll
-        for (int i = 0; i < LPL; ++i) offs[i] = (valid && ok && lv[i]) ? base + (unsigned)(i * ES) : kOOB;
+        for (int i = 0; i < LPL; ++i) o[i] = (FULL || lv[i]) ? off + (unsigned)(i * E) : kOOB;
     }
 
-    // Loads node j of a pass in direction FWD (j is clamped by the caller to [0, n-1]).
+    __device__ __forceinline__ Cursor cursor_at(bool fwd) const {
+        const unsigned j = fwd ? 0u : (unsigned)(n - 1);
+        // edge of node j in a pass: (j, j+1) forward, (j-1, j) backward
+        const unsigned e = fwd ? 0u : (unsigned)(n - 2);
+        return Cursor{th0 + j * th_step, f0 + j * f_step, w0 + e * w_step};
+    }
+
+    // Loads the node at the cursor and moves the cursor one node in direction FWD.
+    // Beyond the chain end the loads read other data or zeros; such nodes are never used.
     template <bool FWD, bool WANT_REV>
-    __device__ __forceinline__ void load(Node& nd, int j) const {
-        unsigned o0, os[LPL];
-        if constexpr (HAS_THETA) {
-            offsets<(int)sizeof(TT)>(j, true, o0, os);
-            nd.th.load(r_theta, o0, os);
-        }
-        offsets<4>(j, true, o0, os);
-        nd.lam.load(r_lam_ld, o0, os);
-        const bool has = FWD ? (j < n - 1) : (j > 0);
+    __device__ __forceinline__ void load(Node& nd, Cursor& c) const {
+        // Issue order: edge weight (used last), reverse message, dual, cost (used first),
+        // so one wait for the cost covers the node's other loads.
+        unsigned os[LPL];
+        nd.w = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r_w, (int)c.w, 0, 0));
         if constexpr (WANT_REV) {
-            offsets<4>(FWD ? j : j - 1, has, o0, os);
-            nd.rev.load(r_msg_ld, o0, os);
+            // message slot of the edge toward the unvisited side: j forward, j-1 backward
+            const unsigned ro = FWD ? c.f : c.f - f_step;
+            label_offsets<4>(ro, os);
+            nd.rev.load(r_msg_ld, ro, os);
         }
-        const long long ei = wbase + (long long)(FWD ? j : j - 1) * w_node;
-        const unsigned wo = (has && ok) ? (unsigned)(ei * 4) : kOOB;
-        nd.w = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r_w, (int)wo, 0, 0));
+        label_offsets<4>(c.f, os);
+        nd.lam.load(r_lam_ld, c.f, os);
+        if constexpr (HAS_THETA) {
+            label_offsets<ES>(c.th, os);
+            nd.th.load(r_theta, c.th, os);
+        }
+        if constexpr (FWD) {
+            c.th += th_step; c.f += f_step; c.w += w_step;
+        } else {
+            c.th -= th_step; c.f -= f_step; c.w -= w_step;
+        }
     }
 
-    // Truncated-linear message of v (normalised by its minimum vmin), into out.
-    __device__ __forceinline__ void message(const float (&v)[LPL], float vmin, float wt, float (&out)[LPL]) const {
+    // Value arriving from the left / right neighbour lane of the group (kBig at the
+    // group's first / last lane).
+    __device__ __forceinline__ float from_left(float x) {
+        if constexpr (G == 64) {
+            dl = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, dl), __builtin_bit_cast(int, x),
+                                                                       kWaveShr1, 0xF, 0xF, false));
+            return dl;
+        } else if constexpr (G == 16) {
+            dl = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, dl), __builtin_bit_cast(int, x),
+                                                                       kRowShr1, 0xF, 0xF, false));
+            return dl;
+        } else {
+            const float c = dpp_fill<kWaveShr1>(x, kBig);
+            return sub == 0 ? kBig : c;
+        }
+    }
+    __device__ __forceinline__ float from_right(float x) {
+        if constexpr (G == 64) {
+            dr = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, dr), __builtin_bit_cast(int, x),
+                                                                       kWaveShl1, 0xF, 0xF, false));
+            return dr;
+        } else if constexpr (G == 16) {
+            dr = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, dr), __builtin_bit_cast(int, x),
+                                                                       kRowShl1, 0xF, 0xF, false));
+            return dr;
+        } else {
+            const float c = dpp_fill<kWaveShl1>(x, kBig);
+            return sub == G - 1 ? kBig : c;
+        }
+    }
+
+    // Truncated-linear message of v (normalised by its minimum vmin), into out:
+    // min over labels k' of v[k'] + wt*min(|k - k'|, T), minus vmin.  DT1: the
+    // distance transform reaches exactly one lane across (dt_steps == 1).
+    template <bool DT1>
+    __device__ __forceinline__ void message(const float (&v)[LPL], float vmin, float wt, float (&out)[LPL]) {
+        float wk[LPL + 1];
+        wk[0] = 0.0f;
+#pragma unroll
+        for (int i = 1; i <= LPL; ++i) wk[i] = i == 1 ? wt : wt * (float)i;
         float f[LPL], b[LPL];
         f[0] = v[0];
 #pragma unroll
@@ -251,22 +317,31 @@ struct Walker {
         b[LPL - 1] = v[LPL - 1];
 #pragma unroll
         for (int i = LPL - 2; i >= 0; --i) b[i] = fminf(v[i], b[i + 1] + wt);
-        for (int s = 0; s < dt_steps; ++s) {
-            float cl = dpp_fill<kWaveShr1>(f[LPL - 1], kBig);
-            float cr = dpp_fill<kWaveShl1>(b[0], kBig);
-            if (sub == 0) cl = kBig;
-            if (sub == G - 1) cr = kBig;
+        const float cap = vmin + wt * Tf;
+        if constexpr (DT1) {
+            const float cl = from_left(f[LPL - 1]);
+            const float cr = from_right(b[0]);
 #pragma unroll
             for (int i = 0; i < LPL; ++i) {
-                f[i] = fminf(f[i], cl + wt * (float)(i + 1));
-                b[i] = fminf(b[i], cr + wt * (float)(LPL - i));
+                const float e = fminf(fminf(f[i], b[i]), cap);
+                const float d = fminf(e, fminf(cl + wk[i + 1], cr + wk[LPL - i])) - vmin;
+                out[i] = (FULL || lv[i]) ? d : 0.0f;
             }
-        }
-        const float cap = vmin + wt * (float)T;
+        } else {
+            for (int s = 0; s < dt_steps; ++s) {
+                const float cl = from_left(f[LPL - 1]);
+                const float cr = from_right(b[0]);
 #pragma unroll
-        for (int i = 0; i < LPL; ++i) {
-            float d = fminf(fminf(f[i], b[i]), cap) - vmin;
-            out[i] = lv[i] ? d : 0.0f;
+                for (int i = 0; i < LPL; ++i) {
+                    f[i] = fminf(f[i], cl + wk[i + 1]);
+                    b[i] = fminf(b[i], cr + wk[LPL - i]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < LPL; ++i) {
+                const float d = fminf(fminf(f[i], b[i]), cap) - vmin;
+                out[i] = (FULL || lv[i]) ? d : 0.0f;
+            }
         }
     }
 
@@ -280,48 +355,65 @@ struct Walker {
     // One directional pass.  KIND: 0 = backward message pass (R0), 1 = iterative update,
     // 2 = naive update, 3 = final min-marginals.  Adds the normalisation constants of a
     // message pass (= chain optimum) to `opt`.
-    template <bool FWD, int KIND>
+    template <bool FWD, int KIND, bool DT1>
     __device__ void pass(float gamma, bool store_msg, double& opt) {
         constexpr bool WANT_REV = KIND != 0;
         float carry[LPL];
 #pragma unroll
         for (int i = 0; i < LPL; ++i) carry[i] = 0.0f;
+        dl = kBig;
+        dr = kBig;
+        const __amdgpu_buffer_rsrc_t msg_st = store_msg ? r_msg_st : make_rsrc(nullptr, 0u);
+        Cursor lc = cursor_at(FWD);
+        unsigned sf = lc.f;                                           // store cursor (dual, messages)
+        unsigned sl = lab0 + (FWD ? 0u : (unsigned)(n - 1)) * lab_step;  // label slot
         Node ring[PF];
+        // Issued in slot order (the scheduler may not reorder them): the steady-state loop
+        // waits for slot q's loads assuming the later slots' loads were issued after them.
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
-            const int t = q < n ? q : n - 1;
-            load<FWD, WANT_REV>(ring[q], FWD ? t : n - 1 - t);
+            load<FWD, WANT_REV>(ring[q], lc);
+            __builtin_amdgcn_sched_barrier(0);
         }
         int t0 = 0;
-        // Steady state: PF nodes per iteration, loads for node t+PF issued before node t
-        // is processed (clamped to the last node near the end: a redundant reload).
-        for (; t0 + PF <= n; t0 += PF) {
+        // Steady state: every node here has a successor in the walking direction.  Node
+        // t is processed, then its ring slot is refilled with node t + PF.
+        for (; t0 + PF < n; t0 += PF) {
 #pragma unroll
             for (int q = 0; q < PF; ++q) {
-                const int t = t0 + q;
-                Node cur = ring[q];
-                const int tn = (t + PF < n) ? t + PF : n - 1;
-                load<FWD, WANT_REV>(ring[q], FWD ? tn : n - 1 - tn);
-                step<FWD, KIND>(cur, FWD ? t : n - 1 - t, carry, gamma, store_msg, opt);
+                step<FWD, KIND, false, DT1>(ring[q], true, carry, gamma, msg_st, opt, sf, sl);
+                load<FWD, WANT_REV>(ring[q], lc);
             }
         }
-        // Tail: fewer than PF nodes left, already in the ring.
+        // Tail: the last 1..PF nodes, already in the ring; the chain's last node has no
+        // successor.
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
             const int t = t0 + q;
-            if (t < n) step<FWD, KIND>(ring[q], FWD ? t : n - 1 - t, carry, gamma, store_msg, opt);
+            if (t < n) step<FWD, KIND, true, DT1>(ring[q], t < n - 1, carry, gamma, msg_st, opt, sf, sl);
         }
     }
 
+    // A pass with the distance-transform variant this walker's truncation needs.
     template <bool FWD, int KIND>
-    __device__ __forceinline__ void step(const Node& nd, int j, float (&carry)[LPL], float gamma, bool store_msg,
-                                         double& opt) {
+    __device__ __forceinline__ void run_pass(float gamma, bool store_msg, double& opt) {
+        if (dt_steps == 1)
+            pass<FWD, KIND, true>(gamma, store_msg, opt);
+        else
+            pass<FWD, KIND, false>(gamma, store_msg, opt);
+    }
+
+    template <bool FWD, int KIND, bool TAIL, bool DT1>
+    __device__ __forceinline__ void step(const Node& nd, bool has_next, float (&carry)[LPL], float gamma,
+                                         __amdgpu_buffer_rsrc_t msg_st, double& opt, unsigned& sf, unsigned& sl) {
+        if constexpr (!TAIL) has_next = true;
+        float vmin = 0.0f;
         float r[LPL], lamv[LPL];
 #pragma unroll
         for (int i = 0; i < LPL; ++i) {
             lamv[i] = nd.lam.get(i);
             const float x = HAS_THETA ? nd.th.get(i) - lamv[i] : lamv[i];
-            r[i] = lv[i] ? x : kBig;
+            r[i] = (FULL || lv[i]) ? x : kBig;
         }
         float v[LPL];
         if constexpr (KIND == 0) {
@@ -330,51 +422,69 @@ struct Walker {
         } else {
             float m[LPL];
 #pragma unroll
-            for (int i = 0; i < LPL; ++i) m[i] = r[i] + carry[i] + nd.rev.get(i);
-            const float mmin = group_min<G>(lane_min(m));
+            for (int i = 0; i < LPL; ++i) {
+                v[i] = r[i] + carry[i];
+                const float rv = nd.rev.get(i);
+                m[i] = v[i] + ((TAIL && !has_next) ? 0.0f : rv);  // no message beyond the chain end
+            }
+            // The minimum of the message input is reduced together with mmin.  Naive
+            // update and final pass: v = r + carry does not depend on mmin.  Iterative
+            // update: v = rc - gamma*(m - mmin) with rc = r + carry, so
+            // min v = min(rc - gamma*m) + gamma*mmin, again a reduction independent of mmin.
+            float mmin = lane_min(m), bmin;
+            if constexpr (KIND == 1) {
+                float u[LPL];
+#pragma unroll
+                for (int i = 0; i < LPL; ++i) u[i] = (FULL || lv[i]) ? v[i] - gamma * m[i] : kBig;
+                bmin = lane_min(u);
+            } else {
+                bmin = lane_min(v);
+            }
+            group_min2<G>(mmin, bmin);
+            vmin = KIND == 1 ? bmin + gamma * mmin : bmin;
             if constexpr (KIND == 1 || KIND == 2) {
                 float nl[LPL];
 #pragma unroll
                 for (int i = 0; i < LPL; ++i) {
                     float d = (KIND == 1 ? gamma : inv_n) * (m[i] - mmin);
-                    d = lv[i] ? d : 0.0f;
-                    if (KIND == 1) r[i] -= d;
+                    d = (FULL || lv[i]) ? d : 0.0f;
+                    if (KIND == 1) v[i] -= d;
                     nl[i] = lamv[i] + sign * d;
                 }
-                unsigned o0, os[LPL];
-                offsets<4>(j, true, o0, os);
-                store_f32<LPL, FULL>(r_lam_st, o0, os, nl);
+                unsigned os[LPL];
+                label_offsets<4>(sf, os);
+                store_f32<LPL, FULL>(r_lam_st, sf, os, nl);
             } else {  // KIND == 3: normalized min-marginals and argmin
                 float mm[LPL];
                 int first = 0x7fffffff;
 #pragma unroll
                 for (int i = LPL - 1; i >= 0; --i) {
                     mm[i] = m[i] - mmin;
-                    if (lv[i] && m[i] == mmin) first = sub * LPL + i;
+                    if ((FULL || lv[i]) && m[i] == mmin) first = sub * LPL + i;
                 }
                 int lab = group_min_i<G>(first);
                 lab = lab < K ? lab : K - 1;  // defensive: a label always exists for finite costs
-                unsigned o0, os[LPL];
-                offsets<4>(j, true, o0, os);
-                store_f32<LPL, FULL>(r_mm, o0, os, mm);
-                if (ok && sub == 0) labels[base_px + (long long)j * node_px] = lab;
+                unsigned os[LPL];
+                label_offsets<4>(sf, os);
+                store_f32<LPL, FULL>(r_mm, sf, os, mm);
+                __builtin_amdgcn_raw_buffer_store_b32((uint32_t)lab, r_lab, (int)sl, 0, 0);
+                sl = FWD ? sl + lab_step : sl - lab_step;
             }
-#pragma unroll
-            for (int i = 0; i < LPL; ++i) v[i] = carry[i] + r[i];
         }
-        const bool has_next = FWD ? (j < n - 1) : (j > 0);
         if (KIND == 0 || has_next) {
-            const float vmin = group_min<G>(lane_min(v));
+            if constexpr (KIND == 0) vmin = group_min<G>(lane_min(v));
             if constexpr (KIND == 0) opt += (double)vmin;
             if (has_next) {
-                message(v, vmin, nd.w, carry);
-                if (store_msg) {
-                    unsigned o0, os[LPL];
-                    offsets<4>(FWD ? j : j - 1, true, o0, os);
-                    store_f32<LPL, FULL>(r_msg_st, o0, os, carry);
-                }
+                message<DT1>(v, vmin, nd.w, carry);
+                // slot of edge (j, j+1) / (j-1, j); a pass that keeps no messages stores
+                // through an empty descriptor (dropped) rather than branching per node
+                const unsigned mo = FWD ? sf : sf - f_step;
+                unsigned os[LPL];
+                label_offsets<4>(mo, os);
+                store_f32<LPL, FULL>(msg_st, mo, os, carry);
             }
         }
+        sf = FWD ? sf + f_step : sf - f_step;
     }
 };
 
@@ -392,7 +502,7 @@ __device__ __forceinline__ void run_chain(const SweepArgs& a, int chain, int sub
         // R0 and the first update pass read lam_in; update passes write lam
         const __amdgpu_buffer_rsrc_t lam_out = wk.r_lam_st;
         wk.r_lam_st = make_rsrc(nullptr, 0u);
-        wk.template pass<false, 0>(0.0f, true, opt);
+        wk.template run_pass<false, 0>(0.0f, true, opt);
         wk.r_lam_st = lam_out;
         if (a.mode == kModeIterative) {
             for (int s = 0; s < a.n_pass; ++s) {
@@ -404,23 +514,23 @@ __device__ __forceinline__ void run_chain(const SweepArgs& a, int chain, int sub
                 for (int i = 1; i < 8; ++i)
                     if (s == i) g = a.gamma[i];
                 if ((s & 1) == 0)
-                    wk.template pass<true, 1>(g, !last, opt);
+                    wk.template run_pass<true, 1>(g, !last, opt);
                 else
-                    wk.template pass<false, 1>(g, !last, opt);
+                    wk.template run_pass<false, 1>(g, !last, opt);
             }
         } else {
-            wk.template pass<true, 2>(0.0f, false, opt);
+            wk.template run_pass<true, 2>(0.0f, false, opt);
         }
     } else if constexpr (MG == kGroupFinal) {
-        wk.template pass<false, 0>(0.0f, true, opt);
-        wk.template pass<true, 3>(0.0f, false, opt);
+        wk.template run_pass<false, 0>(0.0f, true, opt);
+        wk.template run_pass<true, 3>(0.0f, false, opt);
     } else if constexpr (MG == kGroupOptimum) {
-        wk.template pass<false, 0>(0.0f, false, opt);
+        wk.template run_pass<false, 0>(0.0f, false, opt);
     } else {  // kGroupRecord: recompute a half-step keeping every pass's messages and duals
         const unsigned vb = wk.vol_bytes;
         wk.r_lam_st = make_rsrc(nullptr, 0u);
         wk.r_msg_st = make_rsrc(a.rec_msg[0], vb);
-        wk.template pass<false, 0>(0.0f, true, opt);
+        wk.template run_pass<false, 0>(0.0f, true, opt);
         const int P = a.mode == kModeIterative ? a.n_pass : 1;
         for (int s = 0; s < P; ++s) {
             const float* ld = a.lam_in;
@@ -447,11 +557,11 @@ __device__ __forceinline__ void run_chain(const SweepArgs& a, int chain, int sub
             for (int i = 1; i < 8; ++i)
                 if (s == i) g = a.gamma[i];
             if (a.mode != kModeIterative)
-                wk.template pass<true, 2>(0.0f, true, opt);
+                wk.template run_pass<true, 2>(0.0f, true, opt);
             else if ((s & 1) == 0)
-                wk.template pass<true, 1>(g, true, opt);
+                wk.template run_pass<true, 1>(g, true, opt);
             else
-                wk.template pass<false, 1>(g, true, opt);
+                wk.template run_pass<false, 1>(g, true, opt);
         }
     }
     if (a.opt != nullptr && wk.ok && sub == 0) a.opt[chain] = opt;

@@ -39,6 +39,8 @@ constexpr int kRowHalfMirror = 0x141;
 constexpr int kRowMirror = 0x140;
 constexpr int kWaveShr1 = 0x138;     // lane i <- lane i-1
 constexpr int kWaveShl1 = 0x130;     // lane i <- lane i+1
+constexpr int kRowShr1 = 0x111;      // lane i <- lane i-1 within a row of 16
+constexpr int kRowShl1 = 0x101;      // lane i <- lane i+1 within a row of 16
 
 // An opaque copy: keeps the compiler from treating the two operands of a permlane swap
 // as the same value (it would otherwise fold min(swap.first, swap.second)).
@@ -82,6 +84,42 @@ __device__ __forceinline__ float group_min(float x) {
     if constexpr (G >= 64) x = swap32_min(x);
     return x;
 }
+// Two independent all-reduce minima over groups of G lanes (a and b each get their
+// group's minimum in every lane).  For G = 32 and 64 the cross-row steps carry a and b
+// in the two operands of one permlane swap, so the pair costs little more than one.
+template <int G>
+__device__ __forceinline__ void group_min2(float& a, float& b) {
+    if constexpr (G == 64 || G == 32) {
+        a = group_min<16>(a);
+        b = group_min<16>(b);
+        const uint32_t ua = __builtin_bit_cast(uint32_t, a), ub = __builtin_bit_cast(uint32_t, b);
+        if constexpr (G == 64) {
+            // rows 2,3 of a <-> rows 0,1 of b: c = a's minimum over rows {0,2}, {1,3} in
+            // rows 0, 1 and b's in rows 2, 3
+            auto p = __builtin_amdgcn_permlane32_swap(ua, ub, false, false);
+            const float c = swap16_min(fminf(__builtin_bit_cast(float, (uint32_t)p[0]),
+                                             __builtin_bit_cast(float, (uint32_t)p[1])));
+            // c: a's minimum in lanes 0-31, b's in lanes 32-63; one more swap spreads both
+            const uint32_t uc = __builtin_bit_cast(uint32_t, c);
+            auto q = __builtin_amdgcn_permlane32_swap(uc, opaque_copy(uc), false, false);
+            a = __builtin_bit_cast(float, (uint32_t)q[0]);
+            b = __builtin_bit_cast(float, (uint32_t)q[1]);
+        } else {
+            // rows 1,3 of a <-> rows 0,2 of b: c = a's group minimum in rows 0, 2 and
+            // b's in rows 1, 3
+            auto p = __builtin_amdgcn_permlane16_swap(ua, ub, false, false);
+            const uint32_t uc = __builtin_bit_cast(uint32_t, fminf(__builtin_bit_cast(float, (uint32_t)p[0]),
+                                                                   __builtin_bit_cast(float, (uint32_t)p[1])));
+            auto q = __builtin_amdgcn_permlane16_swap(uc, opaque_copy(uc), false, false);
+            a = __builtin_bit_cast(float, (uint32_t)q[0]);
+            b = __builtin_bit_cast(float, (uint32_t)q[1]);
+        }
+    } else {
+        a = group_min<G>(a);
+        b = group_min<G>(b);
+    }
+}
+
 template <int G>
 __device__ __forceinline__ int group_min_i(int x) {
     if constexpr (G >= 2) x = min(x, dpp_i<kQuadXor1>(x));

@@ -82,6 +82,8 @@ def test_null_and_shape_and_workspace_errors():
     assert _solve(L.DmShape(16, 8, 8), p, dual=0) == -1
     assert _solve(L.DmShape(16, 0, 8), p) == -2
     assert _solve(L.DmShape(16, 8, 300), p) == -2
+    assert _solve(L.DmShape(16384, 16384, 4), p) == -2  # FP32 volume beyond 32-bit offsets
+    assert "offset range" in L.lib().dm_last_error_message().decode()
     assert _solve(L.DmShape(16, 8, 8), p, dtype=7) == -4
     assert _solve(L.DmShape(16, 8, 8), p, ws=ctypes.c_void_p(4096), ws_bytes=16) == -5
 
