@@ -19,12 +19,17 @@
 // v(src(b)) (window source or, for the truncation term, the argmin of v) and to w;
 // the subtraction of vmin sends minus the total to argmin v.  Sources are found in
 // LDS (the group's v), the gather back is a fixed-order sum (no atomics, bitwise
-// deterministic).
+// deterministic).  The kernel's workgroup is one wave, so LDS exchanges need only the
+// LDS wait, not a workgroup barrier.
 #pragma once
 
 #include "dmm_kernels.h"
 
 namespace dm {
+
+using lds_f32 = __attribute__((address_space(3))) float;
+using lds_i32 = __attribute__((address_space(3))) int;
+using gbl_f64 = __attribute__((address_space(1))) double;
 
 struct AdjArgs {
     const void* theta;        // horizontal family: cost [H][W][K]; nullptr for the vertical family
@@ -65,14 +70,60 @@ __device__ __forceinline__ float group_sum(float x) {
     return x;
 }
 
+// Two / three independent group sums (every lane of a group gets its group's sums).
+// For G = 64 the cross-row steps carry two values in the operands of one permlane swap.
+template <int G>
+__device__ __forceinline__ void group_sum2(float& a, float& b) {
+    if constexpr (G == 64) {
+        a = group_sum<16>(a);
+        b = group_sum<16>(b);
+        auto p = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b), false,
+                                                  false);
+        // lanes 0-31: a over rows {0,2}, {1,3}; lanes 32-63: b likewise; then rows r <-> r^1
+        const uint32_t ux = __builtin_bit_cast(uint32_t, __builtin_bit_cast(float, (uint32_t)p[0]) +
+                                                             __builtin_bit_cast(float, (uint32_t)p[1]));
+        auto h = __builtin_amdgcn_permlane16_swap(ux, opaque_copy(ux), false, false);
+        const float c = __builtin_bit_cast(float, (uint32_t)h[0]) + __builtin_bit_cast(float, (uint32_t)h[1]);
+        const uint32_t uc = __builtin_bit_cast(uint32_t, c);
+        auto q = __builtin_amdgcn_permlane32_swap(uc, opaque_copy(uc), false, false);
+        a = __builtin_bit_cast(float, (uint32_t)q[0]);
+        b = __builtin_bit_cast(float, (uint32_t)q[1]);
+    } else {
+        a = group_sum<G>(a);
+        b = group_sum<G>(b);
+    }
+}
+
+// Lowest label of the group whose value equals the group minimum mn (attained by some
+// existing label).  A whole-wave group uses a ballot instead of an integer reduction.
+template <int G, int LPL, bool FULL>
+__device__ __forceinline__ int group_argmin_eq(const float (&x)[LPL], float mn, const bool (&lv)[LPL], int sub) {
+    if constexpr (G == 64) {
+        int first = LPL;
+#pragma unroll
+        for (int i = LPL - 1; i >= 0; --i)
+            if ((FULL || lv[i]) && x[i] == mn) first = i;
+        const unsigned long long mask = __builtin_amdgcn_ballot_w64(first < LPL);
+        const int lane = (int)__builtin_ctzll(mask);
+        return lane * LPL + __builtin_amdgcn_readlane(first, lane);
+    } else {
+        int first = 0x7fffffff;
+#pragma unroll
+        for (int i = LPL - 1; i >= 0; --i)
+            if ((FULL || lv[i]) && x[i] == mn) first = sub * LPL + i;
+        return group_min_i<G>(first);
+    }
+}
+
 // Adjoint pass kinds: update pass of the iterative minorant, naive update pass, final
 // min-marginal pass, backward message pass (R0).
 enum AdjKind : int { kAdjIter = 1, kAdjNaive = 2, kAdjFinal = 3, kAdjR0 = 0 };
 
 template <int G, int LPL, int PF, typename TT, bool FULL, bool HAS_THETA>
 struct AdjWalker {
-    static constexpr int CPW = 64 / G;
+    static constexpr int ES = (int)sizeof(TT);
     static constexpr int GK = G * LPL;
+    static constexpr int kFar = 1 << 20;  // distance of a missing neighbour's candidate
 
     struct Node {
         RawVec<TT, LPL, FULL> th;
@@ -80,82 +131,111 @@ struct AdjWalker {
         RawVec<float, LPL, FULL> gx;  // dL/dcost (first / R0 passes) or dL/dminmarg (final pass)
         float w;
     };
+    struct Cursor {
+        unsigned th, f, w;
+    };
 
     __amdgpu_buffer_rsrc_t r_theta, r_w;
     __amdgpu_buffer_rsrc_t r_lam, r_cmsg, r_rmsg, r_abar, r_bin, r_bout, r_gth, r_gmm;
-    float* __restrict__ lbar;
-    float* __restrict__ grad_theta;
-    double* __restrict__ grad_w;
-    const float* __restrict__ grad_mm;
-    long long base_px, wbase, node_px, w_node;
+    gbl_f64* grad_w;
+    // Offsets as in the forward walker: node 0 of this lane's chain and label, edge (0, 1),
+    // per-node steps; missing chains sit at kOOB with step 0.
+    unsigned th0, f0, w0, th_step, f_step, w_step;
     int sub, grp, n, K, T;
-    float sign, inv_n;
-    unsigned vb;
+    float sign, inv_n, Tf;
     bool ok;
     bool lv[LPL];
-    float* s_v;    // LDS: this group's v
-    float* s_cb;   // LDS: this group's message adjoint
-    int* s_src;    // LDS: source label of each message entry (-1: truncation term)
+    int dt_steps;
+    float g_lb_f = 0.0f;
+    // LDS (typed in the local address space: a generic pointer would make every access a
+    // flat instruction, which waits on the vector-memory counter too)
+    lds_f32* s_v;    // this group's v
+    lds_f32* s_cb;   // this group's message adjoint
+    lds_i32* s_src;  // source label of each message entry (-1: truncation term)
 
-    __device__ AdjWalker(const AdjArgs& a, int chain, int sub_, int grp_, float* sv, float* scb, int* ssrc)
-        : lbar(a.lbar), grad_theta(a.grad_theta), grad_w(a.grad_w), grad_mm(a.grad_mm), node_px(a.node_px),
-          w_node(a.w_node), sub(sub_), grp(grp_), n(a.n), K(a.K), T(a.T), sign(a.sign), inv_n(a.inv_n),
-          vb(a.vol_bytes_f32) {
+    __device__ __forceinline__ AdjWalker(const AdjArgs& a, int chain, int sub_, int grp_, float* sv, float* scb, int* ssrc)
+        : grad_w((gbl_f64*)a.grad_w), sub(sub_), grp(grp_), n(a.n), K(a.K), T(a.T), sign(a.sign), inv_n(a.inv_n) {
         ok = chain < a.n_chains;
-        base_px = (long long)(ok ? chain : 0) * a.chain_px;
-        wbase = (long long)(ok ? chain : 0) * a.w_chain;
+        Tf = (float)a.T;
+        const unsigned long long cpx = (unsigned long long)(ok ? chain : 0) * (unsigned long long)a.chain_px;
+        const unsigned long long e0 = cpx * (unsigned long long)a.K + (unsigned long long)(sub * LPL);
+        const unsigned long long nk = (unsigned long long)a.node_px * (unsigned long long)a.K;
+        f0 = ok ? (unsigned)(e0 * 4ull) : kOOB;
+        th0 = ok ? (unsigned)(e0 * (unsigned long long)ES) : kOOB;
+        f_step = ok ? (unsigned)(nk * 4ull) : 0u;
+        th_step = ok ? (unsigned)(nk * (unsigned long long)ES) : 0u;
+        w0 = ok ? (unsigned)((unsigned long long)chain * (unsigned long long)a.w_chain * 4ull) : kOOB;
+        w_step = ok ? (unsigned)(a.w_node * 4) : 0u;
+        const unsigned vb = a.vol_bytes_f32;
         r_theta = make_rsrc(a.theta, HAS_THETA ? a.vol_bytes_theta : 0u);
         r_w = make_rsrc(a.w, a.w_bytes);
         r_abar = make_rsrc(a.lbar, vb);
         r_gth = make_rsrc(a.grad_theta, a.grad_theta != nullptr ? vb : 0u);
         r_gmm = make_rsrc(a.grad_mm, a.grad_mm != nullptr ? vb : 0u);
 #pragma unroll
-        for (int i = 0; i < LPL; ++i) lv[i] = FULL ? true : (sub * LPL + i < K);
-        s_v = sv + grp * GK;
-        s_cb = scb + grp * GK;
-        s_src = ssrc + grp * GK;
+        for (int i = 0; i < LPL; ++i) lv[i] = FULL ? true : (ok && sub * LPL + i < K);
+        const int need = (a.T - 1 + LPL - 1) / LPL;
+        dt_steps = need < G - 1 ? need : G - 1;
+        s_v = (lds_f32*)sv + grp * GK;
+        s_cb = (lds_f32*)scb + grp * GK;
+        s_src = (lds_i32*)ssrc + grp * GK;
     }
 
-    __device__ __forceinline__ long long elem(int j) const { return (base_px + (long long)j * node_px) * K + sub * LPL; }
+    // dL/dw of an edge += x (lane 0 of the group).  A returning read-modify-write would
+    // make the node wait for all loads in flight (the wait counter is in order); a
+    // no-return atomic does not.  Each edge belongs to one chain, so its updates come
+    // from one wave in program order (and from launches in stream order): the summation
+    // order is fixed and the result deterministic.
+    __device__ __forceinline__ void add_edge_grad(unsigned w_off, float x) const {
+        __hip_atomic_fetch_add(grad_w + (w_off >> 2), (double)x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 
-    template <int ES>
-    __device__ __forceinline__ void offsets(int j, bool valid, unsigned& off0, unsigned (&offs)[LPL]) const {
-        const unsigned base = (unsigned)(elem(j) * ES);
-        off0 = (valid && ok) ? base : kOOB;
+    template <int E>
+    __device__ __forceinline__ void label_offsets(unsigned off, unsigned (&o)[LPL]) const {
 #pragma unroll
-        for (int i = 0; i < LPL; ++i) offs[i] = (valid && ok && lv[i]) ? base + (unsigned)(i * ES) : kOOB;
+        for (int i = 0; i < LPL; ++i) o[i] = (FULL || lv[i]) ? off + (unsigned)(i * E) : kOOB;
     }
 
-    // FWD: the direction of the forward pass being differentiated (the adjoint walks the
-    // other way).  The message produced at node j sits at slot j (FWD) or j-1; the carried
-    // message used at j at slot j-1 (FWD) or j; the reverse message at slot j (FWD) or j-1.
+    // Cursor at the first node the adjoint visits (the forward pass's last node).
+    __device__ __forceinline__ Cursor cursor_start(bool fwd) const {
+        const unsigned j = fwd ? (unsigned)(n - 1) : 0u;
+        const unsigned e = fwd ? (unsigned)(n - 1) : 0xFFFFFFFFu;  // edge leaving node j in the pass
+        return Cursor{th0 + j * th_step, f0 + j * f_step, w0 + e * w_step};
+    }
+    template <bool FWD>
+    __device__ __forceinline__ void advance(Cursor& c) const {
+        // the adjoint walks against the forward pass
+        if constexpr (FWD) {
+            c.th -= th_step; c.f -= f_step; c.w -= w_step;
+        } else {
+            c.th += th_step; c.f += f_step; c.w += w_step;
+        }
+    }
+
+    // Node j of a forward pass in direction FWD: the message leaving j and the reverse
+    // message read at j sit in slot j (FWD) or j-1, the carried message arriving at j in
+    // slot j-1 (FWD) or j.  Issue order: what the step uses last first.
     template <bool FWD, int KIND, bool IS_FIRST>
-    __device__ __forceinline__ void load(Node& nd, int j, bool has_bin) const {
-        unsigned o0, os[LPL];
+    __device__ __forceinline__ void load(Node& nd, Cursor& c) const {
+        unsigned os[LPL];
+        const unsigned rs = FWD ? c.f : c.f - f_step;
+        const unsigned cs = FWD ? c.f - f_step : c.f;
+        nd.w = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r_w, (int)c.w, 0, 0));
+        label_offsets<4>(rs, os);
+        nd.bin.load(r_bin, rs, os);
+        if constexpr (KIND != kAdjR0) nd.rmsg.load(r_rmsg, rs, os);
+        label_offsets<4>(c.f, os);
+        if constexpr (KIND == kAdjFinal) nd.gx.load(r_gmm, c.f, os);
+        else if constexpr (HAS_THETA && (IS_FIRST || KIND == kAdjR0)) nd.gx.load(r_gth, c.f, os);
+        if constexpr (KIND != kAdjFinal) nd.abar.load(r_abar, c.f, os);
+        nd.lam.load(r_lam, c.f, os);
+        label_offsets<4>(cs, os);
+        nd.cmsg.load(r_cmsg, cs, os);
         if constexpr (HAS_THETA) {
-            offsets<(int)sizeof(TT)>(j, true, o0, os);
-            nd.th.load(r_theta, o0, os);
+            label_offsets<ES>(c.th, os);
+            nd.th.load(r_theta, c.th, os);
         }
-        offsets<4>(j, true, o0, os);
-        nd.lam.load(r_lam, o0, os);
-        nd.abar.load(r_abar, o0, os);
-        if constexpr (KIND == kAdjFinal) nd.gx.load(r_gmm, o0, os);
-        else if constexpr (HAS_THETA && (IS_FIRST || KIND == kAdjR0)) nd.gx.load(r_gth, o0, os);
-        const bool out = FWD ? (j < n - 1) : (j > 0);  // a message leaves node j
-        const int out_slot = FWD ? j : j - 1;
-        const bool has_c = FWD ? (j > 0) : (j < n - 1);
-        offsets<4>(FWD ? j - 1 : j, has_c, o0, os);
-        nd.cmsg.load(r_cmsg, o0, os);
-        if constexpr (KIND != kAdjR0) {
-            const bool has_r = FWD ? (j < n - 1) : (j > 0);
-            offsets<4>(FWD ? j : j - 1, has_r, o0, os);
-            nd.rmsg.load(r_rmsg, o0, os);
-        }
-        offsets<4>(out_slot, out && has_bin, o0, os);
-        nd.bin.load(r_bin, o0, os);
-        const long long ei = wbase + (long long)out_slot * w_node;
-        const unsigned wo = (out && ok) ? (unsigned)(ei * 4) : kOOB;
-        nd.w = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r_w, (int)wo, 0, 0));
+        advance<FWD>(c);
     }
 
     __device__ __forceinline__ float lane_min(const float (&x)[LPL]) const {
@@ -165,253 +245,402 @@ struct AdjWalker {
         return m;
     }
 
-    // Lowest label attaining the group minimum `mn` of x.
-    __device__ __forceinline__ int group_argmin(const float (&x)[LPL], float mn) const {
-        int first = 0x7fffffff;
-#pragma unroll
-        for (int i = LPL - 1; i >= 0; --i)
-            if (lv[i] && x[i] == mn) first = sub * LPL + i;
-        return group_min_i<G>(first);
+    // Neighbour-lane moves inside the group: value of lane sub-1 / sub+1, `fill` at the
+    // group's first / last lane.
+    template <typename V>
+    __device__ __forceinline__ V from_left(V x, V fill) const {
+        const int r = __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, fill), __builtin_bit_cast(int, x), kWaveShr1,
+                                                  0xF, 0xF, false);
+        const V y = __builtin_bit_cast(V, r);
+        return (G < 64 && sub == 0) ? fill : y;
+    }
+    template <typename V>
+    __device__ __forceinline__ V from_right(V x, V fill) const {
+        const int r = __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, fill), __builtin_bit_cast(int, x), kWaveShl1,
+                                                  0xF, 0xF, false);
+        const V y = __builtin_bit_cast(V, r);
+        return (G < 64 && sub == G - 1) ? fill : y;
     }
 
-    // Adjoint of out(b) = min(window, vmin + wT) - vmin given cb = d L / d out; returns
-    // d L / d v in vbar and d L / d w.
-    __device__ __forceinline__ float message_adjoint(const float (&v)[LPL], float wt, const float (&cb)[LPL],
-                                                     float (&vbar)[LPL]) {
-        const float vmin = group_min<G>(lane_min(v));
-        const int astar = group_argmin(v, vmin);
+    // Adjoint of the truncated-linear message out = min(DT(v), vmin + wT) - vmin for the
+    // output adjoint cb: the part that reaches v through the selected sources (vbar), and
+    // per-lane partial sums of dL/dw (wl) and of dL/dvmin (zl: truncated entries minus all
+    // entries; the caller routes the group total to the minimiser).
+    //
+    // DTM 0 / 1 (the distance transform reaches 0 / 1 lanes across): the forward's scans
+    // are replayed with the same arithmetic, recording which operand each min took and
+    // the distance of its source, and the adjoint runs the scans in reverse.  Ties go to
+    // the closer source, then to the lower label; a source at distance >= T, or above
+    // the truncation level, gives the truncation term.  DTM 2 (longer reach): sources are
+    // searched in LDS over the window (candidates 0, -1, +1, -2, +2, ... in that order).
+    template <int DTM>
+    __device__ __forceinline__ void msg_adjoint(const float (&v)[LPL], float vmin, float wt, const float (&cb)[LPL],
+                                                float (&vbar)[LPL], float& wl, float& zl) {
+        const float cap = __builtin_fmaf(wt, Tf, vmin);
+        if constexpr (DTM == 2) {
 #pragma unroll
-        for (int i = 0; i < LPL; ++i) s_v[sub * LPL + i] = v[i];
-        __syncthreads();
-        const float cap = vmin + wt * (float)T;
-        float wpart = 0.0f, tpart = 0.0f, apart = 0.0f;
+            for (int i = 0; i < LPL; ++i) s_v[sub * LPL + i] = v[i];
+            wave_lds_sync();
+            float wpart = 0.0f, cpart = 0.0f, apart = 0.0f;
 #pragma unroll
-        for (int i = 0; i < LPL; ++i) {
-            const int b = sub * LPL + i;
-            int src = -1;
-            float dist = (float)T;
-            if (lv[i]) {
-                float best = v[i];
-                int bd = 0;
-                for (int t = 1; t < T && t < K; ++t) {
-                    const int lo = b - t, hi = b + t;
-                    if (lo >= 0) {
-                        const float c = s_v[lo] + wt * (float)t;
-                        if (c < best) { best = c; bd = -t; }
+            for (int i = 0; i < LPL; ++i) {
+                const int b = sub * LPL + i;
+                int src = -1;
+                float dist = Tf;
+                if (FULL || lv[i]) {
+                    float best = v[i];
+                    int bd = 0;
+                    for (int t = 1; t < T && t < K; ++t) {
+                        const int lo = b - t, hi = b + t;
+                        if (lo >= 0) {
+                            const float c = s_v[lo] + wt * (float)t;
+                            if (c < best) { best = c; bd = -t; }
+                        }
+                        if (hi < K) {
+                            const float c = s_v[hi] + wt * (float)t;
+                            if (c < best) { best = c; bd = t; }
+                        }
                     }
-                    if (hi < K) {
-                        const float c = s_v[hi] + wt * (float)t;
-                        if (c < best) { best = c; bd = t; }
+                    if (best <= cap) {
+                        src = b + bd;
+                        dist = (float)(bd < 0 ? -bd : bd);
                     }
+                    wpart += cb[i] * dist;
+                    if (src < 0) cpart += cb[i];
+                    apart += cb[i];
                 }
-                if (best <= cap) {
-                    src = b + bd;
-                    dist = (float)(bd < 0 ? -bd : bd);
-                }
-                wpart += cb[i] * dist;
-                if (src < 0) tpart += cb[i];
-                apart += cb[i];
+                s_cb[b] = (FULL || lv[i]) ? cb[i] : 0.0f;
+                s_src[b] = src;
             }
-            s_cb[b] = lv[i] ? cb[i] : 0.0f;
-            s_src[b] = src;
-        }
-        __syncthreads();
-        const float wsum = group_sum<G>(wpart);
-        const float tsum = group_sum<G>(tpart);
-        const float asum = group_sum<G>(apart);
+            wave_lds_sync();
 #pragma unroll
-        for (int i = 0; i < LPL; ++i) {
-            const int a = sub * LPL + i;
-            float acc = 0.0f;
-            if (lv[i]) {
-                const int lo = a - (T - 1) > 0 ? a - (T - 1) : 0;
-                const int hi = a + (T - 1) < K - 1 ? a + (T - 1) : K - 1;
-                for (int b = lo; b <= hi; ++b)
-                    if (s_src[b] == a) acc += s_cb[b];
-                if (a == astar) acc += tsum - asum;
+            for (int i = 0; i < LPL; ++i) {
+                const int a = sub * LPL + i;
+                float acc = 0.0f;
+                if (FULL || lv[i]) {
+                    const int lo = a - (T - 1) > 0 ? a - (T - 1) : 0;
+                    const int hi = a + (T - 1) < K - 1 ? a + (T - 1) : K - 1;
+                    for (int b = lo; b <= hi; ++b)
+                        if (s_src[b] == a) acc += s_cb[b];
+                }
+                vbar[i] = acc;
             }
-            vbar[i] = acc;
+            wave_lds_sync();
+            wl = wpart;
+            zl = cpart - apart;
+        } else {
+            float wk[LPL + 1];
+            wk[0] = 0.0f;
+#pragma unroll
+            for (int i = 1; i <= LPL; ++i) wk[i] = i == 1 ? wt : wt * (float)i;
+            // forward in-lane scans (values as the forward computes them) with choices
+            float f[LPL], b[LPL];
+            int df[LPL], db[LPL];
+            bool fi[LPL], bi[LPL];  // took the neighbour (inherit) rather than v itself
+            f[0] = v[0];
+            df[0] = 0;
+            fi[0] = false;
+#pragma unroll
+            for (int i = 1; i < LPL; ++i) {
+                const float c = f[i - 1] + wt;
+                fi[i] = c < v[i];
+                f[i] = fi[i] ? c : v[i];
+                df[i] = fi[i] ? df[i - 1] + 1 : 0;
+            }
+            b[LPL - 1] = v[LPL - 1];
+            db[LPL - 1] = 0;
+            bi[LPL - 1] = false;
+#pragma unroll
+            for (int i = LPL - 2; i >= 0; --i) {
+                const float c = b[i + 1] + wt;
+                bi[i] = c < v[i];
+                b[i] = bi[i] ? c : v[i];
+                db[i] = bi[i] ? db[i + 1] + 1 : 0;
+            }
+            float cl = kBig, cr = kBig;
+            int dcl = kFar, dcr = kFar;
+            if constexpr (DTM == 1) {
+                cl = from_left(f[LPL - 1], kBig);
+                cr = from_right(b[0], kBig);
+                dcl = from_left(df[LPL - 1], kFar);
+                dcr = from_right(db[0], kFar);
+            }
+            float fb[LPL], bb[LPL];
+            float CL = 0.0f, CR = 0.0f, wpart = 0.0f, cpart = 0.0f, apart = 0.0f;
+#pragma unroll
+            for (int i = 0; i < LPL; ++i) {
+                // left side: in-lane forward chain, or (DTM 1) the left lane's chain end
+                float lvv = f[i];
+                int ld = df[i];
+                bool useF = true;
+                if constexpr (DTM == 1) {
+                    const float vl = cl + wk[i + 1];
+                    useF = f[i] <= vl;
+                    lvv = useF ? f[i] : vl;
+                    ld = useF ? df[i] : dcl + i + 1;
+                }
+                float rvv = b[i];
+                int rd = db[i];
+                bool useB = true;
+                if constexpr (DTM == 1) {
+                    const float vr = cr + wk[LPL - i];
+                    useB = b[i] <= vr;
+                    rvv = useB ? b[i] : vr;
+                    rd = useB ? db[i] : dcr + LPL - i;
+                }
+                const bool left = (lvv < rvv) | ((lvv == rvv) & (ld <= rd));
+                const float wv = left ? lvv : rvv;
+                const int wd = left ? ld : rd;
+                const bool win = (wv <= cap) & (wd < T);
+                const float c = (FULL || lv[i]) ? cb[i] : 0.0f;
+                fb[i] = (win & left & useF) ? c : 0.0f;
+                bb[i] = (win & !left & useB) ? c : 0.0f;
+                if constexpr (DTM == 1) {
+                    const float cL = (win & left & !useF) ? c : 0.0f;
+                    const float cR = (win & !left & !useB) ? c : 0.0f;
+                    CL += cL;
+                    CR += cR;
+                    wpart += cL * (float)(i + 1) + cR * (float)(LPL - i);
+                }
+                cpart += win ? 0.0f : c;
+                apart += c;
+            }
+            if constexpr (DTM == 1) {
+                // the left lane's chain end fed this lane's left candidates, and vice versa
+                fb[LPL - 1] += from_right(CL, 0.0f);
+                bb[0] += from_left(CR, 0.0f);
+            }
+            // reverse scans
+#pragma unroll
+            for (int i = 0; i < LPL; ++i) vbar[i] = 0.0f;
+#pragma unroll
+            for (int i = LPL - 1; i >= 1; --i) {
+                if (fi[i]) {
+                    fb[i - 1] += fb[i];
+                    wpart += fb[i];
+                } else {
+                    vbar[i] += fb[i];
+                }
+            }
+            vbar[0] += fb[0];
+#pragma unroll
+            for (int i = 0; i < LPL - 1; ++i) {
+                if (bi[i]) {
+                    bb[i + 1] += bb[i];
+                    wpart += bb[i];
+                } else {
+                    vbar[i] += bb[i];
+                }
+            }
+            vbar[LPL - 1] += bb[LPL - 1];
+            wl = wpart + Tf * cpart;
+            zl = cpart - apart;
         }
-        __syncthreads();
-        return wsum;
     }
 
-    // One adjoint pass.  IS_FIRST: first adjoint pass of the half-step (reads the
-    // half-step output adjoint from lbar, scales it to the family's unaries and, for the
-    // horizontal family, adds it to dL/dcost).  IS_LAST: the R0 adjoint, which writes the
-    // half-step input adjoint back to lbar (and adds to dL/dcost).
-    template <bool FWD, int KIND, bool IS_FIRST>
-    __device__ void pass(float gamma, bool has_bin) {
-        float carry[LPL];
+    // One adjoint pass over the forward pass FWD of kind KIND.  IS_FIRST: the half-step's
+    // last update pass (its input adjoint in lbar is dL/d(dual after the half-step); it is
+    // turned into units of the family's unaries r = cost - dual (rows) or dual (columns)
+    // and, for rows, added to dL/dcost).  R0: writes dL/d(dual before the half-step) back
+    // to lbar and adds dL/dr to dL/dcost for rows.
+    template <bool FWD, int KIND, bool IS_FIRST, int DTM>
+    __device__ __forceinline__ void pass(float gamma) {
+        float cbar[LPL];
 #pragma unroll
-        for (int i = 0; i < LPL; ++i) carry[i] = 0.0f;
-        int next_label = 0;  // final mode: label of the node visited before (LB pairwise term)
+        for (int i = 0; i < LPL; ++i) cbar[i] = 0.0f;
+        int next_label = 0;  // final pass: optimum label of the node visited before
+        Cursor lc = cursor_start(FWD);
+        Cursor sc = lc;
         Node ring[PF];
-        // The adjoint walks against FWD: step t visits node FWD ? n-1-t : t.
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
-            const int t = q < n ? q : n - 1;
-            load<FWD, KIND, IS_FIRST>(ring[q], FWD ? n - 1 - t : t, has_bin);
+            load<FWD, KIND, IS_FIRST>(ring[q], lc);
+            __builtin_amdgcn_sched_barrier(0);  // keep slot order (the loop's waits assume it)
         }
         int t0 = 0;
         for (; t0 + PF <= n; t0 += PF) {
 #pragma unroll
             for (int q = 0; q < PF; ++q) {
-                const int t = t0 + q;
-                Node cur = ring[q];
-                const int tn = (t + PF < n) ? t + PF : n - 1;
-                load<FWD, KIND, IS_FIRST>(ring[q], FWD ? n - 1 - tn : tn, has_bin);
-                step<FWD, KIND, IS_FIRST>(cur, FWD ? n - 1 - t : t, carry, gamma, next_label);
+                step<FWD, KIND, IS_FIRST, DTM>(ring[q], t0 + q, cbar, gamma, next_label, sc);
+                load<FWD, KIND, IS_FIRST>(ring[q], lc);
             }
         }
 #pragma unroll
-        for (int q = 0; q < PF; ++q) {
-            const int t = t0 + q;
-            if (t < n) step<FWD, KIND, IS_FIRST>(ring[q], FWD ? n - 1 - t : t, carry, gamma, next_label);
-        }
+        for (int q = 0; q < PF; ++q)
+            if (t0 + q < n) step<FWD, KIND, IS_FIRST, DTM>(ring[q], t0 + q, cbar, gamma, next_label, sc);
     }
 
     template <bool FWD, int KIND, bool IS_FIRST>
-    __device__ __forceinline__ void step(const Node& nd, int j, float (&carry)[LPL], float gamma, int& next_label) {
-        const bool out = FWD ? (j < n - 1) : (j > 0);
-        const int out_slot = FWD ? j : j - 1;
-        float r[LPL], ab[LPL], cbo[LPL];
+    __device__ __forceinline__ void run_pass(float gamma) {
+        if (dt_steps == 0)
+            pass<FWD, KIND, IS_FIRST, 0>(gamma);
+        else if (dt_steps == 1)
+            pass<FWD, KIND, IS_FIRST, 1>(gamma);
+        else
+            pass<FWD, KIND, IS_FIRST, 2>(gamma);
+    }
+
+    // Adjoint of the forward step at the node visited t-th (t = 0: the pass's last node).
+    template <bool FWD, int KIND, bool IS_FIRST, int DTM>
+    __device__ __forceinline__ void step(const Node& nd, int t, float (&cbar)[LPL], float gamma, int& next_label,
+                                         Cursor& sc) {
+        const bool out = t != 0;        // a message leaves this node in the forward pass
+        const bool has_c = t != n - 1;  // a carried message arrives at it
+        const unsigned rs = FWD ? sc.f : sc.f - f_step;
+        unsigned os[LPL];
+        float r[LPL], carry[LPL], ab[LPL], cb[LPL];
 #pragma unroll
         for (int i = 0; i < LPL; ++i) {
             const float lam = nd.lam.get(i);
             const float x = HAS_THETA ? nd.th.get(i) - lam : lam;
-            r[i] = lv[i] ? x : kBig;
-            ab[i] = nd.abar.get(i);
-            cbo[i] = out ? carry[i] + nd.bin.get(i) : 0.0f;
+            r[i] = (FULL || lv[i]) ? x : kBig;
+            carry[i] = has_c ? nd.cmsg.get(i) : 0.0f;
+            ab[i] = KIND == kAdjFinal ? 0.0f : nd.abar.get(i);
+            cb[i] = out ? cbar[i] + nd.bin.get(i) : 0.0f;
         }
-        unsigned o0, os[LPL];
-        offsets<4>(j, true, o0, os);
         if constexpr (IS_FIRST) {
-            // lbar holds dL/d(dual after the half-step); the family's last-pass unaries r
-            // relate to it by lambda = cost - r (horizontal) or lambda = r (vertical)
             if constexpr (HAS_THETA) {
                 float g[LPL];
 #pragma unroll
                 for (int i = 0; i < LPL; ++i) g[i] = nd.gx.get(i) + ab[i];
-                store_f32<LPL, FULL>(r_gth, o0, os, g);
+                label_offsets<4>(sc.f, os);
+                store_f32<LPL, FULL>(r_gth, sc.f, os, g);
             }
 #pragma unroll
             for (int i = 0; i < LPL; ++i) ab[i] = (sign > 0.0f) ? -ab[i] : ab[i];
         }
-        float v[LPL], vbar[LPL], rbar[LPL], cbar[LPL];
+        float vbar[LPL], wl = 0.0f, zl = 0.0f;
         if constexpr (KIND == kAdjR0) {
+            float v[LPL];
 #pragma unroll
-            for (int i = 0; i < LPL; ++i) v[i] = nd.cmsg.get(i) + r[i];
-        } else {
-            float m[LPL];
+            for (int i = 0; i < LPL; ++i) v[i] = carry[i] + r[i];
+            const float vmin = group_min<G>(lane_min(v));
+            msg_adjoint<DTM>(v, vmin, nd.w, cb, vbar, wl, zl);
+            group_sum2<G>(wl, zl);
+            const int a_v = group_argmin_eq<G, LPL, FULL>(v, vmin, lv, sub);
+            float rt[LPL], outv[LPL];
 #pragma unroll
-            for (int i = 0; i < LPL; ++i) m[i] = r[i] + nd.cmsg.get(i) + nd.rmsg.get(i);
-            const float mmin = group_min<G>(lane_min(m));
-            const int kstar = group_argmin(m, mmin);
-            float madj[LPL];
-            if constexpr (KIND == kAdjFinal) {
-                // normalized min-marginal adjoint + lower-bound term at the row optimum
-                float gs = 0.0f;
-#pragma unroll
-                for (int i = 0; i < LPL; ++i) gs += lv[i] ? nd.gx.get(i) : 0.0f;
-                gs = group_sum<G>(gs);
-#pragma unroll
-                for (int i = 0; i < LPL; ++i) {
-                    madj[i] = lv[i] ? nd.gx.get(i) : 0.0f;
-                    if (sub * LPL + i == kstar) madj[i] -= gs;
-                    v[i] = nd.cmsg.get(i) + r[i];
-                }
-            } else {
-                // the message leaving node j is computed from r' = r - delta (iterative) or
-                // from r (naive); madj is filled after the message adjoint
-                const float g = KIND == kAdjIter ? gamma : inv_n;
-#pragma unroll
-                for (int i = 0; i < LPL; ++i) {
-                    float dl = g * (m[i] - mmin);
-                    dl = lv[i] ? dl : 0.0f;
-                    v[i] = nd.cmsg.get(i) + (KIND == kAdjIter ? r[i] - dl : r[i]);
-                }
+            for (int i = 0; i < LPL; ++i) {
+                if (sub * LPL + i == a_v) vbar[i] += zl;
+                rt[i] = ab[i] + vbar[i];
+                cbar[i] = (FULL || lv[i]) ? vbar[i] : 0.0f;
+                outv[i] = sign > 0.0f ? -rt[i] : rt[i];  // dL/d(dual before the half-step)
             }
-            float wsum = 0.0f;
+            label_offsets<4>(sc.f, os);
+            if constexpr (HAS_THETA) {
+                float g[LPL];
+#pragma unroll
+                for (int i = 0; i < LPL; ++i) g[i] = nd.gx.get(i) + rt[i];
+                store_f32<LPL, FULL>(r_gth, sc.f, os, g);
+            }
+            store_f32<LPL, FULL>(r_abar, sc.f, os, outv);
+        } else {
+            // replay the forward step (same arithmetic as the forward walker)
+            float v[LPL], m[LPL], u[LPL], vn[LPL];
+#pragma unroll
+            for (int i = 0; i < LPL; ++i) {
+                v[i] = r[i] + carry[i];
+                m[i] = v[i] + (out ? nd.rmsg.get(i) : 0.0f);
+            }
+            float mmin = lane_min(m), bmin;
+            if constexpr (KIND == kAdjIter) {
+#pragma unroll
+                for (int i = 0; i < LPL; ++i) u[i] = (FULL || lv[i]) ? __builtin_fmaf(-gamma, m[i], v[i]) : kBig;
+                bmin = lane_min(u);
+            } else {
+                bmin = lane_min(v);
+            }
+            group_min2<G>(mmin, bmin);
+            float vmin;
+            if constexpr (KIND == kAdjIter) {
+#pragma unroll
+                for (int i = 0; i < LPL; ++i) {
+                    const float d = (FULL || lv[i]) ? gamma * (m[i] - mmin) : 0.0f;
+                    vn[i] = v[i] - d;
+                }
+                vmin = __builtin_fmaf(gamma, mmin, bmin);
+            } else {
+#pragma unroll
+                for (int i = 0; i < LPL; ++i) vn[i] = v[i];
+                vmin = bmin;
+            }
+            const int kstar = group_argmin_eq<G, LPL, FULL>(m, mmin, lv, sub);
             if (out) {
-                wsum = message_adjoint(v, nd.w, cbo, vbar);
+                msg_adjoint<DTM>(vn, vmin, nd.w, cb, vbar, wl, zl);
             } else {
 #pragma unroll
                 for (int i = 0; i < LPL; ++i) vbar[i] = 0.0f;
             }
-            if constexpr (KIND == kAdjFinal) {
+            // third sum: dL/d(r out) (update passes) or dL/dminmarg (final pass)
+            float al = 0.0f;
+#pragma unroll
+            for (int i = 0; i < LPL; ++i)
+                al += (FULL || lv[i]) ? (KIND == kAdjFinal ? nd.gx.get(i) : ab[i]) : 0.0f;
+            group_sum2<G>(wl, zl);
+            al = group_sum<G>(al);
+            const int a_b = group_argmin_eq<G, LPL, FULL>(KIND == kAdjIter ? u : v, bmin, lv, sub);
+            float rbar[LPL], revb[LPL];
+            if constexpr (KIND == kAdjIter) {
+                // vmin = min u + gamma mmin, u = rc - gamma m, d = gamma (m - mmin),
+                // r' = r - d, v' = rc - d; dL/dmmin sums to gamma * sum(dL/dr')
+                const float mminb = gamma * al;
 #pragma unroll
                 for (int i = 0; i < LPL; ++i) {
-                    rbar[i] = madj[i] + vbar[i];
-                    cbar[i] = madj[i] + vbar[i];
+                    const bool valid = FULL || lv[i];
+                    const int lab = sub * LPL + i;
+                    const float ub = lab == a_b ? zl : 0.0f;
+                    const float dbar = valid ? -vbar[i] - ab[i] : 0.0f;
+                    float mb = gamma * dbar - gamma * ub;
+                    if (lab == kstar) mb += mminb;
+                    mb = valid ? mb : 0.0f;
+                    const float rcb = vbar[i] + ub + mb;
+                    revb[i] = out ? mb : 0.0f;
+                    rbar[i] = ab[i] + rcb;
+                    cbar[i] = valid ? rcb : 0.0f;
                 }
-                // lower bound: d opt / d r_j = one-hot of the row optimum's label (kstar)
-                if (g_lb_f != 0.0f) {
+            } else if constexpr (KIND == kAdjNaive) {
+                const float mminb = inv_n * al;
 #pragma unroll
-                    for (int i = 0; i < LPL; ++i)
-                        if (sub * LPL + i == kstar) rbar[i] += g_lb_f;
+                for (int i = 0; i < LPL; ++i) {
+                    const bool valid = FULL || lv[i];
+                    const int lab = sub * LPL + i;
+                    if (lab == a_b) vbar[i] += zl;
+                    float mb = valid ? -inv_n * ab[i] : 0.0f;
+                    if (lab == kstar) mb += mminb;
+                    const float rcb = vbar[i] + mb;
+                    revb[i] = out ? mb : 0.0f;
+                    rbar[i] = ab[i] + rcb;
+                    cbar[i] = valid ? rcb : 0.0f;
+                }
+            } else {  // final pass: normalized min-marginals mm = m - mmin, lower bound
+#pragma unroll
+                for (int i = 0; i < LPL; ++i) {
+                    const bool valid = FULL || lv[i];
+                    const int lab = sub * LPL + i;
+                    if (lab == a_b) vbar[i] += zl;
+                    float mb = valid ? nd.gx.get(i) : 0.0f;
+                    if (lab == kstar) mb -= al;
+                    const float rcb = vbar[i] + mb;
+                    revb[i] = out ? mb : 0.0f;
+                    // d(row optimum)/dr = one-hot of the optimum's label
+                    rbar[i] = rcb + ((lab == kstar) ? g_lb_f : 0.0f);
+                    cbar[i] = valid ? rcb : 0.0f;
                 }
                 if (out) {
                     int dd = kstar - next_label;
                     dd = dd < 0 ? -dd : dd;
-                    wsum += g_lb_f * (float)(dd < T ? dd : T);
+                    wl += g_lb_f * (float)(dd < T ? dd : T);
                 }
                 next_label = kstar;
-            } else {
-                const float g = KIND == kAdjIter ? gamma : inv_n;
-                float rbp[LPL], s = 0.0f;
-#pragma unroll
-                for (int i = 0; i < LPL; ++i) {
-                    rbp[i] = (KIND == kAdjIter) ? ab[i] + vbar[i] : ab[i];
-                    s += lv[i] ? -rbp[i] : 0.0f;
-                }
-                s = group_sum<G>(s);
-#pragma unroll
-                for (int i = 0; i < LPL; ++i) {
-                    float mb = lv[i] ? g * (-rbp[i]) : 0.0f;
-                    if (sub * LPL + i == kstar) mb -= g * s;
-                    madj[i] = mb;
-                    rbar[i] = rbp[i] + (KIND == kAdjNaive ? vbar[i] : 0.0f) + mb;
-                    cbar[i] = vbar[i] + mb;
-                }
             }
-            // adjoint of the reverse message read at node j, for the pass that wrote it
-            const bool has_r = FWD ? (j < n - 1) : (j > 0);
-            unsigned ro0, ros[LPL];
-            offsets<4>(FWD ? j : j - 1, has_r, ro0, ros);
-            store_f32<LPL, FULL>(r_bout, ro0, ros, madj);
-            if (ok && sub == 0 && out && wsum != 0.0f) grad_w[wbase + (long long)out_slot * w_node] += (double)wsum;
-#pragma unroll
-            for (int i = 0; i < LPL; ++i) carry[i] = lv[i] ? cbar[i] : 0.0f;
-            store_f32<LPL, FULL>(r_abar, o0, os, rbar);
-            return;
+            label_offsets<4>(rs, os);
+            store_f32<LPL, FULL>(r_bout, rs, os, revb);
+            label_offsets<4>(sc.f, os);
+            store_f32<LPL, FULL>(r_abar, sc.f, os, rbar);
         }
-        // R0 adjoint
-        float wsum = 0.0f;
-        if (out) {
-            wsum = message_adjoint(v, nd.w, cbo, vbar);
-        } else {
-#pragma unroll
-            for (int i = 0; i < LPL; ++i) vbar[i] = 0.0f;
-        }
-        if (ok && sub == 0 && out && wsum != 0.0f) grad_w[wbase + (long long)out_slot * w_node] += (double)wsum;
-        float rt[LPL], outv[LPL];
-#pragma unroll
-        for (int i = 0; i < LPL; ++i) {
-            rt[i] = ab[i] + vbar[i];
-            carry[i] = lv[i] ? vbar[i] : 0.0f;
-            outv[i] = sign > 0.0f ? -rt[i] : rt[i];  // dL/d(dual before the half-step)
-        }
-        if constexpr (HAS_THETA) {
-            float g[LPL];
-#pragma unroll
-            for (int i = 0; i < LPL; ++i) g[i] = nd.gx.get(i) + rt[i];
-            store_f32<LPL, FULL>(r_gth, o0, os, g);
-        }
-        store_f32<LPL, FULL>(r_abar, o0, os, outv);
+        if (ok && sub == 0 && out && wl != 0.0f) add_edge_grad(sc.w, wl);
+        advance<FWD>(sc);
     }
-
-    float g_lb_f = 0.0f;
 };
 
 template <int G, int LPL, int PF, typename TT, bool FULL, bool HAS_THETA>
@@ -435,12 +664,12 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
         wk.r_rmsg = make_rsrc(a.rec_msg[0], vb);
         wk.r_bin = make_rsrc(nullptr, 0u);
         wk.r_bout = make_rsrc(a.bbar[0], vb);
-        wk.template pass<true, kAdjFinal, false>(0.0f, false);
+        wk.template run_pass<true, kAdjFinal, false>(0.0f);
         wk.r_cmsg = make_rsrc(a.rec_msg[0], vb);
         wk.r_bin = make_rsrc(a.bbar[0], vb);
         wk.r_bout = make_rsrc(nullptr, 0u);
         // the final pass's R0 adjoint turns dL/dr into dL/dcost and dL/d(dual) = -dL/dr
-        wk.template pass<false, kAdjR0, false>(0.0f, true);
+        wk.template run_pass<false, kAdjR0, false>(0.0f);
         return;
     }
     const int P = a.mode == kModeIterative ? a.n_pass : 1;
@@ -462,24 +691,27 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
         wk.r_cmsg = make_rsrc(msg_s, vb);
         wk.r_rmsg = make_rsrc(msg_r, vb);
         const bool has_bin = s < P;
-        wk.r_bin = make_rsrc(a.bbar[s & 1], has_bin ? vb : 0u);
-        wk.r_bout = make_rsrc(a.bbar[(s - 1) & 1], vb);
+        // selects, not a dynamic index (which would put the argument block in scratch)
+        float* const b_odd = a.bbar[1];
+        float* const b_even = a.bbar[0];
+        wk.r_bin = make_rsrc((s & 1) ? b_odd : b_even, has_bin ? vb : 0u);
+        wk.r_bout = make_rsrc((s & 1) ? b_even : b_odd, vb);
         const bool fwd = ((s - 1) & 1) == 0;
         if (a.mode == kModeNaive) {
-            wk.template pass<true, kAdjNaive, true>(0.0f, false);
+            wk.template run_pass<true, kAdjNaive, true>(0.0f);
         } else if (s == P) {
-            if (fwd) wk.template pass<true, kAdjIter, true>(g, has_bin);
-            else wk.template pass<false, kAdjIter, true>(g, has_bin);
+            if (fwd) wk.template run_pass<true, kAdjIter, true>(g);
+            else wk.template run_pass<false, kAdjIter, true>(g);
         } else {
-            if (fwd) wk.template pass<true, kAdjIter, false>(g, has_bin);
-            else wk.template pass<false, kAdjIter, false>(g, has_bin);
+            if (fwd) wk.template run_pass<true, kAdjIter, false>(g);
+            else wk.template run_pass<false, kAdjIter, false>(g);
         }
     }
     wk.r_lam = make_rsrc(a.lam0, vb);
     wk.r_cmsg = make_rsrc(a.rec_msg[0], vb);
     wk.r_bin = make_rsrc(a.bbar[0], vb);
     wk.r_bout = make_rsrc(nullptr, 0u);
-    wk.template pass<false, kAdjR0, false>(0.0f, true);
+    wk.template run_pass<false, kAdjR0, false>(0.0f);
 }
 
 constexpr int kAdjPF = 4;

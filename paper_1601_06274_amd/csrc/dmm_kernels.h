@@ -197,7 +197,7 @@ struct Walker {
     int dt_steps;     // lanes the distance transform must reach across
     float dl, dr;     // distance-transform lane shifts; lanes without a source keep kBig
 
-    __device__ Walker(SweepArgs args, int chain, int sub_)
+    __device__ __forceinline__ Walker(SweepArgs args, int chain, int sub_)
         : sub(sub_), n(args.n), K(args.K), T(args.T), sign(args.sign), inv_n(args.inv_n) {
         ok = chain < args.n_chains;
         Tf = (float)args.T;
@@ -317,7 +317,7 @@ struct Walker {
         b[LPL - 1] = v[LPL - 1];
 #pragma unroll
         for (int i = LPL - 2; i >= 0; --i) b[i] = fminf(v[i], b[i + 1] + wt);
-        const float cap = vmin + wt * Tf;
+        const float cap = __builtin_fmaf(wt, Tf, vmin);
         if constexpr (DT1) {
             const float cl = from_left(f[LPL - 1]);
             const float cr = from_right(b[0]);
@@ -356,7 +356,7 @@ struct Walker {
     // 2 = naive update, 3 = final min-marginals.  Adds the normalisation constants of a
     // message pass (= chain optimum) to `opt`.
     template <bool FWD, int KIND, bool DT1>
-    __device__ void pass(float gamma, bool store_msg, double& opt) {
+    __device__ __forceinline__ void pass(float gamma, bool store_msg, double& opt) {
         constexpr bool WANT_REV = KIND != 0;
         float carry[LPL];
 #pragma unroll
@@ -435,13 +435,13 @@ struct Walker {
             if constexpr (KIND == 1) {
                 float u[LPL];
 #pragma unroll
-                for (int i = 0; i < LPL; ++i) u[i] = (FULL || lv[i]) ? v[i] - gamma * m[i] : kBig;
+                for (int i = 0; i < LPL; ++i) u[i] = (FULL || lv[i]) ? __builtin_fmaf(-gamma, m[i], v[i]) : kBig;
                 bmin = lane_min(u);
             } else {
                 bmin = lane_min(v);
             }
             group_min2<G>(mmin, bmin);
-            vmin = KIND == 1 ? bmin + gamma * mmin : bmin;
+            vmin = KIND == 1 ? __builtin_fmaf(gamma, mmin, bmin) : bmin;
             if constexpr (KIND == 1 || KIND == 2) {
                 float nl[LPL];
 #pragma unroll
@@ -449,7 +449,7 @@ struct Walker {
                     float d = (KIND == 1 ? gamma : inv_n) * (m[i] - mmin);
                     d = (FULL || lv[i]) ? d : 0.0f;
                     if (KIND == 1) v[i] -= d;
-                    nl[i] = lamv[i] + sign * d;
+                    nl[i] = __builtin_fmaf(sign, d, lamv[i]);
                 }
                 unsigned os[LPL];
                 label_offsets<4>(sf, os);

@@ -42,6 +42,11 @@ constexpr int kWaveShl1 = 0x130;     // lane i <- lane i+1
 constexpr int kRowShr1 = 0x111;      // lane i <- lane i-1 within a row of 16
 constexpr int kRowShl1 = 0x101;      // lane i <- lane i+1 within a row of 16
 
+// Orders this wave's LDS accesses: all lanes' earlier LDS writes are visible to later LDS
+// reads of any lane.  For a workgroup of one wave no barrier is needed, and unlike
+// __syncthreads (a workgroup fence) this does not wait for global loads in flight.
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 // An opaque copy: keeps the compiler from treating the two operands of a permlane swap
 // as the same value (it would otherwise fold min(swap.first, swap.second)).
 __device__ __forceinline__ uint32_t opaque_copy(uint32_t x) {
