@@ -112,9 +112,11 @@ def main():
     import ctypes
     lib = P.lib()
     shp = P._lib.DmShape(W, H, K)
-    dkw = dict(T=wl["T"], n_iters=wl["n_iters"], gammas=wl["gammas"])
+    # chain tiles for row and column chains picked once by the library's autotuner
+    tiles = ops.autotune_tiles((H, W, K), torch.float16, T=wl["T"], gammas=wl["gammas"])
+    dkw = dict(T=wl["T"], n_iters=wl["n_iters"], gammas=wl["gammas"], tile=tiles)
     rkw = dict(C=wl["C"], n_warps=wl["n_warps"], n_iters=wl["refine_iters"])
-    dp = ops.discrete_params(T=wl["T"], n_iters=wl["n_iters"], gammas=wl["gammas"], keep_checkpoints=True)
+    dp = ops.discrete_params(keep_checkpoints=True, **dkw)
     ws_d = torch.empty(lib.dm_solve_discrete_workspace(shp, P._lib.DM_F16, ctypes.byref(dp)), dtype=torch.uint8,
                        device=dev)
     ws_db = torch.empty(lib.dm_solve_discrete_backward_workspace(shp, ctypes.byref(dp)), dtype=torch.uint8, device=dev)
@@ -213,6 +215,7 @@ def main():
                         "backward (dL/dcost, dL/dw for L = <G_m, min-marginals> + LB + <G_u, u>); value counts "
                         "the forward's label-node updates per frame",
             "W": W, "H": H, "K": K, "cost_storage": "f16", "state": "f32",
+            "tiles": {"rows": list(tiles[0]), "columns": list(tiles[1])},
             "stages": ["build_cost_volume", "solve_discrete", "refine_continuous", "refine_continuous_backward",
                        "solve_discrete_backward"],
         },

@@ -50,7 +50,7 @@ typedef enum { DM_F32 = 0, DM_F16 = 1 } dm_dtype;   /* storage type of the cost 
 typedef enum { DM_MINORANT_ITERATIVE = 0, DM_MINORANT_NAIVE = 1 } dm_minorant;
 
 /* Grid of W x H pixels with K labels; 1 <= W, H <= 16384, 1 <= K <= 256, and one FP32
- * volume (W*H*K*4 bytes) at most 0xFFFFFF00 bytes: the kernels address volumes with
+ * volume (W*H*K*4 bytes) at most 0xFE000000 bytes: the kernels address volumes with
  * 32-bit byte offsets.  Larger shapes fail with DM_ERR_SHAPE. */
 typedef struct { int W, H, K; } dm_shape;
 
@@ -127,6 +127,11 @@ int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const float* w_h, c
                       int32_t* labels_out, float* minmarg_out, float* dual_inout,
                       double* bounds_out, double* lb_trace_out,
                       void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* The tile used when p->tile_lanes is 0: the compiled (lanes per chain, labels per lane)
+ * tile with the fewest idle label slots for K labels (more lanes on ties).  Host only;
+ * returns DM_ERR_SHAPE for K outside [1, 256], DM_ERR_NULL for null outputs. */
+int dm_default_tile(int K, int* tile_lanes, int* labels_per_lane);
 
 /* Autotuner: measures every compiled (lanes per chain, labels per lane) tile on one
  * half-step of a synthetic instance of shape s (row and column chains separately) and

@@ -7,6 +7,7 @@ from __future__ import annotations
 import argparse
 import concurrent.futures as cf
 import os
+import re
 import subprocess
 import sys
 
@@ -17,10 +18,18 @@ LIB = os.path.join(HERE, "libdmatch.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # (source, extra defines, object name)
-TILES = [(4, 1), (4, 2), (8, 4), (16, 4), (32, 3), (32, 4), (64, 3), (64, 4)]
+def _tiles():
+    """The tile list of csrc/tiles.h (one compilation unit per tile)."""
+    with open(os.path.join(CSRC, "tiles.h")) as f:
+        return [(int(g), int(l)) for g, l in re.findall(r"X\((\d+),\s*(\d+)\)", f.read())]
+
+
+TILES = _tiles()
 UNITS = [("api.hip", [], "api"), ("dmm.hip", [], "dmm"), ("cost_volume.hip", [], "cost_volume"),
          ("refine.hip", [], "refine"), ("batched.hip", [], "batched")]
-UNITS += [("dmm_tile.hip", [f"-DDM_TILE_G={g}", f"-DDM_TILE_L={l}"], f"dmm_tile_{g}x{l}") for g, l in TILES]
+# largest units first so the parallel build's critical path starts early
+UNITS = [("dmm_tile.hip", [f"-DDM_TILE_G={g}", f"-DDM_TILE_L={l}", f"-DDM_TILE_PART={k}"], f"dmm_tile_{g}x{l}_{v}")
+         for k, v in [(2, "adj"), (1, "fwd"), (3, "batch")] for g, l in sorted(TILES, key=lambda t: -t[0] * t[1])] + UNITS
 
 FLAGS = [
     "--offload-arch=gfx950",
@@ -47,6 +56,9 @@ def _compile(unit) -> str:
 def build(jobs: int | None = None, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(UNITS), os.cpu_count() or 1)
+    for f in os.listdir(BUILD):  # objects of units that no longer exist
+        if f.endswith(".o") and f[:-2] not in {u[2] for u in UNITS}:
+            os.remove(os.path.join(BUILD, f))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, UNITS))
     tmp = LIB + ".tmp"

@@ -33,7 +33,7 @@ int validate_shape(const dm_shape& s) {
     DM_REQUIRE(s.H >= 1 && s.H <= 16384, DM_ERR_SHAPE, "H=%d out of range [1, 16384]", s.H);
     DM_REQUIRE(s.K >= 1 && s.K <= 256, DM_ERR_SHAPE, "K=%d out of range [1, 256]", s.K);
     const unsigned long long vol = (unsigned long long)s.W * (unsigned long long)s.H * (unsigned long long)s.K * 4ull;
-    DM_REQUIRE(vol <= 0xFFFFFF00ull, DM_ERR_SHAPE, "W*H*K*4 = %llu bytes exceeds the 32-bit volume offset range", vol);
+    DM_REQUIRE(vol <= 0xFE000000ull, DM_ERR_SHAPE, "W*H*K*4 = %llu bytes exceeds the 32-bit volume offset range", vol);
     return DM_OK;
 }
 

@@ -14,19 +14,13 @@
 #include "batched_kernels.h"
 #include "common.h"
 #include "refine.h"
+#include "tiles.h"
 
 namespace dm {
 
 #define DM_EXTERN_BTILE(g, l) \
     extern template hipError_t launch_batched_tile<g, l>(const BatchLaunch&, bool, dm_dtype, int, hipStream_t);
-DM_EXTERN_BTILE(4, 1)
-DM_EXTERN_BTILE(4, 2)
-DM_EXTERN_BTILE(8, 4)
-DM_EXTERN_BTILE(16, 4)
-DM_EXTERN_BTILE(32, 3)
-DM_EXTERN_BTILE(32, 4)
-DM_EXTERN_BTILE(64, 3)
-DM_EXTERN_BTILE(64, 4)
+DM_FOR_EACH_TILE(DM_EXTERN_BTILE)
 #undef DM_EXTERN_BTILE
 
 namespace {
@@ -34,14 +28,7 @@ namespace {
 hipError_t launch_batched(int G, int LPL, const BatchLaunch& bl, bool full, dm_dtype dt, int workers, hipStream_t st) {
 #define DM_BCASE(g, l) \
     if (G == g && LPL == l) return launch_batched_tile<g, l>(bl, full, dt, workers, st);
-    DM_BCASE(4, 1)
-    DM_BCASE(4, 2)
-    DM_BCASE(8, 4)
-    DM_BCASE(16, 4)
-    DM_BCASE(32, 3)
-    DM_BCASE(32, 4)
-    DM_BCASE(64, 3)
-    DM_BCASE(64, 4)
+    DM_FOR_EACH_TILE(DM_BCASE)
 #undef DM_BCASE
     return hipErrorInvalidValue;
 }

@@ -6,13 +6,68 @@
 // (Sec. 3.1); this kernel provides a truncated windowed SAD in the same role.
 // Edge strengths are image dependent, lower across image edges (Sec. 2.1).
 //
-// Layout: one thread per (pixel, label), label fastest, so each wavefront writes a
-// contiguous run of the label-major volume (the kernel is bound by those writes);
-// the image reads of a window hit the caches.
+// Layout: the volume is label-major ([y][x][d], d fastest).  A block owns one image row
+// and TX consecutive pixels; its threads are the labels (blockDim = K rounded up to a
+// wave), so each pixel's K costs are one contiguous, coalesced write.  The window rows of
+// both images are staged in LDS; each thread first sums the window vertically for the
+// TX + 2R window columns of its label (registers), then slides the horizontal sum.
+// Border handling: window positions are clamped to the image (clamp-to-edge), and a
+// right-image column left of 0 costs `trunc`.
 #include "common.h"
 
 namespace dm {
 
+constexpr int kSadTX = 16;  // pixels per block
+
+template <typename OT, int R>
+__global__ __launch_bounds__(256) void sad_tile_kernel(const float* __restrict__ IL, const float* __restrict__ IR, int W,
+                                                       int H, int K, float trunc, float inv_area,
+                                                       OT* __restrict__ out) {
+    constexpr int TX = kSadTX;
+    constexpr int NR = 2 * R + 1;   // window rows
+    constexpr int NC = TX + 2 * R;  // window columns of the tile
+    __shared__ float sL[NR][NC];
+    __shared__ float sR[NR][NC + 255];
+    const int y = blockIdx.y;
+    const int x0 = blockIdx.x * TX;
+    const int lr = x0 - R;            // image column of sL[.][0]
+    const int rr = x0 - R - (K - 1);  // image column of sR[.][0]
+    const int nrc = NC + K - 1;
+    for (int e = threadIdx.x; e < NR * nrc; e += blockDim.x) {
+        const int row = e / nrc, j = e - row * nrc;
+        const int yy = min(max(y + row - R, 0), H - 1);
+        const int xc = rr + j;
+        sR[row][j] = (xc >= 0 && xc < W) ? IR[(long long)yy * W + xc] : 0.0f;
+        if (j < NC) sL[row][j] = IL[(long long)yy * W + min(max(lr + j, 0), W - 1)];
+    }
+    __syncthreads();
+    const int d = threadIdx.x;
+    if (d >= K) return;
+    // vertical window sums at the (clamped) columns lr + i
+    float col[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        const int xx = min(max(lr + i, 0), W - 1);  // clamped image column
+        const int li = xx - lr;                     // its index in sL
+        const int xr = xx - d;                      // matching right-image column
+        const int ri = xr - rr;
+        float acc = 0.0f;
+#pragma unroll
+        for (int row = 0; row < NR; ++row) acc += (xr >= 0) ? fabsf(sL[row][li] - sR[row][ri]) : trunc;
+        col[i] = acc;
+    }
+#pragma unroll
+    for (int xi = 0; xi < TX; ++xi) {
+        const int x = x0 + xi;
+        if (x >= W) break;
+        float acc = 0.0f;
+#pragma unroll
+        for (int dx = 0; dx < NR; ++dx) acc += col[xi + dx];
+        out[((long long)y * W + x) * K + d] = (OT)fminf(trunc, acc * inv_area);
+    }
+}
+
+// Any odd window (the tiled kernel covers radii 1..3): one thread per (pixel, label).
 template <typename OT>
 __global__ __launch_bounds__(256) void sad_kernel(const float* __restrict__ IL, const float* __restrict__ IR, int W,
                                                   int H, int K, int r, float trunc, float inv_area,
@@ -24,18 +79,15 @@ __global__ __launch_bounds__(256) void sad_kernel(const float* __restrict__ IL, 
         const long long p = idx / K;
         const int x = (int)(p % W), y = (int)(p / W);
         float acc = 0.0f;
-        for (int dy = -r; dy <= r; ++dy) {
-            const int yy = min(max(y + dy, 0), H - 1);
-            const float* Lrow = IL + (long long)yy * W;
-            const float* Rrow = IR + (long long)yy * W;
-            for (int dx = -r; dx <= r; ++dx) {
-                const int xx = min(max(x + dx, 0), W - 1);
-                const int xr = xx - d;
-                acc += (xr >= 0) ? fabsf(Lrow[xx] - Rrow[xr]) : trunc;
+        for (int dx = -r; dx <= r; ++dx) {
+            const int xx = min(max(x + dx, 0), W - 1);
+            const int xr = xx - d;
+            for (int dy = -r; dy <= r; ++dy) {
+                const int yy = min(max(y + dy, 0), H - 1);
+                acc += (xr >= 0) ? fabsf(IL[(long long)yy * W + xx] - IR[(long long)yy * W + xr]) : trunc;
             }
         }
-        const float v = fminf(trunc, acc * inv_area);
-        out[idx] = (OT)v;
+        out[idx] = (OT)fminf(trunc, acc * inv_area);
     }
 }
 
@@ -84,12 +136,27 @@ extern "C" int dm_build_cost_volume(const float* I_left, const float* I_right, d
     const float inv_area = 1.0f / (float)(p->window * p->window);
     // algorithmic bytes: the volume written once, the two images read once
     ProfScope ps(DM_PROF_COST_VOLUME, (double)total * (out_dtype == DM_F16 ? 2 : 4) + 8.0 * s.W * s.H, stream);
-    if (out_dtype == DM_F16)
-        hipLaunchKernelGGL(sad_kernel<_Float16>, dim3(blocks), dim3(256), 0, stream, I_left, I_right, s.W, s.H, s.K, r,
-                           p->trunc, inv_area, static_cast<_Float16*>(cost_out));
-    else
-        hipLaunchKernelGGL(sad_kernel<float>, dim3(blocks), dim3(256), 0, stream, I_left, I_right, s.W, s.H, s.K, r,
-                           p->trunc, inv_area, static_cast<float*>(cost_out));
+    const dim3 tgrid((unsigned)((s.W + kSadTX - 1) / kSadTX), (unsigned)s.H);
+    const dim3 tblock((unsigned)((s.K + 63) / 64 * 64));
+#define DM_SAD_TILE(OT, RR) \
+    hipLaunchKernelGGL((sad_tile_kernel<OT, RR>), tgrid, tblock, 0, stream, I_left, I_right, s.W, s.H, s.K, p->trunc, \
+                       inv_area, static_cast<OT*>(cost_out))
+    if (out_dtype == DM_F16) {
+        if (r == 1) DM_SAD_TILE(_Float16, 1);
+        else if (r == 2) DM_SAD_TILE(_Float16, 2);
+        else if (r == 3) DM_SAD_TILE(_Float16, 3);
+        else
+            hipLaunchKernelGGL(sad_kernel<_Float16>, dim3(blocks), dim3(256), 0, stream, I_left, I_right, s.W, s.H, s.K,
+                               r, p->trunc, inv_area, static_cast<_Float16*>(cost_out));
+    } else {
+        if (r == 1) DM_SAD_TILE(float, 1);
+        else if (r == 2) DM_SAD_TILE(float, 2);
+        else if (r == 3) DM_SAD_TILE(float, 3);
+        else
+            hipLaunchKernelGGL(sad_kernel<float>, dim3(blocks), dim3(256), 0, stream, I_left, I_right, s.W, s.H, s.K, r,
+                               p->trunc, inv_area, static_cast<float*>(cost_out));
+    }
+#undef DM_SAD_TILE
     ps.stop();
     DM_HIP_TRY(hipGetLastError(), "sad launch");
     if (w_h != nullptr || w_v != nullptr) {

@@ -10,20 +10,14 @@
 #include <tuple>
 
 #include "dmm_adjoint.h"
+#include "tiles.h"
 
 namespace dm {
 
 #define DM_EXTERN_TILE(g, l)                                                            \
     extern template hipError_t launch_tile<g, l>(const SweepArgs&, dm_dtype, hipStream_t); \
     extern template hipError_t launch_adjoint_tile<g, l>(const AdjArgs&, dm_dtype, hipStream_t);
-DM_EXTERN_TILE(4, 1)
-DM_EXTERN_TILE(4, 2)
-DM_EXTERN_TILE(8, 4)
-DM_EXTERN_TILE(16, 4)
-DM_EXTERN_TILE(32, 3)
-DM_EXTERN_TILE(32, 4)
-DM_EXTERN_TILE(64, 3)
-DM_EXTERN_TILE(64, 4)
+DM_FOR_EACH_TILE(DM_EXTERN_TILE)
 #undef DM_EXTERN_TILE
 
 // ------------------------------------------------------------------ small kernels
@@ -168,7 +162,9 @@ struct Tile {
 };
 
 // Tiles compiled into the library; a chain of K labels needs G*LPL >= K.
-constexpr Tile kTiles[] = {{4, 1}, {4, 2}, {8, 4}, {16, 4}, {32, 3}, {32, 4}, {64, 3}, {64, 4}};
+#define DM_TILE_ENTRY(g, l) {g, l},
+constexpr Tile kTiles[] = {DM_FOR_EACH_TILE(DM_TILE_ENTRY)};
+#undef DM_TILE_ENTRY
 
 bool tile_compiled(int G, int LPL) {
     for (const Tile& t : kTiles)
@@ -203,14 +199,7 @@ Tile col_tile(const dm_shape& s, const dm_discrete_params& p) {
 hipError_t launch_sweep(Tile t, const SweepArgs& a, dm_dtype dt, hipStream_t st) {
 #define DM_TILE_CASE(g, l) \
     if (t.G == g && t.LPL == l) return launch_tile<g, l>(a, dt, st);
-    DM_TILE_CASE(4, 1)
-    DM_TILE_CASE(4, 2)
-    DM_TILE_CASE(8, 4)
-    DM_TILE_CASE(16, 4)
-    DM_TILE_CASE(32, 3)
-    DM_TILE_CASE(32, 4)
-    DM_TILE_CASE(64, 3)
-    DM_TILE_CASE(64, 4)
+    DM_FOR_EACH_TILE(DM_TILE_CASE)
 #undef DM_TILE_CASE
     return hipErrorInvalidValue;
 }
@@ -218,14 +207,7 @@ hipError_t launch_sweep(Tile t, const SweepArgs& a, dm_dtype dt, hipStream_t st)
 hipError_t launch_adjoint(Tile t, const AdjArgs& a, dm_dtype dt, hipStream_t st) {
 #define DM_TILE_CASE(g, l) \
     if (t.G == g && t.LPL == l) return launch_adjoint_tile<g, l>(a, dt, st);
-    DM_TILE_CASE(4, 1)
-    DM_TILE_CASE(4, 2)
-    DM_TILE_CASE(8, 4)
-    DM_TILE_CASE(16, 4)
-    DM_TILE_CASE(32, 3)
-    DM_TILE_CASE(32, 4)
-    DM_TILE_CASE(64, 3)
-    DM_TILE_CASE(64, 4)
+    DM_FOR_EACH_TILE(DM_TILE_CASE)
 #undef DM_TILE_CASE
     return hipErrorInvalidValue;
 }
@@ -748,6 +730,16 @@ std::map<TuneKey, std::pair<Tile, Tile>> g_tune_cache;
 // shape, and writes the choice into p (tile_lanes/labels_per_lane for rows, the _v fields
 // for columns).  Allocates (and frees) scratch device memory; results are cached per
 // (W, H, K, cost dtype, minorant, max_pass) for the process.
+extern "C" int dm_default_tile(int K, int* tile_lanes, int* labels_per_lane) {
+    clear_error();
+    DM_REQUIRE(tile_lanes != nullptr && labels_per_lane != nullptr, DM_ERR_NULL, "null output");
+    DM_REQUIRE(K >= 1 && K <= 256, DM_ERR_SHAPE, "K=%d out of range [1, 256]", K);
+    const Tile t = default_tile(K);
+    *tile_lanes = t.G;
+    *labels_per_lane = t.LPL;
+    return DM_OK;
+}
+
 extern "C" int dm_autotune_tiles(dm_shape s, dm_dtype cost_dtype, dm_discrete_params* p, void* hip_stream) {
     clear_error();
     DM_REQUIRE(p != nullptr, DM_ERR_NULL, "params is NULL");

@@ -78,8 +78,12 @@ struct SweepArgs {
     float* rec_msg[9];   // record mode: messages written by pass s (s = 0: backward message pass)
 };
 
-// Offset that is outside every buffer: loads return 0, stores are dropped.
-constexpr unsigned kOOB = 0xFFFFFFF0u;
+// Offset that is outside every buffer (volumes are at most kMaxVolBytes): loads return 0,
+// stores are dropped, also for the vector chunks at kOOB + 16*k (no 32-bit wrap).
+// Cursor offsets that step below 0 wrap to >= 2^32 - 16 MiB (one node of the largest
+// volume), which the size limit also keeps out of range.
+constexpr unsigned kOOB = 0xFFFFFF00u;
+constexpr unsigned long long kMaxVolBytes = 0xFE000000ull;
 constexpr int kBufWord3 = 0x00020000;  // gfx9 raw buffer descriptor word 3
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
@@ -94,25 +98,55 @@ __device__ __forceinline__ float f16_bits_to_f(uint32_t b) {
     return (float)__builtin_bit_cast(_Float16, (unsigned short)(b & 0xFFFFu));
 }
 
-// Raw words of LPL consecutive elements of type TT, loaded with one vector buffer load
-// when the tile is full (all labels exist), else one scalar load per label.
+// NW consecutive dwords at byte offset off: vector buffer loads of up to 4 dwords (the
+// chunk offsets go into the instruction's immediate field).
+template <int NW>
+__device__ __forceinline__ void load_words(__amdgpu_buffer_rsrc_t r, unsigned off, uint32_t* w) {
+    if constexpr (NW >= 4) {
+        auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+        w[0] = v[0]; w[1] = v[1]; w[2] = v[2]; w[3] = v[3];
+        if constexpr (NW > 4) load_words<NW - 4>(r, off + 16u, w + 4);
+    } else if constexpr (NW == 3) {
+        auto v = __builtin_amdgcn_raw_buffer_load_b96(r, (int)off, 0, 0);
+        w[0] = v[0]; w[1] = v[1]; w[2] = v[2];
+    } else if constexpr (NW == 2) {
+        auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+        w[0] = v[0]; w[1] = v[1];
+    } else if constexpr (NW == 1) {
+        w[0] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+    }
+}
+
+template <int NW>
+__device__ __forceinline__ void store_words(__amdgpu_buffer_rsrc_t r, unsigned off, const uint32_t* w) {
+    using u4 = __attribute__((ext_vector_type(4))) unsigned;
+    using u3 = __attribute__((ext_vector_type(3))) unsigned;
+    using u2 = __attribute__((ext_vector_type(2))) unsigned;
+    if constexpr (NW >= 4) {
+        __builtin_amdgcn_raw_buffer_store_b128((u4){w[0], w[1], w[2], w[3]}, r, (int)off, 0, 0);
+        if constexpr (NW > 4) store_words<NW - 4>(r, off + 16u, w + 4);
+    } else if constexpr (NW == 3) {
+        __builtin_amdgcn_raw_buffer_store_b96((u3){w[0], w[1], w[2]}, r, (int)off, 0, 0);
+    } else if constexpr (NW == 2) {
+        __builtin_amdgcn_raw_buffer_store_b64((u2){w[0], w[1]}, r, (int)off, 0, 0);
+    } else if constexpr (NW == 1) {
+        __builtin_amdgcn_raw_buffer_store_b32(w[0], r, (int)off, 0, 0);
+    }
+}
+
+// Raw words of LPL consecutive elements of type TT: vector buffer loads when the tile is
+// full (all labels exist), else one scalar load per label (offsets of missing labels are
+// out of range).
 template <typename TT, int LPL, bool FULL>
 struct RawVec;
 
 template <int LPL, bool FULL>
 struct RawVec<float, LPL, FULL> {
     uint32_t w[LPL];
-    // off[i]: byte offset of element i (only off[0] used for the vector form)
+    // off0: byte offset of element 0 (vector form); offs[i]: of element i (scalar form)
     __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, unsigned off0, const unsigned (&offs)[LPL]) {
-        if constexpr (FULL && LPL == 4) {
-            auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off0, 0, 0);
-            w[0] = v[0]; w[1] = v[1]; w[2] = v[2]; w[3] = v[3];
-        } else if constexpr (FULL && LPL == 3) {
-            auto v = __builtin_amdgcn_raw_buffer_load_b96(r, (int)off0, 0, 0);
-            w[0] = v[0]; w[1] = v[1]; w[2] = v[2];
-        } else if constexpr (FULL && LPL == 2) {
-            auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off0, 0, 0);
-            w[0] = v[0]; w[1] = v[1];
+        if constexpr (FULL) {
+            load_words<LPL>(r, off0, w);
         } else {
 #pragma unroll
             for (int i = 0; i < LPL; ++i) w[i] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)offs[i], 0, 0);
@@ -123,15 +157,13 @@ struct RawVec<float, LPL, FULL> {
 
 template <int LPL, bool FULL>
 struct RawVec<_Float16, LPL, FULL> {
-    static constexpr bool kPacked = FULL && (LPL == 2 || LPL == 4);
+    // pairs of halves per dword when the lane's labels start 4-byte aligned (even LPL)
+    static constexpr bool kPacked = FULL && (LPL % 2 == 0);
     static constexpr int kWords = kPacked ? LPL / 2 : LPL;
     uint32_t w[kWords];
     __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t r, unsigned off0, const unsigned (&offs)[LPL]) {
-        if constexpr (FULL && LPL == 4) {
-            auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off0, 0, 0);
-            w[0] = v[0]; w[1] = v[1];
-        } else if constexpr (FULL && LPL == 2) {
-            w[0] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)off0, 0, 0);
+        if constexpr (kPacked) {
+            load_words<kWords>(r, off0, w);
         } else {
 #pragma unroll
             for (int i = 0; i < LPL; ++i) w[i] = __builtin_amdgcn_raw_buffer_load_b16(r, (int)offs[i], 0, 0);
@@ -146,20 +178,11 @@ struct RawVec<_Float16, LPL, FULL> {
 template <int LPL, bool FULL>
 __device__ __forceinline__ void store_f32(__amdgpu_buffer_rsrc_t r, unsigned off0, const unsigned (&offs)[LPL],
                                           const float (&v)[LPL]) {
-    if constexpr (FULL && LPL == 4) {
-        __builtin_amdgcn_raw_buffer_store_b128(
-            (__attribute__((ext_vector_type(4))) unsigned){__builtin_bit_cast(uint32_t, v[0]), __builtin_bit_cast(uint32_t, v[1]),
-                                                           __builtin_bit_cast(uint32_t, v[2]), __builtin_bit_cast(uint32_t, v[3])},
-            r, (int)off0, 0, 0);
-    } else if constexpr (FULL && LPL == 3) {
-        __builtin_amdgcn_raw_buffer_store_b96(
-            (__attribute__((ext_vector_type(3))) unsigned){__builtin_bit_cast(uint32_t, v[0]), __builtin_bit_cast(uint32_t, v[1]),
-                                                           __builtin_bit_cast(uint32_t, v[2])},
-            r, (int)off0, 0, 0);
-    } else if constexpr (FULL && LPL == 2) {
-        __builtin_amdgcn_raw_buffer_store_b64(
-            (__attribute__((ext_vector_type(2))) unsigned){__builtin_bit_cast(uint32_t, v[0]), __builtin_bit_cast(uint32_t, v[1])},
-            r, (int)off0, 0, 0);
+    if constexpr (FULL) {
+        uint32_t w[LPL];
+#pragma unroll
+        for (int i = 0; i < LPL; ++i) w[i] = __builtin_bit_cast(uint32_t, v[i]);
+        store_words<LPL>(r, off0, w);
     } else {
 #pragma unroll
         for (int i = 0; i < LPL; ++i) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v[i]), r, (int)offs[i], 0, 0);

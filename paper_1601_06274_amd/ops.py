@@ -81,15 +81,9 @@ class DiscreteResult:
 
 def tile_for(K: int):
     """Default (lanes per chain, labels per lane) the library picks for K labels."""
-    tiles = [(4, 1), (4, 2), (8, 4), (16, 4), (32, 3), (32, 4), (64, 3), (64, 4)]
-    best, waste = None, None
-    for g, l in tiles:
-        if g * l < K:
-            continue
-        w = g * l - K
-        if best is None or w < waste or (w == waste and g > best[0]):
-            best, waste = (g, l), w
-    return best
+    g, l = ctypes.c_int(0), ctypes.c_int(0)
+    L.check("dm_default_tile", L.lib().dm_default_tile(int(K), ctypes.byref(g), ctypes.byref(l)))
+    return g.value, l.value
 
 
 def solve_discrete(cost, w_h, w_v, *, T=3, n_iters=10, n_half_steps=0, minorant="iterative",

@@ -83,6 +83,7 @@ def test_null_and_shape_and_workspace_errors():
     assert _solve(L.DmShape(16, 0, 8), p) == -2
     assert _solve(L.DmShape(16, 8, 300), p) == -2
     assert _solve(L.DmShape(16384, 16384, 4), p) == -2  # FP32 volume beyond 32-bit offsets
+    assert _solve(L.DmShape(16384, 16300, 4), p) == -2  # 4272947200 bytes > 0xFE000000
     assert "offset range" in L.lib().dm_last_error_message().decode()
     assert _solve(L.DmShape(16, 8, 8), p, dtype=7) == -4
     assert _solve(L.DmShape(16, 8, 8), p, ws=ctypes.c_void_p(4096), ws_bytes=16) == -5
@@ -96,3 +97,14 @@ def test_cost_volume_validation():
     cp = L.DmCostParams(3, 0.3, 0.1, 0.1)
     assert lib.dm_build_cost_volume(None, fake, L.DmShape(8, 8, 4), ctypes.byref(cp), 0, fake, None, None, None) == -1
     assert lib.dm_build_cost_volume(fake, fake, L.DmShape(8, 8, 4), ctypes.byref(cp), 5, fake, None, None, None) == -4
+
+
+def test_default_tile_host_query():
+    lib = L.lib()
+    g, l = ctypes.c_int(0), ctypes.c_int(0)
+    for K, want in [(192, (64, 3)), (128, (32, 4)), (5, (4, 2)), (1, (4, 1)), (256, (64, 4)), (96, (32, 3))]:
+        assert lib.dm_default_tile(K, ctypes.byref(g), ctypes.byref(l)) == 0
+        assert (g.value, l.value) == want, K
+        assert g.value * l.value >= K
+    assert lib.dm_default_tile(300, ctypes.byref(g), ctypes.byref(l)) == -2
+    assert lib.dm_default_tile(8, None, ctypes.byref(l)) == -1
