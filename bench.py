@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="for rocprofv3 counter runs: a known-size elementwise kernel, then 2 dual iterations "
+                         "of the frame; prints the probe size")
     return ap.parse_args()
 
 
@@ -94,6 +97,7 @@ def main():
     import synth
     import paper_1601_06274_amd as P
     from paper_1601_06274_amd import ops
+    from paper_1601_06274_amd.traffic import sweep_source_hash
 
     wl = WORKLOAD
     W, H, K = wl["W"], wl["H"], wl["K"]
@@ -132,6 +136,17 @@ def main():
     grad_cost = torch.empty((H, W, K), dtype=torch.float32, device=dev)
     grad_wh = torch.empty((H, W - 1), dtype=torch.float32, device=dev)
     grad_wv = torch.empty((H - 1, W), dtype=torch.float32, device=dev)
+
+    if args.traffic_probe:
+        n = 1 << 28  # 1 GiB of FP32: the in-place multiply reads and writes it once
+        buf = torch.ones(n, dtype=torch.float32, device=dev)
+        for _ in range(3):
+            buf.mul_(1.0)
+        ops.build_cost_volume(IL, IR, K, dtype=torch.float16, cost_out=cost, w_h=w_h, w_v=w_v)
+        ops.solve_discrete(cost, w_h, w_v, dual=dual, workspace=ws_d, labels=labels, **dict(dkw, n_iters=2))
+        torch.cuda.synchronize()
+        print(json.dumps({"traffic_probe_bytes": 4 * n}), flush=True)
+        return 0
 
     def forward():
         ops.build_cost_volume(IL, IR, K, dtype=torch.float16, cost_out=cost, w_h=w_h, w_v=w_v)
@@ -187,10 +202,19 @@ def main():
         try:
             with open(tpath) as f:
                 t = json.load(f)
-            if t.get("kernel_source_hash") == _sweep_source_hash():
+            if t.get("kernel_source_hash") == sweep_source_hash():
                 traffic = t.get("bytes_per_launch")
         except Exception:
             traffic = None
+
+    # FP16 storage: energy of this labeling on the unrounded (FP32) costs vs the FP32-path
+    # labeling, FP64 sums (outside the timed region)
+    cost32 = torch.empty((H, W, K), dtype=torch.float32, device=dev)
+    ops.build_cost_volume(IL, IR, K, dtype=torch.float32, cost_out=cost32, w_h=w_h, w_v=w_v)
+    res32 = ops.solve_discrete(cost32, w_h, w_v, **dkw)
+    e16 = _grid_energy(cost32, w_h, w_v, labels, wl["T"])
+    e32 = _grid_energy(cost32, w_h, w_v, res32.labels, wl["T"])
+    del cost32, res32
 
     N = H * W * K
     updates = N * (8 * wl["n_iters"] + 2)  # forward label-node updates per frame
@@ -240,6 +264,7 @@ def main():
             "sweep_v_GBps": (prof["sweep_v"][2] / prof["sweep_v"][1] / 1e6) if prof["sweep_v"][1] else None,
             "final_per_launch": prof["sweep_final"][1] / max(prof["sweep_final"][0], 1),
         },
+        "fp16_storage": {"energy_fp16_labels": e16, "energy_fp32_labels": e32, "rel_diff": (e16 - e32) / e32},
         "lower_bound": float(bounds[0]),
         "energy": float(bounds[1]),
         "alg_gb_per_sweep_h": per_launch_gb,
@@ -250,13 +275,14 @@ def main():
     return 0
 
 
-def _sweep_source_hash():
-    import hashlib
-    h = hashlib.sha256()
-    for fn in ["dmm_kernels.h", "wave.h"]:
-        with open(os.path.join(ROOT, "paper_1601_06274_amd", "csrc", fn), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+def _grid_energy(cost, w_h, w_v, labels, T):
+    """E(x) = sum of unaries + truncated-linear pairwise terms, FP64 sums (torch on the GPU)."""
+    import torch
+    lab = labels.long()
+    e = cost.gather(2, lab.unsqueeze(2)).double().sum()
+    dh = (lab[:, 1:] - lab[:, :-1]).abs().clamp(max=T).double()
+    dv = (lab[1:, :] - lab[:-1, :]).abs().clamp(max=T).double()
+    return float((e + (w_h.double() * dh).sum() + (w_v.double() * dv).sum()).item())
 
 
 if __name__ == "__main__":

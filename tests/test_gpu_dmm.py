@@ -152,6 +152,14 @@ def test_fp16_cost_storage():
     res, ref, th = _run_both(th64.astype(np.float16), w_h, w_v, 3, 4, theta_dtype=torch.float16, name="fp16")
     np.testing.assert_array_equal(th, ocv.round_half(th64))
     _check(res, ref, th, w_h, w_v, 3, "fp16")
+    # energy error of FP16 storage: the GPU labeling scored on the unrounded costs against
+    # the FP64 oracle's own labeling of the unrounded problem
+    ref64 = odmm.solve_discrete(th64, w_h.astype(np.float64), w_v.astype(np.float64), 3, 4)
+    e16 = oenergy.grid_energy(th64, w_h, w_v, 3, res.labels.cpu().numpy())
+    e64 = oenergy.grid_energy(th64, w_h, w_v, 3, ref64.labels)
+    rel = (e16 - e64) / e64
+    print(f"[parity] fp16 storage energy error vs fp64: E16={e16:.6f} E64={e64:.6f} rel={rel:.3e}", flush=True)
+    assert abs(rel) <= 5e-3
 
 
 def test_warm_start_resume():
