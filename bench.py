@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched (64 uneven instances) and differentiation (8 x 960x320x96) workloads")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for rocprofv3 counter runs: a known-size elementwise kernel, then 2 dual iterations "
                          "of the frame; prints the probe size")
@@ -82,6 +84,134 @@ def cpu_baseline(pair, wl, target_s):
             "sample": f"{reps}x (horizontal half-step on {rows} rows x {wl['W']} + vertical half-step on "
                       f"{cols} columns x {wl['H']}) of the frame's cost volume, K={wl['K']}, FP64 numpy, "
                       f"{el:.1f} s, single thread"}
+
+
+def _timed(fn, reps, torch):
+    """Mean milliseconds of fn() over reps runs (after one untimed run), stream-synchronised."""
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def batched_extra(torch, ops, dev, n=64, seed=4000, n_iters=20, T=3, reps=3):
+    """64 uneven instances (W in [160, 1280], H in [120, 720], K in {32, 64, 128, 192}) of
+    the stereo generator: the batched plan (FP16 cost, one hipGraph launch) against the
+    plain single-instance FP32 forward on the same GPU, Dual_MM 20 iterations each."""
+    import synth
+    specs = synth.batch_specs(n, seed=seed)
+    inst16, inst32 = [], []
+    for sp in specs:
+        pair = synth.stereo_pair(sp.W, sp.H, sp.K, seed=sp.seed)
+        IL = torch.from_numpy(pair.left).to(dev)
+        IR = torch.from_numpy(pair.right).to(dev)
+        c16, wh, wv = ops.build_cost_volume(IL, IR, sp.K, dtype=torch.float16)
+        c32, _, _ = ops.build_cost_volume(IL, IR, sp.K, dtype=torch.float32)
+        inst16.append(dict(cost=c16, w_h=wh, w_v=wv))
+        inst32.append(dict(cost=c32, w_h=wh, w_v=wv))
+    nodes = sum(sp.W * sp.H * sp.K for sp in specs)
+    updates = nodes * (8 * n_iters + 2)
+    t0 = time.perf_counter()
+    plan = ops.BatchedPlan(inst16, T=T, n_iters=n_iters)
+    plan_s = time.perf_counter() - t0
+    try:
+        ms_b = _timed(plan.run, reps, torch)
+        dev_gb = plan.device_bytes / 1e9
+    finally:
+        plan.close()
+    ws = None
+    duals = [torch.empty(d["cost"].shape, dtype=torch.float32, device=dev) for d in inst32]
+
+    def plain():
+        nonlocal ws
+        for d, lam in zip(inst32, duals):
+            r = ops.solve_discrete(d["cost"], d["w_h"], d["w_v"], T=T, n_iters=n_iters, dual=lam, workspace=ws,
+                                   want_bounds=False, want_minmarg=False)
+            if ws is None or r.workspace.numel() > ws.numel():
+                ws = r.workspace
+    ms_p = _timed(plain, reps, torch)
+    return {"workload": f"{n} uneven stereo instances, W in [160,1280], H in [120,720], K in {{32,64,128,192}}, "
+                        f"seed {seed}; Dual_MM {n_iters} its, T={T}",
+            "label_nodes": nodes, "plan_build_s": plan_s, "plan_device_GB": dev_gb,
+            "batched_fp16_ms": ms_b, "batched_fp16_updates_per_s": updates / (ms_b * 1e-3),
+            "plain_fp32_ms": ms_p, "plain_fp32_updates_per_s": updates / (ms_p * 1e-3),
+            "speedup_vs_plain_fp32": ms_p / ms_b}
+
+
+def diff_extra(torch, ops, dev, n=8, W=960, H=320, K=96, n_iters=20, T=3, warps=5, iters=10, seed=5000, reps=2):
+    """Differentiation workload: 8 frames 960x320, K=96, FP16 cost; forward (Dual_MM 20 its
+    with dual checkpoints + refinement 5 x 10 steps) and backward (dL/dcost, dL/dw) per frame,
+    against the plain FP32 forward of the same frames."""
+    import ctypes
+    import synth
+    import paper_1601_06274_amd as P
+    frames = []
+    for i in range(n):
+        pair = synth.stereo_pair(W, H, K, seed=seed + i, slope=0.08, occlusion_bands=2)
+        IL = torch.from_numpy(pair.left).to(dev)
+        IR = torch.from_numpy(pair.right).to(dev)
+        c16, wh, wv = ops.build_cost_volume(IL, IR, K, dtype=torch.float16)
+        c32, _, _ = ops.build_cost_volume(IL, IR, K, dtype=torch.float32)
+        frames.append((c16, c32, wh, wv))
+    dkw = dict(T=T, n_iters=n_iters)
+    rkw = dict(C=3.0, n_warps=warps, n_iters=iters)
+    lib = P.lib()
+    shp = P._lib.DmShape(W, H, K)
+    dp = ops.discrete_params(keep_checkpoints=True, **dkw)
+    ws_d = torch.empty(lib.dm_solve_discrete_workspace(shp, P._lib.DM_F16, ctypes.byref(dp)), dtype=torch.uint8,
+                       device=dev)
+    ws_db = torch.empty(lib.dm_solve_discrete_backward_workspace(shp, ctypes.byref(dp)), dtype=torch.uint8, device=dev)
+    rp = ops.refine_params(keep_tape=True, **rkw)
+    ws_r = torch.empty(lib.dm_refine_continuous_workspace(shp, ctypes.byref(rp)), dtype=torch.uint8, device=dev)
+    ws_rb = torch.empty(lib.dm_refine_continuous_backward_workspace(shp, ctypes.byref(rp)), dtype=torch.uint8,
+                        device=dev)
+    gen = torch.Generator(device=dev).manual_seed(seed)
+    G_m = torch.randn((H, W, K), generator=gen, device=dev)
+    G_u = torch.randn((H, W), generator=gen, device=dev)
+    dual = torch.empty((H, W, K), dtype=torch.float32, device=dev)
+    mm = torch.empty_like(dual)
+    lab = torch.empty((H, W), dtype=torch.int32, device=dev)
+    u = torch.empty((H, W), dtype=torch.float32, device=dev)
+    gc = torch.empty_like(dual)
+    gwh = torch.empty((H, W - 1), dtype=torch.float32, device=dev)
+    gwv = torch.empty((H - 1, W), dtype=torch.float32, device=dev)
+    grad_lpw = []
+
+    def fwd_bwd():
+        grad_lpw.clear()
+        for c16, _, wh, wv in frames:
+            ops.solve_discrete(c16, wh, wv, dual=dual, workspace=ws_d, labels=lab, minmarg=mm, want_bounds=True,
+                               keep_checkpoints=True, **dkw)
+            ops.refine_continuous(c16, lab, wh, wv, workspace=ws_r, u_out=u, keep_tape=True, **rkw)
+            ops.refine_continuous_backward(G_u, c16, wh, wv, ws_r, grad_cost=gc, grad_w_h=gwh, grad_w_v=gwv,
+                                           accumulate=False, workspace=ws_rb, **rkw)
+            ops.solve_discrete_backward(c16, wh, wv, dual, ws_d, grad_minmarg=G_m, grad_lb=1.0, grad_cost=gc,
+                                        grad_w_h=gwh, grad_w_v=gwv, accumulate=True, workspace=ws_db, **dkw)
+            # dL/dlambda_pw: the weights are lambda_pw * exp(...), so sum(dL/dw * w) / lambda_pw
+            grad_lpw.append((gwh * wh).sum() + (gwv * wv).sum())
+
+    ws32 = None
+
+    def plain32():
+        nonlocal ws32
+        for _, c32, wh, wv in frames:
+            r = ops.solve_discrete(c32, wh, wv, dual=dual, workspace=ws32, labels=lab, want_bounds=False,
+                                   want_minmarg=False, **dkw)
+            ws32 = r.workspace
+            ops.refine_continuous(c32, lab, wh, wv, u_out=u, workspace=ws_r, **rkw)
+
+    ms_fb = _timed(fwd_bwd, reps, torch)
+    ms_32 = _timed(plain32, reps, torch)
+    finite = bool(all(torch.isfinite(g).item() for g in grad_lpw))
+    return {"workload": f"{n} frames {W}x{H}, K={K}, FP16 cost; Dual_MM {n_iters} its (dual checkpoints) + "
+                        f"refinement {warps}x{iters}; backward dL/dcost, dL/dw (and dL/dlambda_pw)",
+            "fwd_bwd_fp16_ms_per_batch": ms_fb, "fwd_bwd_fp16_ms_per_frame": ms_fb / n,
+            "plain_fp32_forward_ms_per_batch": ms_32, "ratio_fwd_bwd_to_plain_fwd": ms_fb / ms_32,
+            "checkpoint_GB": ws_d.numel() / 1e9, "backward_workspace_GB": ws_db.numel() / 1e9,
+            "grad_finite": finite}
 
 
 def main():
@@ -269,6 +399,12 @@ def main():
         "energy": float(bounds[1]),
         "alg_gb_per_sweep_h": per_launch_gb,
     }
+    if not args.no_extras:
+        del ws_d, ws_db, ws_r, ws_rb
+        torch.cuda.empty_cache()
+        out["batched"] = batched_extra(torch, ops, dev)
+        torch.cuda.empty_cache()
+        out["differentiation"] = diff_extra(torch, ops, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pair, wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -536,37 +536,23 @@ struct AdjWalker {
             store_f32<LPL, FULL>(r_abar, sc.f, os, outv);
         } else {
             // replay the forward step (same arithmetic as the forward walker)
-            float v[LPL], m[LPL], u[LPL], vn[LPL];
+            float v[LPL], m[LPL], vn[LPL];
 #pragma unroll
             for (int i = 0; i < LPL; ++i) {
                 v[i] = r[i] + carry[i];
                 m[i] = v[i] + (out ? nd.rmsg.get(i) : 0.0f);
             }
+            // message input: v (naive, final) or u = rc - gamma*m (iterative; the updated
+            // r' + carry up to the node constant gamma*mmin)
             float mmin = lane_min(m), bmin;
-            if constexpr (KIND == kAdjIter) {
 #pragma unroll
-                for (int i = 0; i < LPL; ++i) u[i] = (FULL || lv[i]) ? __builtin_fmaf(-gamma, m[i], v[i]) : kBig;
-                bmin = lane_min(u);
-            } else {
-                bmin = lane_min(v);
-            }
+            for (int i = 0; i < LPL; ++i)
+                vn[i] = KIND == kAdjIter ? ((FULL || lv[i]) ? __builtin_fmaf(-gamma, m[i], v[i]) : kBig) : v[i];
+            bmin = lane_min(vn);
             group_min2<G>(mmin, bmin);
-            float vmin;
-            if constexpr (KIND == kAdjIter) {
-#pragma unroll
-                for (int i = 0; i < LPL; ++i) {
-                    const float d = (FULL || lv[i]) ? gamma * (m[i] - mmin) : 0.0f;
-                    vn[i] = v[i] - d;
-                }
-                vmin = __builtin_fmaf(gamma, mmin, bmin);
-            } else {
-#pragma unroll
-                for (int i = 0; i < LPL; ++i) vn[i] = v[i];
-                vmin = bmin;
-            }
             const int kstar = group_argmin_eq<G, LPL, FULL>(m, mmin, lv, sub);
             if (out) {
-                msg_adjoint<DTM>(vn, vmin, nd.w, cb, vbar, wl, zl);
+                msg_adjoint<DTM>(vn, bmin, nd.w, cb, vbar, wl, zl);
             } else {
 #pragma unroll
                 for (int i = 0; i < LPL; ++i) vbar[i] = 0.0f;
@@ -578,11 +564,11 @@ struct AdjWalker {
                 al += (FULL || lv[i]) ? (KIND == kAdjFinal ? nd.gx.get(i) : ab[i]) : 0.0f;
             group_sum2<G>(wl, zl);
             al = group_sum<G>(al);
-            const int a_b = group_argmin_eq<G, LPL, FULL>(KIND == kAdjIter ? u : v, bmin, lv, sub);
+            const int a_b = group_argmin_eq<G, LPL, FULL>(vn, bmin, lv, sub);
             float rbar[LPL], revb[LPL];
             if constexpr (KIND == kAdjIter) {
-                // vmin = min u + gamma mmin, u = rc - gamma m, d = gamma (m - mmin),
-                // r' = r - d, v' = rc - d; dL/dmmin sums to gamma * sum(dL/dr')
+                // message of u = rc - gamma m, d = gamma (m - mmin), r' = r - d;
+                // dL/dmmin sums to gamma * sum(dL/dr')
                 const float mminb = gamma * al;
 #pragma unroll
                 for (int i = 0; i < LPL; ++i) {

@@ -451,27 +451,24 @@ struct Walker {
                 m[i] = v[i] + ((TAIL && !has_next) ? 0.0f : rv);  // no message beyond the chain end
             }
             // The minimum of the message input is reduced together with mmin.  Naive
-            // update and final pass: v = r + carry does not depend on mmin.  Iterative
-            // update: v = rc - gamma*(m - mmin) with rc = r + carry, so
-            // min v = min(rc - gamma*m) + gamma*mmin, again a reduction independent of mmin.
+            // update and final pass: the input is v = r + carry.  Iterative update: the
+            // updated r' + carry = rc - gamma*(m - mmin) (rc = r + carry) differs from
+            // u = rc - gamma*m by the node constant gamma*mmin, and messages are defined up
+            // to constants, so the message is taken of u: it does not wait for mmin.
             float mmin = lane_min(m), bmin;
             if constexpr (KIND == 1) {
-                float u[LPL];
 #pragma unroll
-                for (int i = 0; i < LPL; ++i) u[i] = (FULL || lv[i]) ? __builtin_fmaf(-gamma, m[i], v[i]) : kBig;
-                bmin = lane_min(u);
-            } else {
-                bmin = lane_min(v);
+                for (int i = 0; i < LPL; ++i) v[i] = (FULL || lv[i]) ? __builtin_fmaf(-gamma, m[i], v[i]) : kBig;
             }
+            bmin = lane_min(v);
             group_min2<G>(mmin, bmin);
-            vmin = KIND == 1 ? __builtin_fmaf(gamma, mmin, bmin) : bmin;
+            vmin = bmin;
             if constexpr (KIND == 1 || KIND == 2) {
                 float nl[LPL];
 #pragma unroll
                 for (int i = 0; i < LPL; ++i) {
                     float d = (KIND == 1 ? gamma : inv_n) * (m[i] - mmin);
                     d = (FULL || lv[i]) ? d : 0.0f;
-                    if (KIND == 1) v[i] -= d;
                     nl[i] = __builtin_fmaf(sign, d, lamv[i]);
                 }
                 unsigned os[LPL];
