@@ -337,6 +337,31 @@ def main():
         except Exception:
             traffic = None
 
+    # The same step with the forward keeping every pass's messages and intermediate duals
+    # (keep_checkpoints = 2: about 7 volumes per half-step in HBM, no recompute).
+    del ws_d, ws_db
+    torch.cuda.empty_cache()
+    dp2 = ops.discrete_params(keep_checkpoints=2, **dkw)
+    ws_d2 = torch.empty(lib.dm_solve_discrete_workspace(shp, P._lib.DM_F16, ctypes.byref(dp2)), dtype=torch.uint8,
+                        device=dev)
+    ws_db2 = torch.empty(lib.dm_solve_discrete_backward_workspace(shp, ctypes.byref(dp2)), dtype=torch.uint8,
+                         device=dev)
+
+    def step_record():
+        ops.build_cost_volume(IL, IR, K, dtype=torch.float16, cost_out=cost, w_h=w_h, w_v=w_v)
+        ops.solve_discrete(cost, w_h, w_v, dual=dual, workspace=ws_d2, labels=labels, minmarg=minmarg,
+                           want_bounds=True, keep_checkpoints=2, **dkw)
+        ops.refine_continuous(cost, labels, w_h, w_v, workspace=ws_r, u_out=u, keep_tape=True, **rkw)
+        ops.refine_continuous_backward(G_u, cost, w_h, w_v, ws_r, grad_cost=grad_cost, grad_w_h=grad_wh,
+                                       grad_w_v=grad_wv, accumulate=False, workspace=ws_rb, **rkw)
+        ops.solve_discrete_backward(cost, w_h, w_v, dual, ws_d2, grad_minmarg=G_m, grad_lb=g_lb, grad_cost=grad_cost,
+                                    grad_w_h=grad_wh, grad_w_v=grad_wv, accumulate=True, workspace=ws_db2,
+                                    keep_checkpoints=2, **dkw)
+    ms_record = _timed(step_record, max(2, args.steps // 2), torch)
+    record_gb = (ws_d2.numel() + ws_db2.numel()) / 1e9
+    del ws_d2, ws_db2
+    torch.cuda.empty_cache()
+
     # FP16 storage: energy of this labeling on the unrounded (FP32) costs vs the FP32-path
     # labeling, FP64 sums (outside the timed region)
     cost32 = torch.empty((H, W, K), dtype=torch.float32, device=dev)
@@ -374,6 +399,8 @@ def main():
                        "solve_discrete_backward"],
         },
         "fwd_bwd_ms_per_frame": ms_per_step,
+        "fwd_bwd_record_all": {"ms_per_frame": ms_record, "workspace_GB": record_gb,
+                               "note": "forward keeps every pass's messages (keep_checkpoints=2), no recompute"},
         "forward_only": {"ms_per_frame": fwd_ms, "label_node_updates_per_s": updates / (fwd_ms * 1e-3)},
         "grad_finite": grad_finite,
         "roofline": {
@@ -400,7 +427,7 @@ def main():
         "alg_gb_per_sweep_h": per_launch_gb,
     }
     if not args.no_extras:
-        del ws_d, ws_db, ws_r, ws_rb
+        del ws_r, ws_rb
         torch.cuda.empty_cache()
         out["batched"] = batched_extra(torch, ops, dev)
         torch.cuda.empty_cache()

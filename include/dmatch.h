@@ -115,9 +115,14 @@ typedef struct {
     int   labels_per_lane;  /* row chains: 0 = automatic; else with tile_lanes*lpl >= K */
     int   tile_lanes_v;     /* column chains: 0 = same as rows (see dm_autotune_tiles)  */
     int   labels_per_lane_v;
-    int   keep_checkpoints; /* 1: the workspace keeps the dual before every half-step
-                               (one FP32 volume each; the size query includes them) for
-                               dm_solve_discrete_backward                                */
+    int   keep_checkpoints; /* for dm_solve_discrete_backward (the size query includes
+                               what is kept):
+                               0: nothing kept;
+                               1: the dual before every half-step (one FP32 volume per
+                                  half-step; the backward recomputes the messages);
+                               2: also every pass's messages and the duals between passes
+                                  (2*P + 1 volumes per half-step, P = update passes; the
+                                  backward recomputes nothing)                          */
 } dm_discrete_params;
 
 size_t dm_solve_discrete_workspace(dm_shape s, dm_dtype cost_dtype, const dm_discrete_params* p);
@@ -152,14 +157,15 @@ int dm_autotune_tiles(dm_shape s, dm_dtype cost_dtype, dm_discrete_params* p, vo
  * before that half-step, and of the other family at the final dual (unique optima there
  * assumed).  Labels carry no gradient.
  *   dual          [H][W][K] the final dual of the forward call.
- *   fwd_workspace the forward's workspace, run with keep_checkpoints = 1 and the same
- *                 parameters, unchanged since.
+ *   fwd_workspace the forward's workspace, run with keep_checkpoints = 1 or 2 and the
+ *                 same parameters, unchanged since.
  *   grad_cost     [H][W][K] float32 dL/dcost; grad_w_h, grad_w_v dL/dw (may be NULL).
  *   accumulate    0: outputs overwritten; 1: gradients added.
  * Per half-step (in reverse) the forward passes are recomputed from the checkpoint,
- * keeping every pass's messages, then the passes are differentiated chain by chain.
- * The backward workspace holds (max_pass + 1) message volumes, max_pass - 1 dual
- * volumes, three adjoint volumes and FP64 edge accumulators. */
+ * keeping every pass's messages (keep_checkpoints = 1; with 2 the forward kept them),
+ * then the passes are differentiated chain by chain.  The backward workspace holds
+ * (max_pass + 1) message volumes and max_pass - 1 dual volumes (2 and 0 with
+ * keep_checkpoints = 2), three adjoint volumes and FP64 edge accumulators. */
 size_t dm_solve_discrete_backward_workspace(dm_shape s, const dm_discrete_params* p);
 
 int dm_solve_discrete_backward(const float* grad_minmarg, double grad_lb, const void* cost,

@@ -218,12 +218,15 @@ double sweep_bytes(const SweepArgs& a, dm_dtype dt) {
     const double b = a.theta != nullptr ? (dt == DM_F16 ? 2.0 : 4.0) : 0.0;
     const double nodes = (double)a.n * a.n_chains * a.K;
     double per = 0.0;
-    switch (a.mode) {
+    // record mode (dual checkpoints with every pass's messages) also stores the last
+    // pass's messages
+    const double rec = (a.mode & kRecordFlag) ? 4.0 : 0.0;
+    switch (a.mode & ~kRecordFlag) {
         case kModeIterative:
-            per = b + 8.0;                                 // R0: cost, dual; message out
+            per = b + 8.0 + rec;                           // R0: cost, dual; message out
             for (int s = 0; s < a.n_pass; ++s) per += (s < a.n_pass - 1) ? b + 16.0 : b + 12.0;
             break;
-        case kModeNaive: per = (b + 8.0) + (b + 12.0); break;
+        case kModeNaive: per = (b + 8.0) + (b + 12.0) + rec; break;
         case kModeOptimum: per = b + 4.0; break;
         case kModeFinal: per = (b + 8.0) + (b + 8.0) + (a.minmarg != nullptr ? 4.0 : 0.0); break;
         default: break;
@@ -245,7 +248,20 @@ struct WsLayout {
     size_t vol_bytes;
     long long max_chains;
     int n_slots, n_partial;
+    int slab_vols;  // FP32 volumes kept per half-step
 };
+
+// Update passes of a half-step (the adjoint's P).
+int pass_count(const dm_discrete_params& p) { return p.minorant == DM_MINORANT_ITERATIVE ? p.max_pass : 1; }
+
+// Volumes kept per half-step: none; its input dual (checkpoint, messages recomputed in the
+// backward); or its input dual, the messages of every pass (P + 1) and the duals after
+// update passes 1 .. P-1 (recorded in the forward, no recompute).
+int slab_volumes(const dm_discrete_params& p) {
+    if (p.keep_checkpoints == 1) return 1;
+    if (p.keep_checkpoints == 2) return 1 + (pass_count(p) + 1) + (pass_count(p) - 1);
+    return 0;
+}
 
 constexpr int kEnergyBlocks = 1024;
 
@@ -269,7 +285,8 @@ WsLayout layout(const dm_shape& s, const dm_discrete_params& p) {
     off = align_up(off + (size_t)s.W * s.H * sizeof(int), 256);
     L.vol_bytes = align_up(vol * sizeof(float), 256);
     L.ckpt = off;
-    if (p.keep_checkpoints) off += (size_t)S * L.vol_bytes;  // dual before every half-step
+    L.slab_vols = slab_volumes(p);
+    off += (size_t)S * L.slab_vols * L.vol_bytes;  // per half-step: its input dual (+ records)
     L.total = off;
     return L;
 }
@@ -293,7 +310,7 @@ int validate_params(const dm_shape& s, const dm_discrete_params* p) {
                    "gamma[max_pass-1] must be 1 for a maximal minorant (got %g)", (double)p->gamma[p->max_pass - 1]);
     }
     DM_REQUIRE(p->warm_start == 0 || p->warm_start == 1, DM_ERR_PARAM, "warm_start must be 0 or 1");
-    DM_REQUIRE(p->keep_checkpoints == 0 || p->keep_checkpoints == 1, DM_ERR_PARAM, "keep_checkpoints must be 0 or 1");
+    DM_REQUIRE(p->keep_checkpoints >= 0 && p->keep_checkpoints <= 2, DM_ERR_PARAM, "keep_checkpoints must be 0, 1 or 2");
     if (p->tile_lanes != 0 || p->labels_per_lane != 0) {
         DM_REQUIRE(tile_compiled(p->tile_lanes, p->labels_per_lane), DM_ERR_UNSUPPORTED,
                    "tile %d lanes x %d labels is not compiled in", p->tile_lanes, p->labels_per_lane);
@@ -359,7 +376,12 @@ extern "C" int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const fl
     // With checkpoints, half-step k reads the dual from ckpt[k] and writes ckpt[k+1] (the
     // last one writes dual_inout): the checkpoints cost no extra traffic.
     float* ckpt0 = reinterpret_cast<float*>(ws + L.ckpt);
-    auto ckpt = [&](int k) { return reinterpret_cast<float*>(ws + L.ckpt + (size_t)k * L.vol_bytes); };
+    auto slab_vol = [&](int k, int i) {
+        return reinterpret_cast<float*>(ws + L.ckpt + ((size_t)k * L.slab_vols + i) * L.vol_bytes);
+    };
+    auto ckpt = [&](int k) { return slab_vol(k, 0); };
+    const int P = pass_count(*p);
+    const bool record = p->keep_checkpoints == 2;
     const bool use_ckpt = p->keep_checkpoints && S > 0;
     if (use_ckpt) {
         ProfScope ps(DM_PROF_OTHER, 8.0 * vol, stream);
@@ -416,6 +438,12 @@ extern "C" int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const fl
         if (use_ckpt) {
             a.lam_in = ckpt(k);
             a.lam = (k + 1 < S) ? ckpt(k + 1) : dual_inout;
+        }
+        if (record) {
+            // every pass's messages and intermediate duals into the half-step's slab
+            a.mode |= kRecordFlag;
+            for (int i = 0; i <= P && i < 9; ++i) a.rec_msg[i] = slab_vol(k, 1 + i);
+            for (int i = 1; i < P && i < 8; ++i) a.rec_lam[i] = slab_vol(k, P + 1 + i);
         }
         DM_HIP_TRY(launch_sweep_prof(k % 2 == 0 ? tile : tile_v, a, cost_dtype, stream), "half-step launch");
     }
@@ -474,7 +502,9 @@ struct BwdLayout {
 
 BwdLayout bwd_layout(const dm_shape& s, const dm_discrete_params& p) {
     BwdLayout L{};
-    L.P = p.minorant == DM_MINORANT_ITERATIVE ? p.max_pass : 1;
+    // recompute volumes: every pass of a half-step, or (records kept by the forward) only
+    // the final pass's two
+    L.P = p.keep_checkpoints == 2 ? 1 : pass_count(p);
     L.vol = align_up((size_t)s.W * s.H * s.K * sizeof(float), 256);
     size_t off = 0;
     L.msg = off;
@@ -517,7 +547,8 @@ extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad
                "cost, dual, grad_cost and the forward workspace are required");
     DM_REQUIRE(s.W == 1 || w_h != nullptr, DM_ERR_NULL, "w_h is required when W > 1");
     DM_REQUIRE(s.H == 1 || w_v != nullptr, DM_ERR_NULL, "w_v is required when H > 1");
-    DM_REQUIRE(p->keep_checkpoints == 1, DM_ERR_PARAM, "the forward must have been run with keep_checkpoints = 1");
+    DM_REQUIRE(p->keep_checkpoints == 1 || p->keep_checkpoints == 2, DM_ERR_PARAM,
+               "the forward must have been run with keep_checkpoints = 1 or 2");
     DM_REQUIRE(accumulate == 0 || accumulate == 1, DM_ERR_PARAM, "accumulate must be 0 or 1");
     const WsLayout LF = layout(s, *p);
     DM_REQUIRE(fwd_workspace_bytes >= LF.total, DM_ERR_WORKSPACE, "forward workspace %zu bytes, need %zu",
@@ -670,15 +701,25 @@ extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad
         if (st != DM_OK) return st;
     }
     // 3. half-steps in reverse: recompute from the checkpoint, then differentiate
+    const int PF = pass_count(*p);
     for (int k = S - 1; k >= 0; --k) {
-        const float* ck = reinterpret_cast<const float*>(fws + LF.ckpt + (size_t)k * LF.vol_bytes);
+        auto fslab = [&](int i) {
+            return reinterpret_cast<const float*>(fws + LF.ckpt + ((size_t)k * LF.slab_vols + i) * LF.vol_bytes);
+        };
+        const float* ck = fslab(0);
         const bool h = (k % 2) == 0;
-        SweepArgs a = h ? rows : cols;
-        a.mode = a.mode | kRecordFlag;
-        a.lam_in = ck;
-        a.lam = const_cast<float*>(ck);
-        DM_HIP_TRY(launch_sweep(h ? tile : tile_v, a, cost_dtype, stream), "half-step recompute");
         AdjArgs b = adj_from(h ? rows : cols, h ? gwh : gwv);
+        if (p->keep_checkpoints == 2) {
+            // the forward kept this half-step's messages and intermediate duals
+            for (int i = 0; i <= PF && i < 9; ++i) b.rec_msg[i] = fslab(1 + i);
+            for (int i = 1; i < PF && i < 8; ++i) b.rec_lam[i] = fslab(PF + 1 + i);
+        } else {
+            SweepArgs a = h ? rows : cols;
+            a.mode = a.mode | kRecordFlag;
+            a.lam_in = ck;
+            a.lam = const_cast<float*>(ck);
+            DM_HIP_TRY(launch_sweep(h ? tile : tile_v, a, cost_dtype, stream), "half-step recompute");
+        }
         b.lam0 = ck;
         DM_HIP_TRY(launch_adjoint(h ? tile : tile_v, b, cost_dtype, stream), "half-step adjoint");
         // the last half-step's family enters dL/dLB at the dual before that half-step

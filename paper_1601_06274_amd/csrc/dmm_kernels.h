@@ -568,6 +568,9 @@ __device__ __forceinline__ void run_chain(const SweepArgs& a, int chain, int sub
 #pragma unroll
             for (int i = 0; i < 8; ++i)
                 if (s == i && s + 1 < P) st = a.rec_lam[i + 1];
+            // the last pass writes the half-step's output dual unless it would overwrite
+            // the input (the backward's recompute from a checkpoint)
+            if (s + 1 == P && a.lam != a.lam_in) st = a.lam;
             wk.r_lam_ld = make_rsrc(ld, vb);
             wk.r_lam_st = make_rsrc(st, st != nullptr ? vb : 0u);
             wk.r_msg_ld = make_rsrc(mld, vb);

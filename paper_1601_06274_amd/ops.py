@@ -65,7 +65,9 @@ def discrete_params(T=3, n_iters=10, n_half_steps=0, minorant="iterative", gamma
             (p.tile_lanes, p.labels_per_lane), (p.tile_lanes_v, p.labels_per_lane_v) = tile
         else:
             p.tile_lanes, p.labels_per_lane = int(tile[0]), int(tile[1])
-    p.keep_checkpoints = 1 if keep_checkpoints else 0
+    # False/True -> 0/1 (dual checkpoints, messages recomputed); 2 or "record" -> 2 (the
+    # forward also keeps every pass's messages and intermediate duals)
+    p.keep_checkpoints = 2 if keep_checkpoints in (2, "record") else (1 if keep_checkpoints else 0)
     return p
 
 
@@ -132,14 +134,14 @@ def solve_discrete(cost, w_h, w_v, *, T=3, n_iters=10, n_half_steps=0, minorant=
 def solve_discrete_backward(cost, w_h, w_v, dual, fwd_workspace, *, grad_minmarg=None, grad_lb=0.0, T=3,
                             n_iters=10, n_half_steps=0, minorant="iterative", gammas=(0.25, 0.25, 1.0), tile=None,
                             grad_cost=None, grad_w_h=None, grad_w_v=None, accumulate=False, workspace=None,
-                            stream=None):
+                            stream=None, keep_checkpoints=True):
     """Adjoint of solve_discrete (dm_solve_discrete_backward); the forward must have run with
     keep_checkpoints=True and the same parameters.  Returns (grad_cost, grad_w_h, grad_w_v)."""
     H, W, K = cost.shape
     dev = cost.device
     _check_dev("dual", dual, torch.float32, (H, W, K))
     _check_dev("grad_minmarg", grad_minmarg, torch.float32, (H, W, K))
-    p = discrete_params(T, n_iters, n_half_steps, minorant, gammas, False, tile, True)
+    p = discrete_params(T, n_iters, n_half_steps, minorant, gammas, False, tile, keep_checkpoints or True)
     shape = L.DmShape(W, H, K)
     lib = L.lib()
     ws_bytes = max(int(lib.dm_solve_discrete_backward_workspace(shape, ctypes.byref(p))), 256)

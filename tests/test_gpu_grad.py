@@ -218,3 +218,27 @@ def test_backward_deterministic():
     b = ops.solve_discrete_backward(th, wh, wv, res.dual, res.workspace, grad_minmarg=Gm, grad_lb=1.0, T=3, n_iters=2)
     torch.cuda.synchronize()
     assert all(torch.equal(x, y) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("minorant", ["iterative", "naive"])
+def test_record_all_checkpoints_match_recompute(minorant):
+    """keep_checkpoints=2 (the forward keeps every pass's messages) gives the same forward
+    results and bit-identical gradients as recomputing from dual checkpoints."""
+    ops = _need()
+    theta, w_h, w_v = synth.tiny_instance(11, 13, 12, seed=31, w_max=0.5)
+    th, wh, wv = _dev(theta, torch.float16), _dev(w_h), _dev(w_v)
+    Gm = _dev(np.random.default_rng(5).normal(size=theta.shape))
+    print(f"[case] record-all checkpoints {minorant}", flush=True)
+    kw = dict(T=3, n_iters=3, minorant=minorant)
+    out = {}
+    for mode in (1, 2):
+        r = ops.solve_discrete(th, wh, wv, keep_checkpoints=mode, **kw)
+        g = ops.solve_discrete_backward(th, wh, wv, r.dual, r.workspace, grad_minmarg=Gm, grad_lb=0.5,
+                                        keep_checkpoints=mode, **kw)
+        torch.cuda.synchronize()
+        out[mode] = (r, g)
+    (r1, g1), (r2, g2) = out[1], out[2]
+    assert torch.equal(r1.labels, r2.labels) and torch.equal(r1.dual, r2.dual) and torch.equal(r1.minmarg, r2.minmarg)
+    assert torch.equal(r1.bounds, r2.bounds)
+    for a, b in zip(g1, g2):
+        assert torch.equal(a, b)
