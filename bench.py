@@ -227,7 +227,7 @@ def main():
     import synth
     import paper_1601_06274_amd as P
     from paper_1601_06274_amd import ops
-    from paper_1601_06274_amd.traffic import sweep_source_hash
+    from paper_1601_06274_amd.traffic import source_hash
 
     wl = WORKLOAD
     W, H, K = wl["W"], wl["H"], wl["K"]
@@ -272,8 +272,13 @@ def main():
         buf = torch.ones(n, dtype=torch.float32, device=dev)
         for _ in range(3):
             buf.mul_(1.0)
+        del buf
         ops.build_cost_volume(IL, IR, K, dtype=torch.float16, cost_out=cost, w_h=w_h, w_v=w_v)
-        ops.solve_discrete(cost, w_h, w_v, dual=dual, workspace=ws_d, labels=labels, **dict(dkw, n_iters=2))
+        k2 = dict(dkw, n_iters=2)
+        ops.solve_discrete(cost, w_h, w_v, dual=dual, workspace=ws_d, labels=labels, minmarg=minmarg,
+                           keep_checkpoints=True, **k2)
+        ops.solve_discrete_backward(cost, w_h, w_v, dual, ws_d, grad_minmarg=G_m, grad_lb=g_lb, grad_cost=grad_cost,
+                                    grad_w_h=grad_wh, grad_w_v=grad_wv, workspace=ws_db, **k2)
         torch.cuda.synchronize()
         print(json.dumps({"traffic_probe_bytes": 4 * n}), flush=True)
         return 0
@@ -310,32 +315,42 @@ def main():
     fwd_ms = (time.perf_counter() - t0) * 1e3 / args.steps
     ops.profiler_disable()
 
-    # Timed steps: forward + backward of the whole frame.
+    prof = {k: ops.profiler_query(k) for k in ["sweep_h", "sweep_v", "sweep_final", "cost_volume"]}
+
+    # Timed steps: forward + backward of the whole frame; the backward's sweeps are
+    # bracketed by HIP events on their stream.
+    bwd_kinds = ["adjoint_h", "adjoint_v", "adjoint_final", "recompute_h", "recompute_v"]
+    ops.profiler_enable(bwd_kinds)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         res = step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    ops.profiler_disable()
     ms_per_step = el * 1e3 / args.steps
     grad_finite = bool(torch.isfinite(grad_cost).all().item() and torch.isfinite(grad_wh).all().item())
+    prof.update({k: ops.profiler_query(k) for k in bwd_kinds})
 
-    prof = {k: ops.profiler_query(k) for k in ["sweep_h", "sweep_v", "sweep_final", "cost_volume"]}
+    def roof(kind, traffic_file, kernel):
+        """Roofline object of one kernel kind: algorithmic bytes per launch / mean launch time."""
+        n, ms, by = prof[kind]
+        achieved = (by / n) / (ms / n * 1e-3) / 1e9 if n else 0.0
+        traffic = None  # HBM bytes per launch from rocprofv3 counters of the same kernel source
+        tpath = os.path.join(ROOT, "profiles", traffic_file)
+        if os.path.exists(tpath):
+            try:
+                with open(tpath) as f:
+                    t = json.load(f)
+                if t.get("kernel_source_hash") == source_hash(t.get("sources", "sweep")):
+                    traffic = t.get("bytes_per_launch")
+            except (OSError, ValueError):
+                traffic = None
+        return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "alg_bytes_per_launch": by / n if n else None,
+                "avg_launch_ms": ms / n if n else None, "launches": n}
     n_h, ms_h, by_h = prof["sweep_h"]
-    achieved = (by_h / n_h) / (ms_h / n_h * 1e-3) / 1e9 if n_h else 0.0
     per_launch_gb = by_h / n_h / 1e9 if n_h else 0.0
-
-    # Bandwidth-level traffic from rocprofv3 counters of the same kernel, if recorded.
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "sweep_h_traffic.json")
-    if os.path.exists(tpath):
-        try:
-            with open(tpath) as f:
-                t = json.load(f)
-            if t.get("kernel_source_hash") == sweep_source_hash():
-                traffic = t.get("bytes_per_launch")
-        except Exception:
-            traffic = None
 
     # The same step with the forward keeping every pass's messages and intermediate duals
     # (keep_checkpoints = 2: about 7 volumes per half-step in HBM, no recompute).
@@ -403,23 +418,21 @@ def main():
                                "note": "forward keeps every pass's messages (keep_checkpoints=2), no recompute"},
         "forward_only": {"ms_per_frame": fwd_ms, "label_node_updates_per_s": updates / (fwd_ms * 1e-3)},
         "grad_finite": grad_finite,
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "horizontal half-step chain sweep (R0 + 3 update passes, FP16 cost)",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "alg_bytes_per_launch": by_h / n_h if n_h else None,
-            "avg_launch_ms": ms_h / n_h if n_h else None,
-        },
+        # the step's dominant kernel (about 30% of the step): the adjoint of the horizontal half-step
+        "roofline": roof("adjoint_h", "adjoint_h_traffic.json",
+                         "adjoint of the horizontal half-step (R0 + 3 update passes in reverse, FP16 cost)"),
+        "roofline_forward_sweep": roof("sweep_h", "sweep_h_traffic.json",
+                                       "horizontal half-step chain sweep (R0 + 3 update passes, FP16 cost)"),
         "stage_ms": {
             "cost_volume": prof["cost_volume"][1] / max(prof["cost_volume"][0], 1),
             "sweep_h_per_launch": ms_h / max(n_h, 1),
             "sweep_v_per_launch": prof["sweep_v"][1] / max(prof["sweep_v"][0], 1),
             "sweep_v_GBps": (prof["sweep_v"][2] / prof["sweep_v"][1] / 1e6) if prof["sweep_v"][1] else None,
             "final_per_launch": prof["sweep_final"][1] / max(prof["sweep_final"][0], 1),
+            "adjoint_h_per_launch": prof["adjoint_h"][1] / max(prof["adjoint_h"][0], 1),
+            "adjoint_v_per_launch": prof["adjoint_v"][1] / max(prof["adjoint_v"][0], 1),
+            "recompute_h_per_launch": prof["recompute_h"][1] / max(prof["recompute_h"][0], 1),
+            "recompute_v_per_launch": prof["recompute_v"][1] / max(prof["recompute_v"][0], 1),
         },
         "fp16_storage": {"energy_fp16_labels": e16, "energy_fp32_labels": e32, "rel_diff": (e16 - e32) / e32},
         "lower_bound": float(bounds[0]),

@@ -280,6 +280,11 @@ typedef enum {
     DM_PROF_REFINE_LINEARIZE = 6, /* per-warp data-term linearisation              */
     DM_PROF_REFINE_ITER = 7,      /* primal-dual iteration                         */
     DM_PROF_OTHER = 8,            /* fills, copies                                 */
+    DM_PROF_ADJOINT_H = 9,        /* adjoint of a horizontal half-step             */
+    DM_PROF_ADJOINT_V = 10,       /* adjoint of a vertical half-step               */
+    DM_PROF_ADJOINT_FINAL = 11,   /* adjoint of the final row pass                 */
+    DM_PROF_RECOMPUTE_H = 12,     /* backward's recompute of a horizontal half-step */
+    DM_PROF_RECOMPUTE_V = 13,     /* backward's recompute of a vertical half-step  */
     DM_PROF_KINDS = 16
 } dm_prof_kind;
 

@@ -234,6 +234,36 @@ double sweep_bytes(const SweepArgs& a, dm_dtype dt) {
     return per * nodes + (a.mode == kModeFinal ? 4.0 * a.n * a.n_chains : 0.0);
 }
 
+// Algorithmic HBM bytes of one adjoint launch (per label-node: what its passes read and
+// write; cost b bytes, every other volume 4).
+double adjoint_bytes(const AdjArgs& a, dm_dtype dt) {
+    const bool theta = a.theta != nullptr;
+    const double b = theta ? (dt == DM_F16 ? 2.0 : 4.0) : 0.0;
+    const double nodes = (double)a.n * a.n_chains * a.K;
+    // kind: 0 R0, 1 update, 3 final; first: the half-step's last update pass
+    auto pass = [&](int kind, bool first, bool has_bin) {
+        double x = b + 8.0;                                       // cost, dual, carried message
+        if (kind != 3) x += 4.0;                                  // dual adjoint in
+        if (kind != 0) x += 4.0;                                  // reverse message
+        if (has_bin) x += 4.0;                                    // stored-message adjoint in
+        const bool gx = kind == 3 || (theta && (first || kind == 0));
+        if (gx) x += 4.0;                                         // dL/dcost or dL/dminmarg in
+        x += 4.0;                                                 // dual adjoint out
+        if (kind != 0) x += 4.0;                                  // reverse-message adjoint out
+        if (theta && (first || kind == 0)) x += 4.0;              // dL/dcost out
+        return x;
+    };
+    double per = 0.0;
+    if (a.mode == kModeFinal) {
+        per = pass(3, false, false) + pass(0, false, true);
+    } else {
+        const int P = a.mode == kModeIterative ? a.n_pass : 1;
+        for (int s = P; s >= 1; --s) per += pass(1, s == P, s < P);
+        per += pass(0, false, true);
+    }
+    return per * nodes;
+}
+
 hipError_t launch_sweep_prof(Tile t, const SweepArgs& a, dm_dtype dt, hipStream_t st) {
     int kind = DM_PROF_SWEEP_H;
     if (a.mode == kModeFinal) kind = DM_PROF_SWEEP_FINAL;
@@ -693,6 +723,7 @@ extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad
         b.lam0 = dual;
         b.grad_mm = grad_minmarg;
         b.g_lb = lb_last == 0 ? 0.0 : grad_lb;
+        ProfScope ps(DM_PROF_ADJOINT_FINAL, profiler_on() ? adjoint_bytes(b, cost_dtype) : 0.0, stream);
         DM_HIP_TRY(launch_adjoint(tile, b, cost_dtype, stream), "final adjoint");
     }
     // 2. column part of dL/dLB at the final dual
@@ -718,10 +749,16 @@ extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad
             a.mode = a.mode | kRecordFlag;
             a.lam_in = ck;
             a.lam = const_cast<float*>(ck);
+            ProfScope ps(h ? DM_PROF_RECOMPUTE_H : DM_PROF_RECOMPUTE_V, profiler_on() ? sweep_bytes(a, cost_dtype) : 0.0,
+                         stream);
             DM_HIP_TRY(launch_sweep(h ? tile : tile_v, a, cost_dtype, stream), "half-step recompute");
         }
         b.lam0 = ck;
-        DM_HIP_TRY(launch_adjoint(h ? tile : tile_v, b, cost_dtype, stream), "half-step adjoint");
+        {
+            ProfScope ps(h ? DM_PROF_ADJOINT_H : DM_PROF_ADJOINT_V, profiler_on() ? adjoint_bytes(b, cost_dtype) : 0.0,
+                         stream);
+            DM_HIP_TRY(launch_adjoint(h ? tile : tile_v, b, cost_dtype, stream), "half-step adjoint");
+        }
         // the last half-step's family enters dL/dLB at the dual before that half-step
         if (k == S - 1 && grad_lb != 0.0) {
             st = lb_inject(h, ck);

@@ -25,11 +25,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PROBE_KERNEL = "MulFunctor"
 
 
-def sweep_source_hash() -> str:
-    """Hash of the sources of the chain sweep kernels (a stored traffic figure is valid
-    only for the kernel it was measured on)."""
+SOURCES = {"sweep": ["dmm_kernels.h", "wave.h", "tiles.h"],
+           "adjoint": ["dmm_kernels.h", "wave.h", "tiles.h", "dmm_adjoint.h"]}
+
+
+def source_hash(which: str = "sweep") -> str:
+    """Hash of the sources of the chain sweep ("sweep") or adjoint ("adjoint") kernels (a
+    stored traffic figure is valid only for the kernel it was measured on)."""
     h = hashlib.sha256()
-    for fn in ["dmm_kernels.h", "wave.h", "tiles.h"]:
+    for fn in SOURCES[which]:
         with open(os.path.join(HERE, "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -61,7 +65,7 @@ def _median_for(d: dict[str, list[float]], sub: str) -> tuple[float, int, str]:
     return statistics.median(vals), len(vals), names[0]
 
 
-def summarize(fetch_csv: str, write_csv: str, copy_bytes: float, kernel: str) -> dict:
+def summarize(fetch_csv: str, write_csv: str, copy_bytes: float, kernel: str, sources: str = "sweep") -> dict:
     fd = _per_dispatch(fetch_csv, "FETCH_SIZE")
     wd = _per_dispatch(write_csv, "WRITE_SIZE")
     pf, _, _ = _median_for(fd, PROBE_KERNEL)
@@ -72,7 +76,8 @@ def summarize(fetch_csv: str, write_csv: str, copy_bytes: float, kernel: str) ->
     sw = copy_bytes / pw
     return {
         "kernel": name,
-        "kernel_source_hash": sweep_source_hash(),
+        "sources": sources,
+        "kernel_source_hash": source_hash(sources),
         "dispatches": [nf, nw],
         "fetch_kib_raw": kf,
         "write_kib_raw": kw,
@@ -93,9 +98,10 @@ def main(argv=None) -> int:
     ap.add_argument("--write", required=True)
     ap.add_argument("--copy-bytes", type=float, required=True)
     ap.add_argument("--kernel", required=True)
+    ap.add_argument("--sources", default="sweep", choices=sorted(SOURCES))
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
-    res = summarize(a.fetch, a.write, a.copy_bytes, a.kernel)
+    res = summarize(a.fetch, a.write, a.copy_bytes, a.kernel, a.sources)
     txt = json.dumps(res, indent=1)
     if a.out:
         with open(a.out, "w") as f:
