@@ -12,6 +12,7 @@ import pytest
 
 import synth
 from oracle import dmm as odmm, energy as oenergy, cost_volume as ocv
+from paper_1601_06274_amd.build import TILES  # the compiled tile list (read from csrc/tiles.h)
 from tests.parity import MM_RTOL, check_labels, minmarg_errors, summarize
 
 torch = pytest.importorskip("torch")
@@ -81,7 +82,19 @@ def test_label_counts_and_tiles(K):
     _check(res, ref, th, w_h, w_v, 2 if K > 1 else 1, f"K{K}")
 
 
-@pytest.mark.parametrize("tile", [(4, 1), (4, 2), (8, 4), (16, 4), (32, 3), (32, 4), (64, 3), (64, 4)])
+@pytest.mark.parametrize("tile", TILES)
+def test_forced_tiles_full(tile):
+    """Every compiled tile with K = lanes x labels per lane (vector loads, no masked labels)."""
+    K = tile[0] * tile[1]
+    theta, w_h, w_v = synth.tiny_instance(5, 7, K, seed=100 + K, w_max=0.4)
+    res, ref, th = _run_both(theta, w_h, w_v, 3, 2, tile=tile, name=f"full{tile}")
+    _check(res, ref, th, w_h, w_v, 3, f"full{tile}")
+    res, ref, th = _run_both(theta.astype(np.float16), w_h, w_v, 3, 2, theta_dtype=torch.float16, tile=tile,
+                             name=f"full16{tile}")
+    _check(res, ref, th, w_h, w_v, 3, f"full16{tile}")
+
+
+@pytest.mark.parametrize("tile", TILES)
 def test_forced_tiles(tile):
     K = min(tile[0] * tile[1], 24)
     theta, w_h, w_v = synth.tiny_instance(9, 13, K, seed=100 + K, w_max=0.4)

@@ -77,6 +77,13 @@ def test_discrete_grad_tiles(tile):
     assert _discrete_case(5, 8, K, 3, 1, seed=K + tile[0], tile=tile, dirs=2) <= REL
 
 
+@pytest.mark.parametrize("tile", [(16, 4), (32, 6), (64, 3), (64, 4)])
+def test_discrete_grad_full_tiles(tile):
+    """Full tiles (vector loads; whole-wave ballots and paired sums for 64 lanes), FP16 cost."""
+    K = tile[0] * tile[1]
+    assert _discrete_case(4, 6, K, 3, 1, seed=K, tile=tile, dirs=2, cost_dtype=torch.float16) <= REL
+
+
 @pytest.mark.parametrize("T", [1, 5])
 def test_discrete_grad_truncations(T):
     assert _discrete_case(5, 6, 9, T, 2, seed=10 + T, dirs=2) <= REL
