@@ -120,9 +120,19 @@ typedef struct {
                                0: nothing kept;
                                1: the dual before every half-step (one FP32 volume per
                                   half-step; the backward recomputes the messages);
-                               2: also every pass's messages and the duals between passes
-                                  (2*P + 1 volumes per half-step, P = update passes; the
-                                  backward recomputes nothing)                          */
+                               2: also what the backward would recompute (P = update
+                                  passes): with selection tapes (below) every pass's tape
+                                  (P + 1 tapes of W*H*lanes*ceil(lpl/4)*4 bytes, lanes x
+                                  lpl the larger family tile); otherwise every pass's
+                                  messages and the duals between passes (2*P volumes)  */
+    int   recompute_selections; /* 0: the backward reads selection tapes - which operand
+                               each min of a message took and each node's argmins,
+                               one byte per label and pass, written by the recompute
+                               (or, with keep_checkpoints 2, the forward) - whenever
+                               the truncation reaches at most one lane across in both
+                               families' tiles (trunc_T - 1 <= labels per lane) and a
+                               tape fits 4 GiB; 1: the backward always recomputes the
+                               selections from the forward's values (same results)   */
 } dm_discrete_params;
 
 size_t dm_solve_discrete_workspace(dm_shape s, dm_dtype cost_dtype, const dm_discrete_params* p);
@@ -161,11 +171,14 @@ int dm_autotune_tiles(dm_shape s, dm_dtype cost_dtype, dm_discrete_params* p, vo
  *                 same parameters, unchanged since.
  *   grad_cost     [H][W][K] float32 dL/dcost; grad_w_h, grad_w_v dL/dw (may be NULL).
  *   accumulate    0: outputs overwritten; 1: gradients added.
- * Per half-step (in reverse) the forward passes are recomputed from the checkpoint,
- * keeping every pass's messages (keep_checkpoints = 1; with 2 the forward kept them),
- * then the passes are differentiated chain by chain.  The backward workspace holds
- * (max_pass + 1) message volumes and max_pass - 1 dual volumes (2 and 0 with
- * keep_checkpoints = 2), three adjoint volumes and FP64 edge accumulators. */
+ * Per half-step (in reverse) the forward passes are recomputed from the checkpoint
+ * (keep_checkpoints = 1; with 2 the forward kept what is needed), keeping every pass's
+ * selection tape (see recompute_selections) or else its messages and intermediate
+ * duals, then the passes are differentiated chain by chain.  The backward workspace
+ * holds, with tapes, one message and one dual volume and max_pass + 1 tapes (2 tapes
+ * with keep_checkpoints = 2); without, max_pass + 1 message volumes and max_pass - 1
+ * dual volumes (2 and 0 with keep_checkpoints = 2); plus three adjoint volumes and
+ * FP64 edge accumulators. */
 size_t dm_solve_discrete_backward_workspace(dm_shape s, const dm_discrete_params* p);
 
 int dm_solve_discrete_backward(const float* grad_minmarg, double grad_lb, const void* cost,

@@ -40,7 +40,8 @@ class DmDiscreteParams(ctypes.Structure):
     _fields_ = [("n_iters", ctypes.c_int), ("n_half_steps", ctypes.c_int), ("trunc_T", ctypes.c_int),
                 ("minorant", ctypes.c_int), ("max_pass", ctypes.c_int), ("gamma", ctypes.c_float * 8),
                 ("warm_start", ctypes.c_int), ("tile_lanes", ctypes.c_int), ("labels_per_lane", ctypes.c_int),
-                ("tile_lanes_v", ctypes.c_int), ("labels_per_lane_v", ctypes.c_int), ("keep_checkpoints", ctypes.c_int)]
+                ("tile_lanes_v", ctypes.c_int), ("labels_per_lane_v", ctypes.c_int), ("keep_checkpoints", ctypes.c_int),
+                ("recompute_selections", ctypes.c_int)]
 
 
 class DmRefineParams(ctypes.Structure):

@@ -16,7 +16,8 @@ namespace dm {
 
 #define DM_EXTERN_TILE(g, l)                                                            \
     extern template hipError_t launch_tile<g, l>(const SweepArgs&, dm_dtype, hipStream_t); \
-    extern template hipError_t launch_adjoint_tile<g, l>(const AdjArgs&, dm_dtype, hipStream_t);
+    extern template hipError_t launch_adjoint_tile<g, l, false>(const AdjArgs&, dm_dtype, hipStream_t); \
+    extern template hipError_t launch_adjoint_tile<g, l, true>(const AdjArgs&, dm_dtype, hipStream_t);
 DM_FOR_EACH_TILE(DM_EXTERN_TILE)
 #undef DM_EXTERN_TILE
 
@@ -205,8 +206,10 @@ hipError_t launch_sweep(Tile t, const SweepArgs& a, dm_dtype dt, hipStream_t st)
 }
 
 hipError_t launch_adjoint(Tile t, const AdjArgs& a, dm_dtype dt, hipStream_t st) {
-#define DM_TILE_CASE(g, l) \
-    if (t.G == g && t.LPL == l) return launch_adjoint_tile<g, l>(a, dt, st);
+#define DM_TILE_CASE(g, l)                                                                          \
+    if (t.G == g && t.LPL == l)                                                                     \
+        return a.tape[0] != nullptr ? launch_adjoint_tile<g, l, true>(a, dt, st)                    \
+                                    : launch_adjoint_tile<g, l, false>(a, dt, st);
     DM_FOR_EACH_TILE(DM_TILE_CASE)
 #undef DM_TILE_CASE
     return hipErrorInvalidValue;
@@ -219,14 +222,19 @@ double sweep_bytes(const SweepArgs& a, dm_dtype dt) {
     const double nodes = (double)a.n * a.n_chains * a.K;
     double per = 0.0;
     // record mode (dual checkpoints with every pass's messages) also stores the last
-    // pass's messages
-    const double rec = (a.mode & kRecordFlag) ? 4.0 : 0.0;
+    // pass's messages; tape mode instead writes every pass's tape
+    const bool tape = (a.mode & kRecordFlag) && a.tape[0] != nullptr;
+    const double rec = ((a.mode & kRecordFlag) && !tape) ? 4.0 : 0.0;
+    if (tape) {
+        const int P = (a.mode & ~kRecordFlag) == kModeIterative ? a.n_pass : 1;
+        per += (P + 1) * (double)a.tape_px / a.K;
+    }
     switch (a.mode & ~kRecordFlag) {
         case kModeIterative:
-            per = b + 8.0 + rec;                           // R0: cost, dual; message out
+            per += b + 8.0 + rec;                          // R0: cost, dual; message out
             for (int s = 0; s < a.n_pass; ++s) per += (s < a.n_pass - 1) ? b + 16.0 : b + 12.0;
             break;
-        case kModeNaive: per = (b + 8.0) + (b + 12.0) + rec; break;
+        case kModeNaive: per += (b + 8.0) + (b + 12.0) + rec; break;
         case kModeOptimum: per = b + 4.0; break;
         case kModeFinal: per = (b + 8.0) + (b + 8.0) + (a.minmarg != nullptr ? 4.0 : 0.0); break;
         default: break;
@@ -241,10 +249,11 @@ double adjoint_bytes(const AdjArgs& a, dm_dtype dt) {
     const double b = theta ? (dt == DM_F16 ? 2.0 : 4.0) : 0.0;
     const double nodes = (double)a.n * a.n_chains * a.K;
     // kind: 0 R0, 1 update, 3 final; first: the half-step's last update pass
+    const bool tape = a.tape[0] != nullptr;
     auto pass = [&](int kind, bool first, bool has_bin) {
-        double x = b + 8.0;                                       // cost, dual, carried message
+        // cost, dual, carried and reverse messages (recomputing form) or the tape
+        double x = tape ? (double)a.tape_px / a.K : b + 8.0 + (kind != 0 ? 4.0 : 0.0);
         if (kind != 3) x += 4.0;                                  // dual adjoint in
-        if (kind != 0) x += 4.0;                                  // reverse message
         if (has_bin) x += 4.0;                                    // stored-message adjoint in
         const bool gx = kind == 3 || (theta && (first || kind == 0));
         if (gx) x += 4.0;                                         // dL/dcost or dL/dminmarg in
@@ -278,7 +287,9 @@ struct WsLayout {
     size_t vol_bytes;
     long long max_chains;
     int n_slots, n_partial;
-    int slab_vols;  // FP32 volumes kept per half-step
+    size_t slab_bytes;  // kept per half-step
+    bool tape;          // the selections are kept as tapes
+    size_t tape_bytes;  // bytes of one tape
 };
 
 // Update passes of a half-step (the adjoint's P).
@@ -291,6 +302,25 @@ int slab_volumes(const dm_discrete_params& p) {
     if (p.keep_checkpoints == 1) return 1;
     if (p.keep_checkpoints == 2) return 1 + (pass_count(p) + 1) + (pass_count(p) - 1);
     return 0;
+}
+
+// Tape bytes per pixel of a tile, and whether the tape form covers its distance
+// transform (the truncation reaches at most one lane across).
+size_t tape_px_bytes(Tile t) { return (size_t)t.G * kTapeWords(t.LPL) * 4; }
+bool tape_tile_ok(Tile t, int T) {
+    const int need = (T - 1 + t.LPL - 1) / t.LPL;
+    return (need < t.G - 1 ? need : t.G - 1) <= 1;
+}
+// The backward reads selection tapes instead of recomputing the selections when both
+// families' tiles allow it, the caller did not ask for recomputation and one tape fits
+// the 32-bit buffer range.  Returns the bytes of one tape (0: no tapes).
+size_t tape_bytes_for(const dm_shape& s, const dm_discrete_params& p) {
+    if (p.recompute_selections) return 0;
+    const Tile r = row_tile(s, p), c = col_tile(s, p);
+    if (!tape_tile_ok(r, p.trunc_T) || !tape_tile_ok(c, p.trunc_T)) return 0;
+    const size_t px = tape_px_bytes(r) > tape_px_bytes(c) ? tape_px_bytes(r) : tape_px_bytes(c);
+    const size_t b = align_up((size_t)s.W * s.H * px, 256);
+    return b <= kMaxVolBytes ? b : 0;
 }
 
 constexpr int kEnergyBlocks = 1024;
@@ -315,8 +345,15 @@ WsLayout layout(const dm_shape& s, const dm_discrete_params& p) {
     off = align_up(off + (size_t)s.W * s.H * sizeof(int), 256);
     L.vol_bytes = align_up(vol * sizeof(float), 256);
     L.ckpt = off;
-    L.slab_vols = slab_volumes(p);
-    off += (size_t)S * L.slab_vols * L.vol_bytes;  // per half-step: its input dual (+ records)
+    L.tape_bytes = tape_bytes_for(s, p);
+    L.tape = L.tape_bytes != 0;
+    // per half-step: its input dual, plus (keep_checkpoints 2) every pass's tape or its
+    // messages and intermediate duals
+    if (p.keep_checkpoints == 2 && L.tape)
+        L.slab_bytes = L.vol_bytes + (size_t)(pass_count(p) + 1) * L.tape_bytes;
+    else
+        L.slab_bytes = (size_t)slab_volumes(p) * L.vol_bytes;
+    off += (size_t)S * L.slab_bytes;
     L.total = off;
     return L;
 }
@@ -341,6 +378,8 @@ int validate_params(const dm_shape& s, const dm_discrete_params* p) {
     }
     DM_REQUIRE(p->warm_start == 0 || p->warm_start == 1, DM_ERR_PARAM, "warm_start must be 0 or 1");
     DM_REQUIRE(p->keep_checkpoints >= 0 && p->keep_checkpoints <= 2, DM_ERR_PARAM, "keep_checkpoints must be 0, 1 or 2");
+    DM_REQUIRE(p->recompute_selections == 0 || p->recompute_selections == 1, DM_ERR_PARAM,
+               "recompute_selections must be 0 or 1");
     if (p->tile_lanes != 0 || p->labels_per_lane != 0) {
         DM_REQUIRE(tile_compiled(p->tile_lanes, p->labels_per_lane), DM_ERR_UNSUPPORTED,
                    "tile %d lanes x %d labels is not compiled in", p->tile_lanes, p->labels_per_lane);
@@ -407,7 +446,11 @@ extern "C" int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const fl
     // last one writes dual_inout): the checkpoints cost no extra traffic.
     float* ckpt0 = reinterpret_cast<float*>(ws + L.ckpt);
     auto slab_vol = [&](int k, int i) {
-        return reinterpret_cast<float*>(ws + L.ckpt + ((size_t)k * L.slab_vols + i) * L.vol_bytes);
+        return reinterpret_cast<float*>(ws + L.ckpt + (size_t)k * L.slab_bytes + (size_t)i * L.vol_bytes);
+    };
+    auto slab_tape = [&](int k, int i) {
+        return reinterpret_cast<unsigned*>(ws + L.ckpt + (size_t)k * L.slab_bytes + L.vol_bytes +
+                                           (size_t)i * L.tape_bytes);
     };
     auto ckpt = [&](int k) { return slab_vol(k, 0); };
     const int P = pass_count(*p);
@@ -469,7 +512,16 @@ extern "C" int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const fl
             a.lam_in = ckpt(k);
             a.lam = (k + 1 < S) ? ckpt(k + 1) : dual_inout;
         }
-        if (record) {
+        if (record && L.tape) {
+            // every pass's selection tape into the half-step's slab; messages and duals
+            // in place as in the plain half-step
+            a.mode |= kRecordFlag;
+            for (int i = 0; i < 9; ++i) a.rec_msg[i] = msg;
+            for (int i = 0; i < 8; ++i) a.rec_lam[i] = a.lam;
+            for (int i = 0; i <= P && i < 9; ++i) a.tape[i] = slab_tape(k, i);
+            a.tape_bytes = (unsigned)L.tape_bytes;
+            a.tape_px = (unsigned)tape_px_bytes(k % 2 == 0 ? tile : tile_v);
+        } else if (record) {
             // every pass's messages and intermediate duals into the half-step's slab
             a.mode |= kRecordFlag;
             for (int i = 0; i <= P && i < 9; ++i) a.rec_msg[i] = slab_vol(k, 1 + i);
@@ -526,7 +578,8 @@ namespace dm {
 namespace {
 
 struct BwdLayout {
-    size_t vol, msg, lam, bbar, lbar, gwh, gwv, lab, total;
+    size_t vol, msg, lam, tape, bbar, lbar, gwh, gwv, lab, total;
+    size_t tape_bytes;  // one tape (0: the selections are recomputed)
     int P;
 };
 
@@ -536,11 +589,16 @@ BwdLayout bwd_layout(const dm_shape& s, const dm_discrete_params& p) {
     // the final pass's two
     L.P = p.keep_checkpoints == 2 ? 1 : pass_count(p);
     L.vol = align_up((size_t)s.W * s.H * s.K * sizeof(float), 256);
+    L.tape_bytes = tape_bytes_for(s, p);
+    const bool tape = L.tape_bytes != 0;
     size_t off = 0;
     L.msg = off;
-    off += (size_t)(L.P + 1) * L.vol;
+    // with tapes, messages and intermediate duals of a recompute stay in place
+    off += (size_t)(tape ? 1 : L.P + 1) * L.vol;
     L.lam = off;
-    off += (size_t)(L.P > 1 ? L.P - 1 : 0) * L.vol;
+    off += (size_t)(L.P > 1 ? (tape ? 1 : L.P - 1) : 0) * L.vol;
+    L.tape = off;
+    off += tape ? (size_t)(L.P + 1) * L.tape_bytes : 0;
     L.bbar = off;
     off += 2 * L.vol;
     L.lbar = off;
@@ -639,8 +697,18 @@ extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad
     rows.n_pass = p->max_pass;
     for (int i = 0; i < 8; ++i) rows.gamma[i] = p->gamma[i];
     rows.mode = p->minorant == DM_MINORANT_NAIVE ? kModeNaive : kModeIterative;
-    for (int i = 0; i <= P && i < 9; ++i) rows.rec_msg[i] = vol_at(LB.msg, i);
-    for (int i = 1; i < P && i < 8; ++i) rows.rec_lam[i] = vol_at(LB.lam, i - 1);
+    const bool tape = LB.tape_bytes != 0;
+    if (tape) {
+        for (int i = 0; i < 9; ++i) rows.rec_msg[i] = vol_at(LB.msg, 0);
+        for (int i = 1; i < 8; ++i) rows.rec_lam[i] = P > 1 ? vol_at(LB.lam, 0) : nullptr;
+        for (int i = 0; i <= P && i < 9; ++i)
+            rows.tape[i] = reinterpret_cast<unsigned*>(ws + LB.tape + (size_t)i * LB.tape_bytes);
+        rows.tape_bytes = (unsigned)LB.tape_bytes;
+        rows.tape_px = (unsigned)tape_px_bytes(tile);
+    } else {
+        for (int i = 0; i <= P && i < 9; ++i) rows.rec_msg[i] = vol_at(LB.msg, i);
+        for (int i = 1; i < P && i < 8; ++i) rows.rec_lam[i] = vol_at(LB.lam, i - 1);
+    }
     rows.msg = rows.rec_msg[0];
     rows.labels = lab;
     SweepArgs cols = rows;
@@ -655,6 +723,7 @@ extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad
     cols.n_chains = s.W;
     cols.sign = -1.0f;
     cols.inv_n = 1.0f / (float)s.H;
+    if (tape) cols.tape_px = (unsigned)tape_px_bytes(tile_v);
 
     auto adj_from = [&](const SweepArgs& a, double* gw) {
         AdjArgs b{};
@@ -667,6 +736,9 @@ extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad
         b.grad_w = gw;
         for (int i = 0; i < 9; ++i) b.rec_msg[i] = a.rec_msg[i];
         for (int i = 0; i < 8; ++i) b.rec_lam[i] = a.rec_lam[i];
+        for (int i = 0; i < 9; ++i) b.tape[i] = a.tape[i];
+        b.tape_bytes = a.tape_bytes;
+        b.tape_px = a.tape_px;
         b.chain_px = a.chain_px;
         b.node_px = a.node_px;
         b.w_chain = a.w_chain;
@@ -735,12 +807,19 @@ extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad
     const int PF = pass_count(*p);
     for (int k = S - 1; k >= 0; --k) {
         auto fslab = [&](int i) {
-            return reinterpret_cast<const float*>(fws + LF.ckpt + ((size_t)k * LF.slab_vols + i) * LF.vol_bytes);
+            return reinterpret_cast<const float*>(fws + LF.ckpt + (size_t)k * LF.slab_bytes + (size_t)i * LF.vol_bytes);
         };
         const float* ck = fslab(0);
         const bool h = (k % 2) == 0;
         AdjArgs b = adj_from(h ? rows : cols, h ? gwh : gwv);
-        if (p->keep_checkpoints == 2) {
+        if (p->keep_checkpoints == 2 && tape) {
+            // the forward kept this half-step's tapes
+            for (int i = 0; i < 9; ++i)
+                b.tape[i] = i <= PF ? reinterpret_cast<const unsigned*>(fws + LF.ckpt + (size_t)k * LF.slab_bytes +
+                                                                        LF.vol_bytes + (size_t)i * LF.tape_bytes)
+                                    : nullptr;
+            b.tape_bytes = (unsigned)LF.tape_bytes;
+        } else if (p->keep_checkpoints == 2) {
             // the forward kept this half-step's messages and intermediate duals
             for (int i = 0; i <= PF && i < 9; ++i) b.rec_msg[i] = fslab(1 + i);
             for (int i = 1; i < PF && i < 8; ++i) b.rec_lam[i] = fslab(PF + 1 + i);

@@ -49,6 +49,9 @@ struct AdjArgs {
     float sign;               // +1 horizontal (lambda += h), -1 vertical
     float inv_n;
     float gamma[8];
+    const unsigned* tape[9];  // tape mode: selection tape of pass s (0: backward message pass)
+    unsigned tape_bytes;      // bytes of one tape
+    unsigned tape_px;         // tape bytes per pixel of this tile (byte accounting only)
 };
 
 template <int G>
@@ -130,13 +133,17 @@ struct AdjWalker {
         RawVec<float, LPL, FULL> lam, cmsg, rmsg, abar, bin;
         RawVec<float, LPL, FULL> gx;  // dL/dcost (first / R0 passes) or dL/dminmarg (final pass)
         float w;
+        uint32_t tw[kTapeWords(LPL)];  // tape mode: the node's selection bytes
     };
     struct Cursor {
-        unsigned th, f, w;
+        unsigned th, f, w, tp;
     };
+    static constexpr int kTW = kTapeWords(LPL);
 
     __amdgpu_buffer_rsrc_t r_theta, r_w;
     __amdgpu_buffer_rsrc_t r_lam, r_cmsg, r_rmsg, r_abar, r_bin, r_bout, r_gth, r_gmm;
+    __amdgpu_buffer_rsrc_t r_tape;  // tape mode: the current pass's tape
+    unsigned tp0, tp_step;
     gbl_f64* grad_w;
     // Offsets as in the forward walker: node 0 of this lane's chain and label, edge (0, 1),
     // per-node steps; missing chains sit at kOOB with step 0.
@@ -176,6 +183,10 @@ struct AdjWalker {
         for (int i = 0; i < LPL; ++i) lv[i] = FULL ? true : (ok && sub * LPL + i < K);
         const int need = (a.T - 1 + LPL - 1) / LPL;
         dt_steps = need < G - 1 ? need : G - 1;
+        const unsigned long long ts = (unsigned long long)(G * kTW * 4);
+        tp0 = ok ? (unsigned)(cpx * ts + (unsigned long long)(sub * kTW * 4)) : kOOB;
+        tp_step = ok ? (unsigned)((unsigned long long)a.node_px * ts) : 0u;
+        r_tape = make_rsrc(nullptr, 0u);
         s_v = (lds_f32*)sv + grp * GK;
         s_cb = (lds_f32*)scb + grp * GK;
         s_src = (lds_i32*)ssrc + grp * GK;
@@ -200,15 +211,15 @@ struct AdjWalker {
     __device__ __forceinline__ Cursor cursor_start(bool fwd) const {
         const unsigned j = fwd ? (unsigned)(n - 1) : 0u;
         const unsigned e = fwd ? (unsigned)(n - 1) : 0xFFFFFFFFu;  // edge leaving node j in the pass
-        return Cursor{th0 + j * th_step, f0 + j * f_step, w0 + e * w_step};
+        return Cursor{th0 + j * th_step, f0 + j * f_step, w0 + e * w_step, tp0 + j * tp_step};
     }
     template <bool FWD>
     __device__ __forceinline__ void advance(Cursor& c) const {
         // the adjoint walks against the forward pass
         if constexpr (FWD) {
-            c.th -= th_step; c.f -= f_step; c.w -= w_step;
+            c.th -= th_step; c.f -= f_step; c.w -= w_step; c.tp -= tp_step;
         } else {
-            c.th += th_step; c.f += f_step; c.w += w_step;
+            c.th += th_step; c.f += f_step; c.w += w_step; c.tp += tp_step;
         }
     }
 
@@ -293,11 +304,11 @@ struct AdjWalker {
                     for (int t = 1; t < T && t < K; ++t) {
                         const int lo = b - t, hi = b + t;
                         if (lo >= 0) {
-                            const float c = s_v[lo] + wt * (float)t;
+                            const float c = wdist(wt, t, s_v[lo]);
                             if (c < best) { best = c; bd = -t; }
                         }
                         if (hi < K) {
-                            const float c = s_v[hi] + wt * (float)t;
+                            const float c = wdist(wt, t, s_v[hi]);
                             if (c < best) { best = c; bd = t; }
                         }
                     }
@@ -329,10 +340,6 @@ struct AdjWalker {
             wl = wpart;
             zl = cpart - apart;
         } else {
-            float wk[LPL + 1];
-            wk[0] = 0.0f;
-#pragma unroll
-            for (int i = 1; i <= LPL; ++i) wk[i] = i == 1 ? wt : wt * (float)i;
             // forward in-lane scans (values as the forward computes them) with choices
             float f[LPL], b[LPL];
             int df[LPL], db[LPL];
@@ -374,7 +381,7 @@ struct AdjWalker {
                 int ld = df[i];
                 bool useF = true;
                 if constexpr (DTM == 1) {
-                    const float vl = cl + wk[i + 1];
+                    const float vl = wdist(wt, i + 1, cl);
                     useF = f[i] <= vl;
                     lvv = useF ? f[i] : vl;
                     ld = useF ? df[i] : dcl + i + 1;
@@ -383,7 +390,7 @@ struct AdjWalker {
                 int rd = db[i];
                 bool useB = true;
                 if constexpr (DTM == 1) {
-                    const float vr = cr + wk[LPL - i];
+                    const float vr = wdist(wt, LPL - i, cr);
                     useB = b[i] <= vr;
                     rvv = useB ? b[i] : vr;
                     rd = useB ? db[i] : dcr + LPL - i;
@@ -400,7 +407,7 @@ struct AdjWalker {
                     const float cR = (win & !left & !useB) ? c : 0.0f;
                     CL += cL;
                     CR += cR;
-                    wpart += cL * (float)(i + 1) + cR * (float)(LPL - i);
+                    wpart += __builtin_fmaf(cL, (float)(i + 1), cR * (float)(LPL - i));
                 }
                 cpart += win ? 0.0f : c;
                 apart += c;
@@ -433,9 +440,240 @@ struct AdjWalker {
                 }
             }
             vbar[LPL - 1] += bb[LPL - 1];
-            wl = wpart + Tf * cpart;
+            wl = __builtin_fmaf(Tf, cpart, wpart);
             zl = cpart - apart;
         }
+    }
+
+    // ---------------------------------------------------------------- tape mode
+    // The forward's record sweep stored, per pass, node and label, which operand each
+    // min of the message took and the node's two argmins (TapeBit).  The adjoint then
+    // routes adjoints along those selections without the forward's values: it reads
+    // the tape, the stored-message adjoint and the dual adjoint only.
+
+    // Tape-mode loads (issue order: what the step uses last first).
+    template <bool FWD, int KIND, bool IS_FIRST>
+    __device__ __forceinline__ void load_tape(Node& nd, Cursor& c) const {
+        unsigned os[LPL];
+        const unsigned rs = FWD ? c.f : c.f - f_step;
+        label_offsets<4>(rs, os);
+        nd.bin.load(r_bin, rs, os);
+        label_offsets<4>(c.f, os);
+        if constexpr (KIND == kAdjFinal) nd.gx.load(r_gmm, c.f, os);
+        else if constexpr (HAS_THETA && (IS_FIRST || KIND == kAdjR0)) nd.gx.load(r_gth, c.f, os);
+        if constexpr (KIND != kAdjFinal) nd.abar.load(r_abar, c.f, os);
+        load_words<kTW>(r_tape, c.tp, nd.tw);
+        advance<FWD>(c);
+    }
+
+    // Tape bit BIT of label i (as a 32-bit word position).
+    static constexpr int tape_pos(int i, unsigned bit) { return 8 * (i & 3) + __builtin_ctz(bit); }
+    // c where the tape bit is set, else +0: the bit sign-extended into a mask (no compare).
+    template <unsigned BIT>
+    __device__ __forceinline__ float sel(const Node& nd, int i, float c) const {
+        const int m = __builtin_amdgcn_sbfe((int)nd.tw[i >> 2], tape_pos(i, BIT), 1);
+        return __builtin_bit_cast(float, __builtin_bit_cast(int, c) & m);
+    }
+    __device__ __forceinline__ bool has(const Node& nd, int i, unsigned bit) const {
+        return ((nd.tw[i >> 2] >> (8 * (i & 3))) & bit) != 0u;
+    }
+
+    // msg_adjoint<DTM> (DTM 0 / 1) with the selections read from the tape: the same
+    // routing and the same order of additions as the recomputing form, so the results
+    // agree with it bit for bit (up to the sign of zeros: an unselected term adds +0).
+    template <bool DT1>
+    __device__ __forceinline__ void msg_adjoint_tape(const Node& nd, const float (&cb)[LPL], float (&vbar)[LPL],
+                                                     float& wl, float& zl) {
+        float fb[LPL], bb[LPL];
+        float CL = 0.0f, CR = 0.0f, wpart = 0.0f, cpart = 0.0f, apart = 0.0f;
+#pragma unroll
+        for (int i = 0; i < LPL; ++i) {
+            const float c = (FULL || lv[i]) ? cb[i] : 0.0f;
+            fb[i] = sel<kTapeF>(nd, i, c);
+            bb[i] = sel<kTapeB>(nd, i, c);
+            if constexpr (DT1) {
+                const float cL = sel<kTapeCL>(nd, i, c);
+                const float cR = sel<kTapeCR>(nd, i, c);
+                CL += cL;
+                CR += cR;
+                wpart += __builtin_fmaf(cL, (float)(i + 1), cR * (float)(LPL - i));
+            }
+            cpart += has(nd, i, kTapeF | kTapeB | kTapeCL | kTapeCR) ? 0.0f : c;
+            apart += c;
+        }
+        if constexpr (DT1) {
+            fb[LPL - 1] += from_right(CL, 0.0f);
+            bb[0] += from_left(CR, 0.0f);
+        }
+#pragma unroll
+        for (int i = 0; i < LPL; ++i) vbar[i] = 0.0f;
+#pragma unroll
+        for (int i = LPL - 1; i >= 1; --i) {
+            const float t = sel<kTapeFI>(nd, i, fb[i]);  // passed on to the left neighbour
+            fb[i - 1] += t;
+            wpart += t;
+            vbar[i] += fb[i] - t;
+        }
+        vbar[0] += fb[0];
+#pragma unroll
+        for (int i = 0; i < LPL - 1; ++i) {
+            const float t = sel<kTapeBI>(nd, i, bb[i]);
+            bb[i + 1] += t;
+            wpart += t;
+            vbar[i] += bb[i] - t;
+        }
+        vbar[LPL - 1] += bb[LPL - 1];
+        wl = __builtin_fmaf(Tf, cpart, wpart);
+        zl = cpart - apart;
+    }
+
+    template <bool FWD, int KIND, bool IS_FIRST, bool DT1>
+    __device__ __forceinline__ void pass_tape(float gamma) {
+        float cbar[LPL];
+#pragma unroll
+        for (int i = 0; i < LPL; ++i) cbar[i] = 0.0f;
+        int next_label = 0;
+        Cursor lc = cursor_start(FWD);
+        Cursor sc = lc;
+        Node ring[PF];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            load_tape<FWD, KIND, IS_FIRST>(ring[q], lc);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        int t0 = 0;
+        for (; t0 + PF <= n; t0 += PF) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                step_tape<FWD, KIND, IS_FIRST, DT1>(ring[q], t0 + q, cbar, gamma, next_label, sc);
+                load_tape<FWD, KIND, IS_FIRST>(ring[q], lc);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PF; ++q)
+            if (t0 + q < n) step_tape<FWD, KIND, IS_FIRST, DT1>(ring[q], t0 + q, cbar, gamma, next_label, sc);
+    }
+
+    template <bool FWD, int KIND, bool IS_FIRST>
+    __device__ __forceinline__ void run_pass_tape(float gamma) {
+        if (dt_steps == 1)
+            pass_tape<FWD, KIND, IS_FIRST, true>(gamma);
+        else
+            pass_tape<FWD, KIND, IS_FIRST, false>(gamma);
+    }
+
+    // Adjoint of the forward step at the node visited t-th, from the tape (the same
+    // formulas as step()).
+    template <bool FWD, int KIND, bool IS_FIRST, bool DT1>
+    __device__ __forceinline__ void step_tape(const Node& nd, int t, float (&cbar)[LPL], float gamma, int& next_label,
+                                              Cursor& sc) {
+        const bool out = t != 0;
+        const unsigned rs = FWD ? sc.f : sc.f - f_step;
+        unsigned os[LPL];
+        float ab[LPL], cb[LPL];
+#pragma unroll
+        for (int i = 0; i < LPL; ++i) {
+            ab[i] = KIND == kAdjFinal ? 0.0f : nd.abar.get(i);
+            cb[i] = out ? cbar[i] + nd.bin.get(i) : 0.0f;
+        }
+        if constexpr (IS_FIRST) {
+            if constexpr (HAS_THETA) {
+                float g[LPL];
+#pragma unroll
+                for (int i = 0; i < LPL; ++i) g[i] = nd.gx.get(i) + ab[i];
+                label_offsets<4>(sc.f, os);
+                store_f32<LPL, FULL>(r_gth, sc.f, os, g);
+            }
+#pragma unroll
+            for (int i = 0; i < LPL; ++i) ab[i] = (sign > 0.0f) ? -ab[i] : ab[i];
+        }
+        // the last node of a forward pass sends no message: its selection bits are 0 and
+        // its message adjoint cb is 0, so the message adjoint below adds nothing there
+        float vbar[LPL], wl = 0.0f, zl = 0.0f;
+        msg_adjoint_tape<DT1>(nd, cb, vbar, wl, zl);
+        if constexpr (KIND == kAdjR0) {
+            group_sum2<G>(wl, zl);
+            float rt[LPL], outv[LPL];
+#pragma unroll
+            for (int i = 0; i < LPL; ++i) {
+                vbar[i] += sel<kTapeA>(nd, i, zl);
+                rt[i] = ab[i] + vbar[i];
+                cbar[i] = (FULL || lv[i]) ? vbar[i] : 0.0f;
+                outv[i] = sign > 0.0f ? -rt[i] : rt[i];
+            }
+            label_offsets<4>(sc.f, os);
+            if constexpr (HAS_THETA) {
+                float g[LPL];
+#pragma unroll
+                for (int i = 0; i < LPL; ++i) g[i] = nd.gx.get(i) + rt[i];
+                store_f32<LPL, FULL>(r_gth, sc.f, os, g);
+            }
+            store_f32<LPL, FULL>(r_abar, sc.f, os, outv);
+        } else {
+            float al = 0.0f;
+#pragma unroll
+            for (int i = 0; i < LPL; ++i)
+                al += (FULL || lv[i]) ? (KIND == kAdjFinal ? nd.gx.get(i) : ab[i]) : 0.0f;
+            group_sum2<G>(wl, zl);
+            al = group_sum<G>(al);
+            float rbar[LPL], revb[LPL];
+            if constexpr (KIND == kAdjIter) {
+                const float mminb = gamma * al;
+#pragma unroll
+                for (int i = 0; i < LPL; ++i) {
+                    const bool valid = FULL || lv[i];
+                    const float ub = sel<kTapeA>(nd, i, zl);
+                    const float dbar = valid ? -vbar[i] - ab[i] : 0.0f;
+                    float mb = __builtin_fmaf(gamma, dbar, -(gamma * ub));
+                    mb += sel<kTapeK>(nd, i, mminb);
+                    mb = valid ? mb : 0.0f;
+                    const float rcb = vbar[i] + ub + mb;
+                    revb[i] = out ? mb : 0.0f;
+                    rbar[i] = ab[i] + rcb;
+                    cbar[i] = valid ? rcb : 0.0f;
+                }
+            } else if constexpr (KIND == kAdjNaive) {
+                const float mminb = inv_n * al;
+#pragma unroll
+                for (int i = 0; i < LPL; ++i) {
+                    const bool valid = FULL || lv[i];
+                    vbar[i] += sel<kTapeA>(nd, i, zl);
+                    const float mb = valid ? __builtin_fmaf(-inv_n, ab[i], sel<kTapeK>(nd, i, mminb)) : 0.0f;
+                    const float rcb = vbar[i] + mb;
+                    revb[i] = out ? mb : 0.0f;
+                    rbar[i] = ab[i] + rcb;
+                    cbar[i] = valid ? rcb : 0.0f;
+                }
+            } else {  // final pass
+                int first = 0x7fffffff;
+#pragma unroll
+                for (int i = 0; i < LPL; ++i) {
+                    const bool valid = FULL || lv[i];
+                    const bool isk = has(nd, i, kTapeK);
+                    vbar[i] += sel<kTapeA>(nd, i, zl);
+                    float mb = valid ? nd.gx.get(i) : 0.0f;
+                    mb -= sel<kTapeK>(nd, i, al);
+                    const float rcb = vbar[i] + mb;
+                    revb[i] = out ? mb : 0.0f;
+                    rbar[i] = rcb + sel<kTapeK>(nd, i, g_lb_f);
+                    cbar[i] = valid ? rcb : 0.0f;
+                    if (isk) first = sub * LPL + i;
+                }
+                const int kstar = group_min_i<G>(first);
+                if (out) {
+                    int dd = kstar - next_label;
+                    dd = dd < 0 ? -dd : dd;
+                    wl = __builtin_fmaf(g_lb_f, (float)(dd < T ? dd : T), wl);
+                }
+                next_label = kstar;
+            }
+            label_offsets<4>(rs, os);
+            store_f32<LPL, FULL>(r_bout, rs, os, revb);
+            label_offsets<4>(sc.f, os);
+            store_f32<LPL, FULL>(r_abar, sc.f, os, rbar);
+        }
+        if (ok && sub == 0 && out && wl != 0.0f) add_edge_grad(sc.w, wl);
+        advance<FWD>(sc);
     }
 
     // One adjoint pass over the forward pass FWD of kind KIND.  IS_FIRST: the half-step's
@@ -576,7 +814,7 @@ struct AdjWalker {
                     const int lab = sub * LPL + i;
                     const float ub = lab == a_b ? zl : 0.0f;
                     const float dbar = valid ? -vbar[i] - ab[i] : 0.0f;
-                    float mb = gamma * dbar - gamma * ub;
+                    float mb = __builtin_fmaf(gamma, dbar, -(gamma * ub));
                     if (lab == kstar) mb += mminb;
                     mb = valid ? mb : 0.0f;
                     const float rcb = vbar[i] + ub + mb;
@@ -591,8 +829,7 @@ struct AdjWalker {
                     const bool valid = FULL || lv[i];
                     const int lab = sub * LPL + i;
                     if (lab == a_b) vbar[i] += zl;
-                    float mb = valid ? -inv_n * ab[i] : 0.0f;
-                    if (lab == kstar) mb += mminb;
+                    const float mb = valid ? __builtin_fmaf(-inv_n, ab[i], lab == kstar ? mminb : 0.0f) : 0.0f;
                     const float rcb = vbar[i] + mb;
                     revb[i] = out ? mb : 0.0f;
                     rbar[i] = ab[i] + rcb;
@@ -615,7 +852,7 @@ struct AdjWalker {
                 if (out) {
                     int dd = kstar - next_label;
                     dd = dd < 0 ? -dd : dd;
-                    wl += g_lb_f * (float)(dd < T ? dd : T);
+                    wl = __builtin_fmaf(g_lb_f, (float)(dd < T ? dd : T), wl);
                 }
                 next_label = kstar;
             }
@@ -629,12 +866,25 @@ struct AdjWalker {
     }
 };
 
-template <int G, int LPL, int PF, typename TT, bool FULL, bool HAS_THETA>
+// One adjoint pass, recomputing the selections (TAPE false) or reading them from the
+// pass's tape.
+template <bool TAPE, bool FWD, int KIND, bool IS_FIRST, typename AW>
+__device__ __forceinline__ void adjoint_pass(AW& wk, const unsigned* tape, unsigned tape_bytes, float g) {
+    if constexpr (TAPE) {
+        wk.r_tape = make_rsrc(tape, tape_bytes);
+        wk.template run_pass_tape<FWD, KIND, IS_FIRST>(g);
+    } else {
+        wk.template run_pass<FWD, KIND, IS_FIRST>(g);
+    }
+}
+
+template <int G, int LPL, int PF, typename TT, bool FULL, bool HAS_THETA, bool TAPE>
 __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
     using AW = AdjWalker<G, LPL, PF, TT, FULL, HAS_THETA>;
-    __shared__ float s_v[64 * LPL];
-    __shared__ float s_cb[64 * LPL];
-    __shared__ int s_src[64 * LPL];
+    // LDS for the recomputing form's long-reach message adjoint (unused with a tape)
+    __shared__ float s_v[TAPE ? 1 : 64 * LPL];
+    __shared__ float s_cb[TAPE ? 1 : 64 * LPL];
+    __shared__ int s_src[TAPE ? 1 : 64 * LPL];
     constexpr int CPW = 64 / G;
     const int lane = threadIdx.x;
     const int sub = lane % G;
@@ -642,6 +892,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
     const int chain = blockIdx.x * CPW + grp;
     AW wk(a, chain, sub, grp, s_v, s_cb, s_src);
     const unsigned vb = a.vol_bytes_f32;
+    const unsigned tb = a.tape_bytes;
     if (a.mode == kModeFinal) {
         // final row pass: forward min-marginal pass (messages M[1], reverse M[0]), then R0
         wk.g_lb_f = (float)a.g_lb;
@@ -650,12 +901,12 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
         wk.r_rmsg = make_rsrc(a.rec_msg[0], vb);
         wk.r_bin = make_rsrc(nullptr, 0u);
         wk.r_bout = make_rsrc(a.bbar[0], vb);
-        wk.template run_pass<true, kAdjFinal, false>(0.0f);
+        adjoint_pass<TAPE, true, kAdjFinal, false>(wk, a.tape[1], tb, 0.0f);
         wk.r_cmsg = make_rsrc(a.rec_msg[0], vb);
         wk.r_bin = make_rsrc(a.bbar[0], vb);
         wk.r_bout = make_rsrc(nullptr, 0u);
         // the final pass's R0 adjoint turns dL/dr into dL/dcost and dL/d(dual) = -dL/dr
-        wk.template run_pass<false, kAdjR0, false>(0.0f);
+        adjoint_pass<TAPE, false, kAdjR0, false>(wk, a.tape[0], tb, 0.0f);
         return;
     }
     const int P = a.mode == kModeIterative ? a.n_pass : 1;
@@ -663,6 +914,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
         const float* lam_s = a.lam0;
         const float* msg_s = a.rec_msg[1];
         const float* msg_r = a.rec_msg[0];
+        const unsigned* tp = a.tape[1];
         float g = a.gamma[0];
 #pragma unroll
         for (int i = 1; i <= 8; ++i) {
@@ -670,6 +922,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
                 if (i > 1) lam_s = a.rec_lam[i - 1 < 8 ? i - 1 : 7];
                 msg_s = a.rec_msg[i];
                 msg_r = a.rec_msg[i - 1];
+                tp = a.tape[i];
                 g = a.gamma[i - 1];
             }
         }
@@ -684,40 +937,44 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
         wk.r_bout = make_rsrc((s & 1) ? b_even : b_odd, vb);
         const bool fwd = ((s - 1) & 1) == 0;
         if (a.mode == kModeNaive) {
-            wk.template run_pass<true, kAdjNaive, true>(0.0f);
+            adjoint_pass<TAPE, true, kAdjNaive, true>(wk, tp, tb, 0.0f);
         } else if (s == P) {
-            if (fwd) wk.template run_pass<true, kAdjIter, true>(g);
-            else wk.template run_pass<false, kAdjIter, true>(g);
+            if (fwd) adjoint_pass<TAPE, true, kAdjIter, true>(wk, tp, tb, g);
+            else adjoint_pass<TAPE, false, kAdjIter, true>(wk, tp, tb, g);
         } else {
-            if (fwd) wk.template run_pass<true, kAdjIter, false>(g);
-            else wk.template run_pass<false, kAdjIter, false>(g);
+            if (fwd) adjoint_pass<TAPE, true, kAdjIter, false>(wk, tp, tb, g);
+            else adjoint_pass<TAPE, false, kAdjIter, false>(wk, tp, tb, g);
         }
     }
     wk.r_lam = make_rsrc(a.lam0, vb);
     wk.r_cmsg = make_rsrc(a.rec_msg[0], vb);
     wk.r_bin = make_rsrc(a.bbar[0], vb);
     wk.r_bout = make_rsrc(nullptr, 0u);
-    wk.template run_pass<false, kAdjR0, false>(0.0f);
+    adjoint_pass<TAPE, false, kAdjR0, false>(wk, a.tape[0], tb, 0.0f);
 }
 
 constexpr int kAdjPF = 4;
 
-template <int G, int LPL, typename TT, bool HAS_THETA>
+template <int G, int LPL, typename TT, bool HAS_THETA, bool TAPE>
 hipError_t launch_adjoint_tt(const AdjArgs& a, hipStream_t st) {
     constexpr int CPW = 64 / G;
     const unsigned blocks = (unsigned)((a.n_chains + CPW - 1) / CPW);
     if (a.K == G * LPL)
-        hipLaunchKernelGGL((adjoint_kernel<G, LPL, kAdjPF, TT, true, HAS_THETA>), dim3(blocks), dim3(64), 0, st, a);
+        hipLaunchKernelGGL((adjoint_kernel<G, LPL, kAdjPF, TT, true, HAS_THETA, TAPE>), dim3(blocks), dim3(64), 0, st,
+                           a);
     else
-        hipLaunchKernelGGL((adjoint_kernel<G, LPL, kAdjPF, TT, false, HAS_THETA>), dim3(blocks), dim3(64), 0, st, a);
+        hipLaunchKernelGGL((adjoint_kernel<G, LPL, kAdjPF, TT, false, HAS_THETA, TAPE>), dim3(blocks), dim3(64), 0, st,
+                           a);
     return hipGetLastError();
 }
 
-template <int G, int LPL>
+// TAPE: the selections come from the tapes a.tape[] written by the record sweep in tape
+// mode (distance transforms that reach at most one lane across).
+template <int G, int LPL, bool TAPE>
 hipError_t launch_adjoint_tile(const AdjArgs& a, dm_dtype dt, hipStream_t st) {
-    if (a.theta == nullptr) return launch_adjoint_tt<G, LPL, float, false>(a, st);
-    if (dt == DM_F16) return launch_adjoint_tt<G, LPL, _Float16, true>(a, st);
-    return launch_adjoint_tt<G, LPL, float, true>(a, st);
+    if (a.theta == nullptr) return launch_adjoint_tt<G, LPL, float, false, TAPE>(a, st);
+    if (dt == DM_F16) return launch_adjoint_tt<G, LPL, _Float16, true, TAPE>(a, st);
+    return launch_adjoint_tt<G, LPL, float, true, TAPE>(a, st);
 }
 
 }  // namespace dm

@@ -76,7 +76,27 @@ struct SweepArgs {
     float gamma[8];
     float* rec_lam[8];   // record mode: dual after update pass s (s = 1 .. n_pass-1)
     float* rec_msg[9];   // record mode: messages written by pass s (s = 0: backward message pass)
+    unsigned* tape[9];   // tape mode: selection tape of pass s (s = 0: backward message pass)
+    unsigned tape_bytes; // bytes of one tape
+    unsigned tape_px;    // tape bytes per pixel of this tile (byte accounting only)
 };
+
+// Selection tape: what the adjoint of a pass needs from the forward, one byte per label
+// and node: which operand each min of the message's distance transform took, and the
+// node's two argmins.  Per lane and node the bytes of its LPL labels are packed into
+// kTapeWords(LPL) dwords (label i in byte i % 4 of word i / 4); a node's lanes are
+// contiguous, so the tape of a pass is [pixel][lane][word].
+enum TapeBit : unsigned {
+    kTapeFI = 1,    // forward in-lane scan: took the left neighbour + w (not v itself)
+    kTapeBI = 2,    // backward in-lane scan: took the right neighbour + w
+    kTapeF = 4,     // message entry from the forward scan of this lane
+    kTapeB = 8,     // from the backward scan of this lane
+    kTapeCL = 16,   // from the left lane's forward-scan end
+    kTapeCR = 32,   // from the right lane's backward-scan end (none of F/B/CL/CR: the cap)
+    kTapeK = 64,    // argmin of the min-marginal m (lowest label)
+    kTapeA = 128,   // argmin of the message input (lowest label)
+};
+__host__ __device__ constexpr int kTapeWords(int lpl) { return (lpl + 3) / 4; }
 
 // Offset that is outside every buffer (volumes are at most kMaxVolBytes): loads return 0,
 // stores are dropped, also for the vector chunks at kOOB + 16*k (no 32-bit wrap).
@@ -189,6 +209,33 @@ __device__ __forceinline__ void store_f32(__amdgpu_buffer_rsrc_t r, unsigned off
     }
 }
 
+// Candidate value base + w*k of a source k labels away, as one fused operation (the
+// forward, the tape recording and the adjoint's recomputation round it alike whatever
+// the compiler contracts elsewhere).
+__device__ __forceinline__ float wdist(float w, int k, float base) { return __builtin_fmaf(w, (float)k, base); }
+
+// Tape byte BIT of the group's lowest label whose value equals the group minimum mn,
+// or'ed into the owning lane's tape words (label sub*LPL + i: byte i % 4 of word i / 4).
+template <int G, int LPL, bool FULL, int NW>
+__device__ __forceinline__ void tape_argmin(const float (&x)[LPL], float mn, const bool (&lv)[LPL], int sub,
+                                            unsigned bit, uint32_t (&tw)[NW]) {
+    int first = LPL;
+#pragma unroll
+    for (int i = LPL - 1; i >= 0; --i)
+        if ((FULL || lv[i]) && x[i] == mn) first = i;
+    bool own;
+    if constexpr (G == 64) {
+        const unsigned long long mask = __builtin_amdgcn_ballot_w64(first < LPL);
+        own = first < LPL && (int)__builtin_ctzll(mask) == sub;
+    } else {
+        const int g = group_min_i<G>(first < LPL ? sub * LPL + first : 0x7fffffff);
+        own = first < LPL && g == sub * LPL + first;
+    }
+    const unsigned b = bit << (8 * (first & 3));
+#pragma unroll
+    for (int j = 0; j < NW; ++j) tw[j] |= (own && (first >> 2) == j) ? b : 0u;
+}
+
 // ------------------------------------------------------------------ chain walker
 template <int G, int LPL, int PF, typename TT, bool FULL, bool HAS_THETA>
 struct Walker {
@@ -219,6 +266,12 @@ struct Walker {
     bool lv[LPL];     // label exists (and the chain exists)
     int dt_steps;     // lanes the distance transform must reach across
     float dl, dr;     // distance-transform lane shifts; lanes without a source keep kBig
+    // tape mode: store descriptor of the current pass's tape, this lane's tape offset at
+    // node 0 and its per-node step
+    static constexpr int kTW = kTapeWords(LPL);
+    static constexpr int kFar = 1 << 20;  // source distance of a missing neighbour lane
+    __amdgpu_buffer_rsrc_t r_tape_st;
+    unsigned tp0, tp_step;
 
     __device__ __forceinline__ Walker(SweepArgs args, int chain, int sub_)
         : sub(sub_), n(args.n), K(args.K), T(args.T), sign(args.sign), inv_n(args.inv_n) {
@@ -249,6 +302,10 @@ struct Walker {
         for (int i = 0; i < LPL; ++i) lv[i] = FULL ? true : (ok && sub * LPL + i < K);
         const int need = (args.T - 1 + LPL - 1) / LPL;
         dt_steps = need < G - 1 ? need : G - 1;
+        const unsigned long long ts = (unsigned long long)(G * kTW * 4);
+        tp0 = ok ? (unsigned)(cpx * ts + (unsigned long long)(sub * kTW * 4)) : kOOB;
+        tp_step = ok ? (unsigned)((unsigned long long)args.node_px * ts) : 0u;
+        r_tape_st = make_rsrc(nullptr, 0u);
     }
 
     // Per-label byte offsets of an access at `off` (element size E).  A full tile uses
@@ -329,10 +386,6 @@ struct Walker {
     // distance transform reaches exactly one lane across (dt_steps == 1).
     template <bool DT1>
     __device__ __forceinline__ void message(const float (&v)[LPL], float vmin, float wt, float (&out)[LPL]) {
-        float wk[LPL + 1];
-        wk[0] = 0.0f;
-#pragma unroll
-        for (int i = 1; i <= LPL; ++i) wk[i] = i == 1 ? wt : wt * (float)i;
         float f[LPL], b[LPL];
         f[0] = v[0];
 #pragma unroll
@@ -347,7 +400,7 @@ struct Walker {
 #pragma unroll
             for (int i = 0; i < LPL; ++i) {
                 const float e = fminf(fminf(f[i], b[i]), cap);
-                const float d = fminf(e, fminf(cl + wk[i + 1], cr + wk[LPL - i])) - vmin;
+                const float d = fminf(e, fminf(wdist(wt, i + 1, cl), wdist(wt, LPL - i, cr))) - vmin;
                 out[i] = (FULL || lv[i]) ? d : 0.0f;
             }
         } else {
@@ -356,14 +409,139 @@ struct Walker {
                 const float cr = from_right(b[0]);
 #pragma unroll
                 for (int i = 0; i < LPL; ++i) {
-                    f[i] = fminf(f[i], cl + wk[i + 1]);
-                    b[i] = fminf(b[i], cr + wk[LPL - i]);
+                    f[i] = fminf(f[i], wdist(wt, i + 1, cl));
+                    b[i] = fminf(b[i], wdist(wt, LPL - i, cr));
                 }
             }
 #pragma unroll
             for (int i = 0; i < LPL; ++i) {
                 const float d = fminf(fminf(f[i], b[i]), cap) - vmin;
                 out[i] = (FULL || lv[i]) ? d : 0.0f;
+            }
+        }
+    }
+
+    // Integer value of the neighbour lane (kFar at the group's first / last lane).
+    __device__ __forceinline__ int from_left_i(int x) const {
+        if constexpr (G == 16) return __builtin_amdgcn_update_dpp(kFar, x, kRowShr1, 0xF, 0xF, false);
+        const int y = __builtin_amdgcn_update_dpp(kFar, x, kWaveShr1, 0xF, 0xF, false);
+        return (G < 64 && sub == 0) ? kFar : y;
+    }
+    __device__ __forceinline__ int from_right_i(int x) const {
+        if constexpr (G == 16) return __builtin_amdgcn_update_dpp(kFar, x, kRowShl1, 0xF, 0xF, false);
+        const int y = __builtin_amdgcn_update_dpp(kFar, x, kWaveShl1, 0xF, 0xF, false);
+        return (G < 64 && sub == G - 1) ? kFar : y;
+    }
+
+    // message<DT1> (same values, same arithmetic) that also records, per label, the
+    // operand each min took (tape bits FI, BI, F, B, CL, CR).  The distance transform
+    // reaches at most one lane across (dt_steps 0 or 1).  Ties between candidates go to
+    // the closer source, then to the left one (lower label); the cap (vmin + wT) wins
+    // over a window candidate only if strictly lower, and a source at distance >= T is
+    // the cap.
+    //
+    // Fast form (T >= LPL, so an in-lane source is always within the window): the left
+    // candidate wins a tie with the right one when it is the label itself (distance 0),
+    // which covers the ties of untouched labels; a wave with any other tie between the
+    // left and right candidates takes the general form with per-label source distances.
+    template <bool DT1>
+    __device__ __forceinline__ void message_tp(const float (&v)[LPL], float vmin, float wt, float (&out)[LPL],
+                                               uint32_t (&tw)[kTW]) {
+        float f[LPL], b[LPL];
+        bool fi[LPL], bi[LPL];
+        f[0] = v[0];
+        fi[0] = false;
+#pragma unroll
+        for (int i = 1; i < LPL; ++i) {
+            const float c = f[i - 1] + wt;
+            f[i] = fminf(v[i], c);
+            fi[i] = c < v[i];
+        }
+        b[LPL - 1] = v[LPL - 1];
+        bi[LPL - 1] = false;
+#pragma unroll
+        for (int i = LPL - 2; i >= 0; --i) {
+            const float c = b[i + 1] + wt;
+            b[i] = fminf(v[i], c);
+            bi[i] = c < v[i];
+        }
+        // source distances of the lane's chain ends (the neighbour lanes' candidates)
+        int df_end = 0, db_beg = 0;
+#pragma unroll
+        for (int i = 1; i < LPL; ++i) df_end = fi[i] ? df_end + 1 : 0;
+#pragma unroll
+        for (int i = LPL - 2; i >= 0; --i) db_beg = bi[i] ? db_beg + 1 : 0;
+        const float cap = __builtin_fmaf(wt, Tf, vmin);
+        float cl = kBig, cr = kBig;
+        int dcl = kFar, dcr = kFar;
+        if constexpr (DT1) {
+            cl = from_left(f[LPL - 1]);
+            cr = from_right(b[0]);
+            dcl = from_left_i(df_end);
+            dcr = from_right_i(db_beg);
+        }
+        float vl[LPL], vr[LPL];
+        bool useF[LPL], useB[LPL];
+        bool hard = T < LPL;
+#pragma unroll
+        for (int j = 0; j < kTW; ++j) tw[j] = 0u;
+#pragma unroll
+        for (int i = 0; i < LPL; ++i) {
+            const bool valid = FULL || lv[i];
+            vl[i] = wdist(wt, i + 1, cl);
+            vr[i] = wdist(wt, LPL - i, cr);
+            if constexpr (DT1) {
+                const float e = fminf(fminf(f[i], b[i]), cap);
+                const float d = fminf(e, fminf(vl[i], vr[i])) - vmin;
+                out[i] = valid ? d : 0.0f;
+            } else {
+                const float d = fminf(fminf(f[i], b[i]), cap) - vmin;
+                out[i] = valid ? d : 0.0f;
+            }
+            useF[i] = !DT1 || f[i] <= vl[i];
+            useB[i] = !DT1 || b[i] <= vr[i];
+            const float lvv = useF[i] ? f[i] : vl[i];
+            const float rvv = useB[i] ? b[i] : vr[i];
+            const bool left = lvv <= rvv;
+            // a tie is decided here only when the left candidate is the label itself
+            hard |= valid & (lvv == rvv) & (fi[i] | !useF[i]);
+            const float wv = left ? lvv : rvv;
+            const bool near = left ? (useF[i] | (dcl + i + 1 < T)) : (useB[i] | (dcr + LPL - i < T));
+            const bool win = (wv <= cap) & near;
+            const unsigned t1 = useF[i] ? kTapeF : kTapeCL;
+            const unsigned t2 = useB[i] ? kTapeB : kTapeCR;
+            const unsigned route = win ? (left ? t1 : t2) : 0u;
+            const unsigned x = route | (fi[i] ? kTapeFI : 0u) | (bi[i] ? kTapeBI : 0u);
+            tw[i >> 2] |= (valid ? x : 0u) << (8 * (i & 3));
+        }
+        if (__builtin_amdgcn_ballot_w64(hard) != 0ull) {
+            // general form: per-label source distances decide the ties
+            int df[LPL], db[LPL];
+            df[0] = 0;
+#pragma unroll
+            for (int i = 1; i < LPL; ++i) df[i] = fi[i] ? df[i - 1] + 1 : 0;
+            db[LPL - 1] = 0;
+#pragma unroll
+            for (int i = LPL - 2; i >= 0; --i) db[i] = bi[i] ? db[i + 1] + 1 : 0;
+#pragma unroll
+            for (int j = 0; j < kTW; ++j) tw[j] = 0u;
+#pragma unroll
+            for (int i = 0; i < LPL; ++i) {
+                const bool valid = FULL || lv[i];
+                const float lvv = useF[i] ? f[i] : vl[i];
+                const int ld = useF[i] ? df[i] : dcl + i + 1;
+                const float rvv = useB[i] ? b[i] : vr[i];
+                const int rd = useB[i] ? db[i] : dcr + LPL - i;
+                const bool left = (lvv < rvv) | ((lvv == rvv) & (ld <= rd));
+                const float wv = left ? lvv : rvv;
+                const int wd = left ? ld : rd;
+                const bool win = (wv <= cap) & (wd < T);
+                unsigned x = (fi[i] ? kTapeFI : 0u) | (bi[i] ? kTapeBI : 0u);
+                x |= (win & left & useF[i]) ? kTapeF : 0u;
+                x |= (win & !left & useB[i]) ? kTapeB : 0u;
+                x |= (win & left & !useF[i]) ? kTapeCL : 0u;
+                x |= (win & !left & !useB[i]) ? kTapeCR : 0u;
+                tw[i >> 2] |= (valid ? x : 0u) << (8 * (i & 3));
             }
         }
     }
@@ -378,7 +556,7 @@ struct Walker {
     // One directional pass.  KIND: 0 = backward message pass (R0), 1 = iterative update,
     // 2 = naive update, 3 = final min-marginals.  Adds the normalisation constants of a
     // message pass (= chain optimum) to `opt`.
-    template <bool FWD, int KIND, bool DT1>
+    template <bool FWD, int KIND, bool DT1, bool TP>
     __device__ __forceinline__ void pass(float gamma, bool store_msg, double& opt) {
         constexpr bool WANT_REV = KIND != 0;
         float carry[LPL];
@@ -390,6 +568,7 @@ struct Walker {
         Cursor lc = cursor_at(FWD);
         unsigned sf = lc.f;                                           // store cursor (dual, messages)
         unsigned sl = lab0 + (FWD ? 0u : (unsigned)(n - 1)) * lab_step;  // label slot
+        unsigned stp = tp0 + (FWD ? 0u : (unsigned)(n - 1)) * tp_step;   // tape slot
         Node ring[PF];
         // Issued in slot order (the scheduler may not reorder them): the steady-state loop
         // waits for slot q's loads assuming the later slots' loads were issued after them.
@@ -404,7 +583,7 @@ struct Walker {
         for (; t0 + PF < n; t0 += PF) {
 #pragma unroll
             for (int q = 0; q < PF; ++q) {
-                step<FWD, KIND, false, DT1>(ring[q], true, carry, gamma, msg_st, opt, sf, sl);
+                step<FWD, KIND, false, DT1, TP>(ring[q], true, carry, gamma, msg_st, opt, sf, sl, stp);
                 load<FWD, WANT_REV>(ring[q], lc);
             }
         }
@@ -413,24 +592,29 @@ struct Walker {
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
             const int t = t0 + q;
-            if (t < n) step<FWD, KIND, true, DT1>(ring[q], t < n - 1, carry, gamma, msg_st, opt, sf, sl);
+            if (t < n) step<FWD, KIND, true, DT1, TP>(ring[q], t < n - 1, carry, gamma, msg_st, opt, sf, sl, stp);
         }
     }
 
-    // A pass with the distance-transform variant this walker's truncation needs.
-    template <bool FWD, int KIND>
+    // A pass with the distance-transform variant this walker's truncation needs.  TP:
+    // also write the pass's selection tape (the host enables it only for dt_steps <= 1).
+    template <bool FWD, int KIND, bool TP = false>
     __device__ __forceinline__ void run_pass(float gamma, bool store_msg, double& opt) {
         if (dt_steps == 1)
-            pass<FWD, KIND, true>(gamma, store_msg, opt);
+            pass<FWD, KIND, true, TP>(gamma, store_msg, opt);
         else
-            pass<FWD, KIND, false>(gamma, store_msg, opt);
+            pass<FWD, KIND, false, TP>(gamma, store_msg, opt);
     }
 
-    template <bool FWD, int KIND, bool TAIL, bool DT1>
+    template <bool FWD, int KIND, bool TAIL, bool DT1, bool TP>
     __device__ __forceinline__ void step(const Node& nd, bool has_next, float (&carry)[LPL], float gamma,
-                                         __amdgpu_buffer_rsrc_t msg_st, double& opt, unsigned& sf, unsigned& sl) {
+                                         __amdgpu_buffer_rsrc_t msg_st, double& opt, unsigned& sf, unsigned& sl,
+                                         unsigned& stp) {
         if constexpr (!TAIL) has_next = true;
         float vmin = 0.0f;
+        uint32_t tw[kTW];  // tape: message selections and the two argmins
+#pragma unroll
+        for (int j = 0; j < kTW; ++j) tw[j] = 0u;
         float r[LPL], lamv[LPL];
 #pragma unroll
         for (int i = 0; i < LPL; ++i) {
@@ -463,6 +647,15 @@ struct Walker {
             bmin = lane_min(v);
             group_min2<G>(mmin, bmin);
             vmin = bmin;
+            if constexpr (TP) {
+                // the message selections are or'ed in later: keep the argmin byte apart
+                uint32_t tk[kTW];
+#pragma unroll
+                for (int j = 0; j < kTW; ++j) tk[j] = 0u;
+                tape_argmin<G, LPL, FULL, kTW>(m, mmin, lv, sub, kTapeK, tk);
+#pragma unroll
+                for (int j = 0; j < kTW; ++j) tw[j] = tk[j];
+            }
             if constexpr (KIND == 1 || KIND == 2) {
                 float nl[LPL];
 #pragma unroll
@@ -495,7 +688,15 @@ struct Walker {
             if constexpr (KIND == 0) vmin = group_min<G>(lane_min(v));
             if constexpr (KIND == 0) opt += (double)vmin;
             if (has_next) {
-                message<DT1>(v, vmin, nd.w, carry);
+                if constexpr (TP) {
+                    uint32_t tm[kTW];
+                    message_tp<DT1>(v, vmin, nd.w, carry, tm);
+#pragma unroll
+                    for (int j = 0; j < kTW; ++j) tw[j] |= tm[j];
+                    tape_argmin<G, LPL, FULL, kTW>(v, vmin, lv, sub, kTapeA, tw);
+                } else {
+                    message<DT1>(v, vmin, nd.w, carry);
+                }
                 // slot of edge (j, j+1) / (j-1, j); a pass that keeps no messages stores
                 // through an empty descriptor (dropped) rather than branching per node
                 const unsigned mo = FWD ? sf : sf - f_step;
@@ -504,6 +705,10 @@ struct Walker {
                 store_f32<LPL, FULL>(msg_st, mo, os, carry);
             }
         }
+        if constexpr (TP) {
+            store_words<kTW>(r_tape_st, stp, tw);
+            stp = FWD ? stp + tp_step : stp - tp_step;
+        }
         sf = FWD ? sf + f_step : sf - f_step;
     }
 };
@@ -511,7 +716,10 @@ struct Walker {
 // Mode groups compiled as separate kernels (separate symbols in profiles, and each
 // kernel holds only the passes it runs): half-step (iterative or naive minorant),
 // final row pass, column optimum pass.
-enum ModeGroup : int { kGroupHalfStep = 0, kGroupFinal = 1, kGroupOptimum = 2, kGroupRecord = 3 };
+// Record: a half-step keeping every pass's messages and intermediate duals.  Tape: a
+// half-step writing every pass's selection tape (messages and duals in place, as in the
+// plain half-step).
+enum ModeGroup : int { kGroupHalfStep = 0, kGroupFinal = 1, kGroupOptimum = 2, kGroupRecord = 3, kGroupTape = 4 };
 
 // All passes of one mode group for the chain owned by this lane group.
 template <int G, int LPL, int PF, typename TT, bool FULL, bool HAS_THETA, int MG>
@@ -546,23 +754,31 @@ __device__ __forceinline__ void run_chain(const SweepArgs& a, int chain, int sub
         wk.template run_pass<true, 3>(0.0f, false, opt);
     } else if constexpr (MG == kGroupOptimum) {
         wk.template run_pass<false, 0>(0.0f, false, opt);
-    } else {  // kGroupRecord: recompute a half-step keeping every pass's messages and duals
+    } else {
+        // kGroupRecord: a half-step keeping every pass's messages and duals.  kGroupTape:
+        // the same walk with the message and dual buffers aliased by the caller (a.msg for
+        // every message volume; one volume for the intermediate duals), each pass writing
+        // its selection tape; the last pass's messages are not stored.
+        constexpr bool TP = MG == kGroupTape;
         const unsigned vb = wk.vol_bytes;
         wk.r_lam_st = make_rsrc(nullptr, 0u);
         wk.r_msg_st = make_rsrc(a.rec_msg[0], vb);
-        wk.template run_pass<false, 0>(0.0f, true, opt);
+        if constexpr (TP) wk.r_tape_st = make_rsrc(a.tape[0], a.tape_bytes);
+        wk.template run_pass<false, 0, TP>(0.0f, true, opt);
         const int P = a.mode == kModeIterative ? a.n_pass : 1;
         for (int s = 0; s < P; ++s) {
             const float* ld = a.lam_in;
             float* st = nullptr;
             float* mld = a.rec_msg[0];
             float* mst = a.rec_msg[1];
+            unsigned* tp = a.tape[1];
 #pragma unroll
             for (int i = 1; i < 8; ++i) {
                 if (s == i) {
                     ld = a.rec_lam[i];
                     mld = a.rec_msg[i];
                     mst = a.rec_msg[i + 1];
+                    tp = a.tape[i + 1];
                 }
             }
 #pragma unroll
@@ -575,16 +791,18 @@ __device__ __forceinline__ void run_chain(const SweepArgs& a, int chain, int sub
             wk.r_lam_st = make_rsrc(st, st != nullptr ? vb : 0u);
             wk.r_msg_ld = make_rsrc(mld, vb);
             wk.r_msg_st = make_rsrc(mst, vb);
+            if constexpr (TP) wk.r_tape_st = make_rsrc(tp, a.tape_bytes);
+            const bool keep_msg = !TP || s + 1 < P;
             float g = a.gamma[0];
 #pragma unroll
             for (int i = 1; i < 8; ++i)
                 if (s == i) g = a.gamma[i];
             if (a.mode != kModeIterative)
-                wk.template run_pass<true, 2>(0.0f, true, opt);
+                wk.template run_pass<true, 2, TP>(0.0f, keep_msg, opt);
             else if ((s & 1) == 0)
-                wk.template run_pass<true, 1>(g, true, opt);
+                wk.template run_pass<true, 1, TP>(g, keep_msg, opt);
             else
-                wk.template run_pass<false, 1>(g, true, opt);
+                wk.template run_pass<false, 1, TP>(g, keep_msg, opt);
         }
     }
     if (a.opt != nullptr && wk.ok && sub == 0) a.opt[chain] = opt;
@@ -616,6 +834,7 @@ hipError_t launch_tt(const SweepArgs& a, hipStream_t st) {
     if (a.mode & kRecordFlag) {
         SweepArgs b = a;
         b.mode = a.mode & ~kRecordFlag;
+        if (a.tape[0] != nullptr) return launch_mg<G, LPL, TT, HAS_THETA, kGroupTape>(b, st);
         return launch_mg<G, LPL, TT, HAS_THETA, kGroupRecord>(b, st);
     }
     if (a.mode == kModeFinal) return launch_mg<G, LPL, TT, HAS_THETA, kGroupFinal>(a, st);

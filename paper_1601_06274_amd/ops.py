@@ -48,7 +48,8 @@ def _cost_dtype(cost):
 
 
 def discrete_params(T=3, n_iters=10, n_half_steps=0, minorant="iterative", gammas=(0.25, 0.25, 1.0),
-                    warm_start=False, tile=None, keep_checkpoints=False) -> L.DmDiscreteParams:
+                    warm_start=False, tile=None, keep_checkpoints=False,
+                    recompute_selections=False) -> L.DmDiscreteParams:
     p = L.DmDiscreteParams()
     p.n_iters = int(n_iters)
     p.n_half_steps = int(n_half_steps)
@@ -68,6 +69,8 @@ def discrete_params(T=3, n_iters=10, n_half_steps=0, minorant="iterative", gamma
     # False/True -> 0/1 (dual checkpoints, messages recomputed); 2 or "record" -> 2 (the
     # forward also keeps every pass's messages and intermediate duals)
     p.keep_checkpoints = 2 if keep_checkpoints in (2, "record") else (1 if keep_checkpoints else 0)
+    # the backward recomputes the selections instead of reading tapes (same results)
+    p.recompute_selections = 1 if recompute_selections else 0
     return p
 
 
@@ -91,16 +94,18 @@ def tile_for(K: int):
 def solve_discrete(cost, w_h, w_v, *, T=3, n_iters=10, n_half_steps=0, minorant="iterative",
                    gammas=(0.25, 0.25, 1.0), dual=None, warm_start=False, want_minmarg=True,
                    want_bounds=True, want_trace=False, tile=None, stream=None, workspace=None,
-                   labels=None, minmarg=None, keep_checkpoints=False) -> DiscreteResult:
+                   labels=None, minmarg=None, keep_checkpoints=False, recompute_selections=False) -> DiscreteResult:
     """Dual_MM on the GPU (dm_solve_discrete).  With keep_checkpoints the returned
-    workspace holds what solve_discrete_backward needs."""
+    workspace holds what solve_discrete_backward needs (called with the same
+    keep_checkpoints and recompute_selections)."""
     H, W, K = cost.shape
     dev = cost.device
     _check_dev("cost", cost)
     _check_dev("w_h", w_h, torch.float32, (H, W - 1))
     _check_dev("w_v", w_v, torch.float32, (H - 1, W))
     dt = _cost_dtype(cost)
-    p = discrete_params(T, n_iters, n_half_steps, minorant, gammas, warm_start, tile, keep_checkpoints)
+    p = discrete_params(T, n_iters, n_half_steps, minorant, gammas, warm_start, tile, keep_checkpoints,
+                        recompute_selections)
     shape = L.DmShape(W, H, K)
     lib = L.lib()
     ws_bytes = lib.dm_solve_discrete_workspace(shape, dt, ctypes.byref(p))
@@ -134,14 +139,15 @@ def solve_discrete(cost, w_h, w_v, *, T=3, n_iters=10, n_half_steps=0, minorant=
 def solve_discrete_backward(cost, w_h, w_v, dual, fwd_workspace, *, grad_minmarg=None, grad_lb=0.0, T=3,
                             n_iters=10, n_half_steps=0, minorant="iterative", gammas=(0.25, 0.25, 1.0), tile=None,
                             grad_cost=None, grad_w_h=None, grad_w_v=None, accumulate=False, workspace=None,
-                            stream=None, keep_checkpoints=True):
+                            stream=None, keep_checkpoints=True, recompute_selections=False):
     """Adjoint of solve_discrete (dm_solve_discrete_backward); the forward must have run with
     keep_checkpoints=True and the same parameters.  Returns (grad_cost, grad_w_h, grad_w_v)."""
     H, W, K = cost.shape
     dev = cost.device
     _check_dev("dual", dual, torch.float32, (H, W, K))
     _check_dev("grad_minmarg", grad_minmarg, torch.float32, (H, W, K))
-    p = discrete_params(T, n_iters, n_half_steps, minorant, gammas, False, tile, keep_checkpoints or True)
+    p = discrete_params(T, n_iters, n_half_steps, minorant, gammas, False, tile, keep_checkpoints or True,
+                        recompute_selections)
     shape = L.DmShape(W, H, K)
     lib = L.lib()
     ws_bytes = max(int(lib.dm_solve_discrete_backward_workspace(shape, ctypes.byref(p))), 256)

@@ -249,3 +249,50 @@ def test_record_all_checkpoints_match_recompute(minorant):
     assert torch.equal(r1.bounds, r2.bounds)
     for a, b in zip(g1, g2):
         assert torch.equal(a, b)
+
+
+TAPE_CASES = [((4, 2), 8, 3, "iterative", 1), ((4, 2), 7, 1, "naive", 2), ((8, 4), 32, 5, "iterative", 2),
+              ((16, 4), 50, 3, "iterative", 1), ((32, 3), 96, 4, "naive", 1), ((64, 3), 192, 3, "iterative", 2),
+              ((64, 3), 150, 2, "iterative", 1), ((64, 4), 256, 3, "iterative", 1), ((64, 4), 200, 5, "naive", 2)]
+
+
+@pytest.mark.parametrize("tile,K,T,minorant,keep", TAPE_CASES)
+def test_selection_tape_matches_recompute(tile, K, T, minorant, keep):
+    """Backward reading the forward's selection tapes equals the backward that recomputes
+    the selections, bit for bit (full and partial tiles, distance transforms within a lane
+    or reaching one lane across, both minorants, tapes from the recompute or the forward)."""
+    _tape_vs_recompute(tile, K, T, minorant, keep, quantized=False)
+
+
+@pytest.mark.parametrize("tile,K,T", [((4, 2), 8, 3), ((16, 4), 64, 4), ((64, 3), 192, 3), ((32, 6), 150, 4)])
+def test_selection_tape_ties(tile, K, T):
+    """Costs and weights on a grid of quarter units: exact ties between candidates at
+    different distances are frequent, so the tape recording's general (distance) form runs
+    beside its fast form."""
+    _tape_vs_recompute(tile, K, T, "iterative", 1, quantized=True)
+
+
+def _tape_vs_recompute(tile, K, T, minorant, keep, quantized):
+    ops = _need()
+    theta, w_h, w_v = synth.tiny_instance(5, 9, K, seed=K + T, w_max=0.5)
+    if quantized:
+        theta = np.round(theta * 4) / 4
+        w_h = np.full_like(w_h, 0.25)
+        w_v = np.full_like(w_v, 0.25)
+    th, wh, wv = _dev(theta, torch.float16), _dev(w_h), _dev(w_v)
+    Gm = _dev(np.random.default_rng(K).normal(size=theta.shape))
+    print(f"[case] tape vs recompute tile={tile} K={K} T={T} {minorant} keep={keep} quantized={quantized}",
+          flush=True)
+    kw = dict(T=T, n_iters=2, minorant=minorant, tile=tile, keep_checkpoints=keep,
+              gammas=(0.25, 0.25, 1.0) if minorant == "iterative" else (1.0,))
+    out = {}
+    for rec in (True, False):
+        r = ops.solve_discrete(th, wh, wv, recompute_selections=rec, **kw)
+        g = ops.solve_discrete_backward(th, wh, wv, r.dual, r.workspace, grad_minmarg=Gm, grad_lb=0.5,
+                                        recompute_selections=rec, **kw)
+        torch.cuda.synchronize()
+        out[rec] = (r, g)
+    (r1, g1), (r2, g2) = out[True], out[False]
+    assert torch.equal(r1.labels, r2.labels) and torch.equal(r1.dual, r2.dual)
+    for a, b in zip(g1, g2):
+        assert torch.equal(a, b), float((a - b).abs().max())
