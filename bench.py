@@ -12,11 +12,15 @@ frames of that size).  One step is
     -> refine_continuous_backward -> solve_discrete_backward
        (dL/dcost and dL/dw for L = <G_m, min-marginals> + LB + <G_u, u>, seeded G)
 
-on images already resident in HBM.  ``ms_per_step`` is forward + backward per frame;
-``value`` is the forward's chain-DP label-node updates per frame (every dual
-iteration visits every label-node in 8 chain sweeps, 4 per half-step, the final
-labeling in 2 more) times frames per second of that step.  A forward-only loop is
-timed first (reported under "forward_only"; the sweep roofline comes from it).
+on images already resident in HBM.  The forward keeps, per half-step, every pass's
+selection tape (keep_checkpoints = 2; about 35 GB at this frame), so the backward
+differentiates without recomputing; the same step with dual checkpoints only (the
+backward recomputes every half-step) is timed beside it.  ``ms_per_step`` is forward
++ backward per frame; ``value`` is the forward's chain-DP label-node updates per frame
+(every dual iteration visits every label-node in 8 chain sweeps, 4 per half-step, the
+final labeling in 2 more) times frames per second of that step.  A forward-only loop
+(dual checkpoints only) is timed first ("forward_only"; the plain sweeps' roofline
+comes from it).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 Prints one JSON line.
@@ -275,37 +279,61 @@ def main():
         del buf
         ops.build_cost_volume(IL, IR, K, dtype=torch.float16, cost_out=cost, w_h=w_h, w_v=w_v)
         k2 = dict(dkw, n_iters=2)
+        # plain sweeps (dual checkpoints only), then the tape-recording forward and its backward
         ops.solve_discrete(cost, w_h, w_v, dual=dual, workspace=ws_d, labels=labels, minmarg=minmarg,
                            keep_checkpoints=True, **k2)
-        ops.solve_discrete_backward(cost, w_h, w_v, dual, ws_d, grad_minmarg=G_m, grad_lb=g_lb, grad_cost=grad_cost,
-                                    grad_w_h=grad_wh, grad_w_v=grad_wv, workspace=ws_db, **k2)
+        del ws_d, ws_db
+        dp2 = ops.discrete_params(keep_checkpoints=2, **k2)
+        ws_d2 = torch.empty(lib.dm_solve_discrete_workspace(shp, P._lib.DM_F16, ctypes.byref(dp2)),
+                            dtype=torch.uint8, device=dev)
+        ws_db2 = torch.empty(lib.dm_solve_discrete_backward_workspace(shp, ctypes.byref(dp2)), dtype=torch.uint8,
+                             device=dev)
+        ops.solve_discrete(cost, w_h, w_v, dual=dual, workspace=ws_d2, labels=labels, minmarg=minmarg,
+                           keep_checkpoints=2, **k2)
+        ops.solve_discrete_backward(cost, w_h, w_v, dual, ws_d2, grad_minmarg=G_m, grad_lb=g_lb, grad_cost=grad_cost,
+                                    grad_w_h=grad_wh, grad_w_v=grad_wv, workspace=ws_db2, keep_checkpoints=2, **k2)
         torch.cuda.synchronize()
         print(json.dumps({"traffic_probe_bytes": 4 * n}), flush=True)
         return 0
 
-    def forward():
+    # keep_checkpoints = 2: the forward records every pass's selection tape (about 35 GB at
+    # this frame, sized for 288 GB of HBM), the backward differentiates without recomputing.
+    dp2 = ops.discrete_params(keep_checkpoints=2, **dkw)
+    ws_d2 = torch.empty(lib.dm_solve_discrete_workspace(shp, P._lib.DM_F16, ctypes.byref(dp2)), dtype=torch.uint8,
+                        device=dev)
+    ws_db2 = torch.empty(lib.dm_solve_discrete_backward_workspace(shp, ctypes.byref(dp2)), dtype=torch.uint8,
+                         device=dev)
+
+    def forward(keep=True, ws=ws_d):
         ops.build_cost_volume(IL, IR, K, dtype=torch.float16, cost_out=cost, w_h=w_h, w_v=w_v)
-        res = ops.solve_discrete(cost, w_h, w_v, dual=dual, workspace=ws_d, labels=labels, minmarg=minmarg,
-                                 want_bounds=True, keep_checkpoints=True, **dkw)
+        res = ops.solve_discrete(cost, w_h, w_v, dual=dual, workspace=ws, labels=labels, minmarg=minmarg,
+                                 want_bounds=True, keep_checkpoints=keep, **dkw)
         ops.refine_continuous(cost, labels, w_h, w_v, workspace=ws_r, u_out=u, keep_tape=True, **rkw)
         return res
 
-    def backward():
+    def backward(keep=True, ws=ws_d, wsb=ws_db):
         ops.refine_continuous_backward(G_u, cost, w_h, w_v, ws_r, grad_cost=grad_cost, grad_w_h=grad_wh,
                                        grad_w_v=grad_wv, accumulate=False, workspace=ws_rb, **rkw)
-        ops.solve_discrete_backward(cost, w_h, w_v, dual, ws_d, grad_minmarg=G_m, grad_lb=g_lb, grad_cost=grad_cost,
-                                    grad_w_h=grad_wh, grad_w_v=grad_wv, accumulate=True, workspace=ws_db, **dkw)
+        ops.solve_discrete_backward(cost, w_h, w_v, dual, ws, grad_minmarg=G_m, grad_lb=g_lb, grad_cost=grad_cost,
+                                    grad_w_h=grad_wh, grad_w_v=grad_wv, accumulate=True, workspace=wsb,
+                                    keep_checkpoints=keep, **dkw)
 
     def step():
-        res = forward()
-        backward()
+        res = forward(2, ws_d2)
+        backward(2, ws_d2, ws_db2)
         return res
+
+    def step_recompute():
+        forward(True, ws_d)
+        backward(True, ws_d, ws_db)
 
     for _ in range(args.warmup):
         step()
+        step_recompute()
     torch.cuda.synchronize()
 
-    # Forward-only frames; the sweep kernels are bracketed by HIP events on their stream.
+    # Forward-only frames (dual checkpoints only); the sweep kernels are bracketed by HIP
+    # events on their stream.
     ops.profiler_enable(["sweep_h", "sweep_v", "sweep_final", "cost_volume"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -317,9 +345,9 @@ def main():
 
     prof = {k: ops.profiler_query(k) for k in ["sweep_h", "sweep_v", "sweep_final", "cost_volume"]}
 
-    # Timed steps: forward + backward of the whole frame; the backward's sweeps are
-    # bracketed by HIP events on their stream.
-    bwd_kinds = ["adjoint_h", "adjoint_v", "adjoint_final", "recompute_h", "recompute_v"]
+    # Timed steps: forward (recording the tapes) + backward of the whole frame; the
+    # record-mode and adjoint sweeps are bracketed by HIP events on their stream.
+    bwd_kinds = ["adjoint_h", "adjoint_v", "adjoint_final", "record_h", "record_v"]
     ops.profiler_enable(bwd_kinds)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -331,6 +359,7 @@ def main():
     ms_per_step = el * 1e3 / args.steps
     grad_finite = bool(torch.isfinite(grad_cost).all().item() and torch.isfinite(grad_wh).all().item())
     prof.update({k: ops.profiler_query(k) for k in bwd_kinds})
+    record_gb = (ws_d2.numel() + ws_db2.numel()) / 1e9
 
     def roof(kind, traffic_file, kernel):
         """Roofline object of one kernel kind: algorithmic bytes per launch / mean launch time."""
@@ -351,31 +380,13 @@ def main():
                 "avg_launch_ms": ms / n if n else None, "launches": n}
     n_h, ms_h, by_h = prof["sweep_h"]
     per_launch_gb = by_h / n_h / 1e9 if n_h else 0.0
-
-    # The same step with the forward keeping every pass's messages and intermediate duals
-    # (keep_checkpoints = 2: about 7 volumes per half-step in HBM, no recompute).
-    del ws_d, ws_db
-    torch.cuda.empty_cache()
-    dp2 = ops.discrete_params(keep_checkpoints=2, **dkw)
-    ws_d2 = torch.empty(lib.dm_solve_discrete_workspace(shp, P._lib.DM_F16, ctypes.byref(dp2)), dtype=torch.uint8,
-                        device=dev)
-    ws_db2 = torch.empty(lib.dm_solve_discrete_backward_workspace(shp, ctypes.byref(dp2)), dtype=torch.uint8,
-                         device=dev)
-
-    def step_record():
-        ops.build_cost_volume(IL, IR, K, dtype=torch.float16, cost_out=cost, w_h=w_h, w_v=w_v)
-        ops.solve_discrete(cost, w_h, w_v, dual=dual, workspace=ws_d2, labels=labels, minmarg=minmarg,
-                           want_bounds=True, keep_checkpoints=2, **dkw)
-        ops.refine_continuous(cost, labels, w_h, w_v, workspace=ws_r, u_out=u, keep_tape=True, **rkw)
-        ops.refine_continuous_backward(G_u, cost, w_h, w_v, ws_r, grad_cost=grad_cost, grad_w_h=grad_wh,
-                                       grad_w_v=grad_wv, accumulate=False, workspace=ws_rb, **rkw)
-        ops.solve_discrete_backward(cost, w_h, w_v, dual, ws_d2, grad_minmarg=G_m, grad_lb=g_lb, grad_cost=grad_cost,
-                                    grad_w_h=grad_wh, grad_w_v=grad_wv, accumulate=True, workspace=ws_db2,
-                                    keep_checkpoints=2, **dkw)
-    ms_record = _timed(step_record, max(2, args.steps // 2), torch)
-    record_gb = (ws_d2.numel() + ws_db2.numel()) / 1e9
     del ws_d2, ws_db2
     torch.cuda.empty_cache()
+
+    # The same step keeping only the dual before every half-step (keep_checkpoints = 1):
+    # the backward recomputes each half-step from its checkpoint, recording its tapes.
+    ms_recompute = _timed(step_recompute, max(2, args.steps // 2), torch)
+    recompute_gb = (ws_d.numel() + ws_db.numel()) / 1e9
 
     # FP16 storage: energy of this labeling on the unrounded (FP32) costs vs the FP32-path
     # labeling, FP64 sums (outside the timed region)
@@ -414,13 +425,18 @@ def main():
                        "solve_discrete_backward"],
         },
         "fwd_bwd_ms_per_frame": ms_per_step,
-        "fwd_bwd_record_all": {"ms_per_frame": ms_record, "workspace_GB": record_gb,
-                               "note": "forward keeps every pass's messages (keep_checkpoints=2), no recompute"},
+        "workspace_GB": record_gb,
+        "fwd_bwd_recompute": {"ms_per_frame": ms_recompute, "workspace_GB": recompute_gb,
+                              "note": "dual checkpoints only (keep_checkpoints=1); the backward recomputes each "
+                                      "half-step, recording its tapes"},
         "forward_only": {"ms_per_frame": fwd_ms, "label_node_updates_per_s": updates / (fwd_ms * 1e-3)},
         "grad_finite": grad_finite,
-        # the step's dominant kernel (about 30% of the step): the adjoint of the horizontal half-step
-        "roofline": roof("adjoint_h", "adjoint_h_traffic.json",
-                         "adjoint of the horizontal half-step (R0 + 3 update passes in reverse, FP16 cost)"),
+        # the step's dominant kernel: the forward's horizontal half-step recording its tapes
+        "roofline": roof("record_h", "record_h_traffic.json",
+                         "horizontal half-step recording the selection tapes (R0 + 3 update passes, FP16 cost)"),
+        "roofline_adjoint": roof("adjoint_h", "adjoint_h_traffic.json",
+                                 "adjoint of the horizontal half-step (R0 + 3 update passes in reverse, from the "
+                                 "tapes)"),
         "roofline_forward_sweep": roof("sweep_h", "sweep_h_traffic.json",
                                        "horizontal half-step chain sweep (R0 + 3 update passes, FP16 cost)"),
         "stage_ms": {
@@ -431,8 +447,8 @@ def main():
             "final_per_launch": prof["sweep_final"][1] / max(prof["sweep_final"][0], 1),
             "adjoint_h_per_launch": prof["adjoint_h"][1] / max(prof["adjoint_h"][0], 1),
             "adjoint_v_per_launch": prof["adjoint_v"][1] / max(prof["adjoint_v"][0], 1),
-            "recompute_h_per_launch": prof["recompute_h"][1] / max(prof["recompute_h"][0], 1),
-            "recompute_v_per_launch": prof["recompute_v"][1] / max(prof["recompute_v"][0], 1),
+            "record_h_per_launch": prof["record_h"][1] / max(prof["record_h"][0], 1),
+            "record_v_per_launch": prof["record_v"][1] / max(prof["record_v"][0], 1),
         },
         "fp16_storage": {"energy_fp16_labels": e16, "energy_fp32_labels": e32, "rel_diff": (e16 - e32) / e32},
         "lower_bound": float(bounds[0]),

@@ -296,8 +296,9 @@ typedef enum {
     DM_PROF_ADJOINT_H = 9,        /* adjoint of a horizontal half-step             */
     DM_PROF_ADJOINT_V = 10,       /* adjoint of a vertical half-step               */
     DM_PROF_ADJOINT_FINAL = 11,   /* adjoint of the final row pass                 */
-    DM_PROF_RECOMPUTE_H = 12,     /* backward's recompute of a horizontal half-step */
-    DM_PROF_RECOMPUTE_V = 13,     /* backward's recompute of a vertical half-step  */
+    DM_PROF_RECORD_H = 12,        /* record-mode horizontal half-step: the forward's with
+                                     keep_checkpoints = 2, or the backward's recompute   */
+    DM_PROF_RECORD_V = 13,        /* record-mode vertical half-step (likewise)          */
     DM_PROF_KINDS = 16
 } dm_prof_kind;
 

@@ -19,7 +19,7 @@ DM_MINORANT_NAIVE = 1
 
 PROF_KINDS = {"sweep_h": 0, "sweep_v": 1, "sweep_final": 2, "sweep_opt": 3, "bounds": 4, "cost_volume": 5,
               "refine_linearize": 6, "refine_iter": 7, "other": 8, "adjoint_h": 9, "adjoint_v": 10,
-              "adjoint_final": 11, "recompute_h": 12, "recompute_v": 13}
+              "adjoint_final": 11, "record_h": 12, "record_v": 13}
 
 STATUS_NAMES = {
     0: "DM_OK", -1: "DM_ERR_NULL", -2: "DM_ERR_SHAPE", -3: "DM_ERR_PARAM", -4: "DM_ERR_DTYPE",

@@ -277,6 +277,7 @@ hipError_t launch_sweep_prof(Tile t, const SweepArgs& a, dm_dtype dt, hipStream_
     int kind = DM_PROF_SWEEP_H;
     if (a.mode == kModeFinal) kind = DM_PROF_SWEEP_FINAL;
     else if (a.mode == kModeOptimum) kind = DM_PROF_SWEEP_OPT;
+    else if (a.mode & kRecordFlag) kind = a.theta != nullptr ? DM_PROF_RECORD_H : DM_PROF_RECORD_V;
     else if (a.theta == nullptr) kind = DM_PROF_SWEEP_V;
     ProfScope ps(kind, profiler_on() ? sweep_bytes(a, dt) : 0.0, st);
     return launch_sweep(t, a, dt, st);
@@ -828,7 +829,7 @@ extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad
             a.mode = a.mode | kRecordFlag;
             a.lam_in = ck;
             a.lam = const_cast<float*>(ck);
-            ProfScope ps(h ? DM_PROF_RECOMPUTE_H : DM_PROF_RECOMPUTE_V, profiler_on() ? sweep_bytes(a, cost_dtype) : 0.0,
+            ProfScope ps(h ? DM_PROF_RECORD_H : DM_PROF_RECORD_V, profiler_on() ? sweep_bytes(a, cost_dtype) : 0.0,
                          stream);
             DM_HIP_TRY(launch_sweep(h ? tile : tile_v, a, cost_dtype, stream), "half-step recompute");
         }

@@ -153,6 +153,7 @@ struct AdjWalker {
     bool ok;
     bool lv[LPL];
     int dt_steps;
+    bool direct;  // the forward used the direct window form (T <= 3)
     float g_lb_f = 0.0f;
     // LDS (typed in the local address space: a generic pointer would make every access a
     // flat instruction, which waits on the vector-memory counter too)
@@ -183,6 +184,7 @@ struct AdjWalker {
         for (int i = 0; i < LPL; ++i) lv[i] = FULL ? true : (ok && sub * LPL + i < K);
         const int need = (a.T - 1 + LPL - 1) / LPL;
         dt_steps = need < G - 1 ? need : G - 1;
+        direct = a.T <= 3 && a.T - 1 <= LPL;
         const unsigned long long ts = (unsigned long long)(G * kTW * 4);
         tp0 = ok ? (unsigned)(cpx * ts + (unsigned long long)(sub * kTW * 4)) : kOOB;
         tp_step = ok ? (unsigned)((unsigned long long)a.node_px * ts) : 0u;
@@ -316,7 +318,7 @@ struct AdjWalker {
                         src = b + bd;
                         dist = (float)(bd < 0 ? -bd : bd);
                     }
-                    wpart += cb[i] * dist;
+                    wpart = __builtin_fmaf(cb[i], dist, wpart);
                     if (src < 0) cpart += cb[i];
                     apart += cb[i];
                 }
@@ -527,7 +529,61 @@ struct AdjWalker {
         zl = cpart - apart;
     }
 
-    template <bool FWD, int KIND, bool IS_FIRST, bool DT1>
+    // Message adjoint from a direct window tape (codes 0-5, distance in bits 3-4): the
+    // routing, the order of additions and the edge and minimum terms of the window search
+    // of msg_adjoint<2>, so the two agree bit for bit (up to the sign of zeros).  Each
+    // source label sums, in ascending target order, what the left lane sends (its
+    // targets before this lane), its own targets, then the right lane's targets one by
+    // one.
+    __device__ __forceinline__ void msg_adjoint_direct(const Node& nd, const float (&cb)[LPL], float (&vbar)[LPL],
+                                                       float& wl, float& zl) {
+        float t[5][LPL];  // t[k][i]: the adjoint of target i if its message took class k
+        float wpart = 0.0f, cpart = 0.0f, apart = 0.0f;
+#pragma unroll
+        for (int i = 0; i < LPL; ++i) {
+            const unsigned x = nd.tw[i >> 2] >> (8 * (i & 3));
+            const unsigned code = x & 7u;
+            const float c = (FULL || lv[i]) ? cb[i] : 0.0f;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) t[k][i] = code == (unsigned)k ? c : 0.0f;
+            wpart = __builtin_fmaf(c, (float)((x >> 3) & 3u), wpart);
+            cpart += code == 5u ? c : 0.0f;
+            apart += c;
+        }
+        // class of a target at offset d from its source: +2 -> 4, +1 -> 2, 0 -> 0, -1 -> 1, -2 -> 3
+        constexpr int cls[5] = {3, 1, 0, 2, 4};  // indexed by d + 2, d = source - target
+        float toR0, toR1 = 0.0f;
+        if constexpr (LPL >= 2) {
+            toR0 = t[4][LPL - 2] + t[2][LPL - 1];
+            toR1 = t[4][LPL - 1];
+        } else {
+            toR0 = t[2][0];
+        }
+        const float fL0 = from_left(toR0, 0.0f);
+        const float fL1 = LPL >= 2 ? from_left(toR1, 0.0f) : 0.0f;
+        const float rA = from_right(t[1][0], 0.0f);
+        const float rB = LPL >= 2 ? from_right(t[3][1], 0.0f) : 0.0f;
+        const float rC = LPL >= 2 ? from_right(t[3][0], 0.0f) : 0.0f;
+#pragma unroll
+        for (int j = 0; j < LPL; ++j) {
+            float acc = j == 0 ? fL0 : (j == 1 ? fL1 : 0.0f);
+#pragma unroll
+            for (int b = (j - 2 > 0 ? j - 2 : 0); b <= (j + 2 < LPL - 1 ? j + 2 : LPL - 1); ++b)
+                acc += t[cls[j - b + 2]][b];
+            if (j == LPL - 1) {
+                acc += rA;
+                if constexpr (LPL >= 2) acc += rB;
+            } else if (j == LPL - 2) {
+                acc += rC;
+            }
+            vbar[j] = acc;
+        }
+        wl = wpart;
+        zl = cpart - apart;
+    }
+
+    // MF: the forward's message form - 1 scans reaching one lane, 2 direct window.
+    template <bool FWD, int KIND, bool IS_FIRST, int MF>
     __device__ __forceinline__ void pass_tape(float gamma) {
         float cbar[LPL];
 #pragma unroll
@@ -545,26 +601,26 @@ struct AdjWalker {
         for (; t0 + PF <= n; t0 += PF) {
 #pragma unroll
             for (int q = 0; q < PF; ++q) {
-                step_tape<FWD, KIND, IS_FIRST, DT1>(ring[q], t0 + q, cbar, gamma, next_label, sc);
+                step_tape<FWD, KIND, IS_FIRST, MF>(ring[q], t0 + q, cbar, gamma, next_label, sc);
                 load_tape<FWD, KIND, IS_FIRST>(ring[q], lc);
             }
         }
 #pragma unroll
         for (int q = 0; q < PF; ++q)
-            if (t0 + q < n) step_tape<FWD, KIND, IS_FIRST, DT1>(ring[q], t0 + q, cbar, gamma, next_label, sc);
+            if (t0 + q < n) step_tape<FWD, KIND, IS_FIRST, MF>(ring[q], t0 + q, cbar, gamma, next_label, sc);
     }
 
     template <bool FWD, int KIND, bool IS_FIRST>
     __device__ __forceinline__ void run_pass_tape(float gamma) {
-        if (dt_steps == 1)
-            pass_tape<FWD, KIND, IS_FIRST, true>(gamma);
+        if (direct)
+            pass_tape<FWD, KIND, IS_FIRST, 2>(gamma);
         else
-            pass_tape<FWD, KIND, IS_FIRST, false>(gamma);
+            pass_tape<FWD, KIND, IS_FIRST, 1>(gamma);
     }
 
     // Adjoint of the forward step at the node visited t-th, from the tape (the same
     // formulas as step()).
-    template <bool FWD, int KIND, bool IS_FIRST, bool DT1>
+    template <bool FWD, int KIND, bool IS_FIRST, int MF>
     __device__ __forceinline__ void step_tape(const Node& nd, int t, float (&cbar)[LPL], float gamma, int& next_label,
                                               Cursor& sc) {
         const bool out = t != 0;
@@ -590,7 +646,10 @@ struct AdjWalker {
         // the last node of a forward pass sends no message: its selection bits are 0 and
         // its message adjoint cb is 0, so the message adjoint below adds nothing there
         float vbar[LPL], wl = 0.0f, zl = 0.0f;
-        msg_adjoint_tape<DT1>(nd, cb, vbar, wl, zl);
+        if constexpr (MF == 2)
+            msg_adjoint_direct(nd, cb, vbar, wl, zl);
+        else
+            msg_adjoint_tape<true>(nd, cb, vbar, wl, zl);
         if constexpr (KIND == kAdjR0) {
             group_sum2<G>(wl, zl);
             float rt[LPL], outv[LPL];
@@ -708,11 +767,11 @@ struct AdjWalker {
             if (t0 + q < n) step<FWD, KIND, IS_FIRST, DTM>(ring[q], t0 + q, cbar, gamma, next_label, sc);
     }
 
+    // The recomputing form: scans for a forward that used them with one lane of reach,
+    // else the window search (the direct window forward's rule, and the general reach).
     template <bool FWD, int KIND, bool IS_FIRST>
     __device__ __forceinline__ void run_pass(float gamma) {
-        if (dt_steps == 0)
-            pass<FWD, KIND, IS_FIRST, 0>(gamma);
-        else if (dt_steps == 1)
+        if (!direct && dt_steps == 1)
             pass<FWD, KIND, IS_FIRST, 1>(gamma);
         else
             pass<FWD, KIND, IS_FIRST, 2>(gamma);

@@ -82,10 +82,13 @@ struct SweepArgs {
 };
 
 // Selection tape: what the adjoint of a pass needs from the forward, one byte per label
-// and node: which operand each min of the message's distance transform took, and the
-// node's two argmins.  Per lane and node the bytes of its LPL labels are packed into
-// kTapeWords(LPL) dwords (label i in byte i % 4 of word i / 4); a node's lanes are
-// contiguous, so the tape of a pass is [pixel][lane][word].
+// and node: which candidate the label's message took, and the node's two argmins.  Per
+// lane and node the bytes of its LPL labels are packed into kTapeWords(LPL) dwords
+// (label i in byte i % 4 of word i / 4); a node's lanes are contiguous, so the tape of a
+// pass is [pixel][lane][word].  Messages in the direct window form (T <= 3) store in
+// bits 0-2 the candidate code (0: the label itself, 1: d = -1, 2: +1, 3: -2, 4: +2,
+// 5: the cap) and in bits 3-4 its distance (T for the cap); messages from the scans
+// store the bits below.  Bits K and A are common to both.
 enum TapeBit : unsigned {
     kTapeFI = 1,    // forward in-lane scan: took the left neighbour + w (not v itself)
     kTapeBI = 2,    // backward in-lane scan: took the right neighbour + w
@@ -266,6 +269,8 @@ struct Walker {
     bool lv[LPL];     // label exists (and the chain exists)
     int dt_steps;     // lanes the distance transform must reach across
     float dl, dr;     // distance-transform lane shifts; lanes without a source keep kBig
+    float dl2, dr2;   // direct window: the second label across the lane edge
+    bool direct;      // direct window form of the message (T <= 3, reach within one lane)
     // tape mode: store descriptor of the current pass's tape, this lane's tape offset at
     // node 0 and its per-node step
     static constexpr int kTW = kTapeWords(LPL);
@@ -302,6 +307,7 @@ struct Walker {
         for (int i = 0; i < LPL; ++i) lv[i] = FULL ? true : (ok && sub * LPL + i < K);
         const int need = (args.T - 1 + LPL - 1) / LPL;
         dt_steps = need < G - 1 ? need : G - 1;
+        direct = args.T <= 3 && args.T - 1 <= LPL;
         const unsigned long long ts = (unsigned long long)(G * kTW * 4);
         tp0 = ok ? (unsigned)(cpx * ts + (unsigned long long)(sub * kTW * 4)) : kOOB;
         tp_step = ok ? (unsigned)((unsigned long long)args.node_px * ts) : 0u;
@@ -351,33 +357,85 @@ struct Walker {
     }
 
     // Value arriving from the left / right neighbour lane of the group (kBig at the
-    // group's first / last lane).
-    __device__ __forceinline__ float from_left(float x) {
+    // group's first / last lane).  For 64- and 16-lane groups the shifted-in value is
+    // kept in a register (`keep`) whose edge lanes are never written.
+    __device__ __forceinline__ float from_left_r(float x, float& keep) {
         if constexpr (G == 64) {
-            dl = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, dl), __builtin_bit_cast(int, x),
-                                                                       kWaveShr1, 0xF, 0xF, false));
-            return dl;
+            keep = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, keep),
+                                                                         __builtin_bit_cast(int, x), kWaveShr1, 0xF,
+                                                                         0xF, false));
+            return keep;
         } else if constexpr (G == 16) {
-            dl = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, dl), __builtin_bit_cast(int, x),
-                                                                       kRowShr1, 0xF, 0xF, false));
-            return dl;
+            keep = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, keep),
+                                                                         __builtin_bit_cast(int, x), kRowShr1, 0xF,
+                                                                         0xF, false));
+            return keep;
         } else {
             const float c = dpp_fill<kWaveShr1>(x, kBig);
             return sub == 0 ? kBig : c;
         }
     }
-    __device__ __forceinline__ float from_right(float x) {
+    __device__ __forceinline__ float from_right_r(float x, float& keep) {
         if constexpr (G == 64) {
-            dr = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, dr), __builtin_bit_cast(int, x),
-                                                                       kWaveShl1, 0xF, 0xF, false));
-            return dr;
+            keep = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, keep),
+                                                                         __builtin_bit_cast(int, x), kWaveShl1, 0xF,
+                                                                         0xF, false));
+            return keep;
         } else if constexpr (G == 16) {
-            dr = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, dr), __builtin_bit_cast(int, x),
-                                                                       kRowShl1, 0xF, 0xF, false));
-            return dr;
+            keep = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, keep),
+                                                                         __builtin_bit_cast(int, x), kRowShl1, 0xF,
+                                                                         0xF, false));
+            return keep;
         } else {
             const float c = dpp_fill<kWaveShl1>(x, kBig);
             return sub == G - 1 ? kBig : c;
+        }
+    }
+    __device__ __forceinline__ float from_left(float x) { return from_left_r(x, dl); }
+    __device__ __forceinline__ float from_right(float x) { return from_right_r(x, dr); }
+
+    // Direct window form of the message for T <= 3 (window |d| < T reaching at most one
+    // lane across): each label takes the minimum of the window candidates v(a) + w|a-b|,
+    // rounded once each, and of the cap vmin + wT.  TP: also records in tape byte bits
+    // 0-2 which candidate the minimum took - the first in the order d = 0, -1, +1, -2,
+    // +2 that attains it, the cap only when strictly lower (codes 0-4, 5 for the cap) -
+    // and in bits 3-4 its distance (T for the cap).
+    template <bool TP>
+    __device__ __forceinline__ void message_direct(const float (&v)[LPL], float vmin, float wt, float (&out)[LPL],
+                                                   uint32_t (&tw)[kTW]) {
+        const float w1 = T > 1 ? wt : kBig;          // disabled candidates sit above every window value
+        const float w2 = T > 2 ? wt + wt : kBig;     // 2w is exact: v + 2w rounds like fma(w, 2, v)
+        const float cap = __builtin_fmaf(wt, Tf, vmin);
+        const float l1 = from_left_r(v[LPL - 1], dl);
+        const float r1 = from_right_r(v[0], dr);
+        float l2 = kBig, r2 = kBig;
+        if constexpr (LPL >= 2) {
+            l2 = from_left_r(v[LPL - 2], dl2);
+            r2 = from_right_r(v[1], dr2);
+        }
+        auto val = [&](int a) -> float {
+            return a < 0 ? (a == -1 ? l1 : l2) : (a >= LPL ? (a == LPL ? r1 : r2) : v[a]);
+        };
+        const unsigned cap_code = 5u | ((unsigned)T << 3);
+#pragma unroll
+        for (int j = 0; j < kTW; ++j) tw[j] = 0u;
+#pragma unroll
+        for (int i = 0; i < LPL; ++i) {
+            const bool valid = FULL || lv[i];
+            const float s0 = v[i];
+            const float cm1 = val(i - 1) + w1, cp1 = val(i + 1) + w1;
+            const float cm2 = val(i - 2) + w2, cp2 = val(i + 2) + w2;
+            const float e = fminf(fminf(fminf(s0, cm1), cp1), fminf(cm2, cp2));
+            out[i] = valid ? fminf(e, cap) - vmin : 0.0f;
+            if constexpr (TP) {
+                unsigned x = 4u | (2u << 3);
+                x = cm2 == e ? (3u | (2u << 3)) : x;
+                x = cp1 == e ? (2u | (1u << 3)) : x;
+                x = cm1 == e ? (1u | (1u << 3)) : x;
+                x = s0 == e ? 0u : x;
+                x = cap < e ? cap_code : x;
+                tw[i >> 2] |= (valid ? x : 0u) << (8 * (i & 3));
+            }
         }
     }
 
@@ -556,7 +614,9 @@ struct Walker {
     // One directional pass.  KIND: 0 = backward message pass (R0), 1 = iterative update,
     // 2 = naive update, 3 = final min-marginals.  Adds the normalisation constants of a
     // message pass (= chain optimum) to `opt`.
-    template <bool FWD, int KIND, bool DT1, bool TP>
+    // MF: message form - 0 scans reaching several lanes, 1 scans reaching one lane (DT1),
+    // 2 direct window.
+    template <bool FWD, int KIND, int MF, bool TP>
     __device__ __forceinline__ void pass(float gamma, bool store_msg, double& opt) {
         constexpr bool WANT_REV = KIND != 0;
         float carry[LPL];
@@ -564,6 +624,8 @@ struct Walker {
         for (int i = 0; i < LPL; ++i) carry[i] = 0.0f;
         dl = kBig;
         dr = kBig;
+        dl2 = kBig;
+        dr2 = kBig;
         const __amdgpu_buffer_rsrc_t msg_st = store_msg ? r_msg_st : make_rsrc(nullptr, 0u);
         Cursor lc = cursor_at(FWD);
         unsigned sf = lc.f;                                           // store cursor (dual, messages)
@@ -583,7 +645,7 @@ struct Walker {
         for (; t0 + PF < n; t0 += PF) {
 #pragma unroll
             for (int q = 0; q < PF; ++q) {
-                step<FWD, KIND, false, DT1, TP>(ring[q], true, carry, gamma, msg_st, opt, sf, sl, stp);
+                step<FWD, KIND, false, MF, TP>(ring[q], true, carry, gamma, msg_st, opt, sf, sl, stp);
                 load<FWD, WANT_REV>(ring[q], lc);
             }
         }
@@ -592,7 +654,7 @@ struct Walker {
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
             const int t = t0 + q;
-            if (t < n) step<FWD, KIND, true, DT1, TP>(ring[q], t < n - 1, carry, gamma, msg_st, opt, sf, sl, stp);
+            if (t < n) step<FWD, KIND, true, MF, TP>(ring[q], t < n - 1, carry, gamma, msg_st, opt, sf, sl, stp);
         }
     }
 
@@ -600,13 +662,19 @@ struct Walker {
     // also write the pass's selection tape (the host enables it only for dt_steps <= 1).
     template <bool FWD, int KIND, bool TP = false>
     __device__ __forceinline__ void run_pass(float gamma, bool store_msg, double& opt) {
-        if (dt_steps == 1)
-            pass<FWD, KIND, true, TP>(gamma, store_msg, opt);
-        else
-            pass<FWD, KIND, false, TP>(gamma, store_msg, opt);
+        if (direct) {
+            pass<FWD, KIND, 2, TP>(gamma, store_msg, opt);
+        } else if constexpr (TP) {
+            pass<FWD, KIND, 1, TP>(gamma, store_msg, opt);  // the host enables tapes for dt_steps <= 1 only
+        } else {
+            if (dt_steps == 1)
+                pass<FWD, KIND, 1, TP>(gamma, store_msg, opt);
+            else
+                pass<FWD, KIND, 0, TP>(gamma, store_msg, opt);
+        }
     }
 
-    template <bool FWD, int KIND, bool TAIL, bool DT1, bool TP>
+    template <bool FWD, int KIND, bool TAIL, int MF, bool TP>
     __device__ __forceinline__ void step(const Node& nd, bool has_next, float (&carry)[LPL], float gamma,
                                          __amdgpu_buffer_rsrc_t msg_st, double& opt, unsigned& sf, unsigned& sl,
                                          unsigned& stp) {
@@ -688,14 +756,22 @@ struct Walker {
             if constexpr (KIND == 0) vmin = group_min<G>(lane_min(v));
             if constexpr (KIND == 0) opt += (double)vmin;
             if (has_next) {
-                if constexpr (TP) {
+                if constexpr (MF == 2) {
                     uint32_t tm[kTW];
-                    message_tp<DT1>(v, vmin, nd.w, carry, tm);
+                    message_direct<TP>(v, vmin, nd.w, carry, tm);
+                    if constexpr (TP) {
+#pragma unroll
+                        for (int j = 0; j < kTW; ++j) tw[j] |= tm[j];
+                        tape_argmin<G, LPL, FULL, kTW>(v, vmin, lv, sub, kTapeA, tw);
+                    }
+                } else if constexpr (TP) {
+                    uint32_t tm[kTW];
+                    message_tp<MF == 1>(v, vmin, nd.w, carry, tm);
 #pragma unroll
                     for (int j = 0; j < kTW; ++j) tw[j] |= tm[j];
                     tape_argmin<G, LPL, FULL, kTW>(v, vmin, lv, sub, kTapeA, tw);
                 } else {
-                    message<DT1>(v, vmin, nd.w, carry);
+                    message<MF == 1>(v, vmin, nd.w, carry);
                 }
                 // slot of edge (j, j+1) / (j-1, j); a pass that keeps no messages stores
                 // through an empty descriptor (dropped) rather than branching per node
