@@ -121,6 +121,7 @@ __device__ __forceinline__ int group_argmin_eq(const float (&x)[LPL], float mn, 
 // Adjoint pass kinds: update pass of the iterative minorant, naive update pass, final
 // min-marginal pass, backward message pass (R0).
 enum AdjKind : int { kAdjIter = 1, kAdjNaive = 2, kAdjFinal = 3, kAdjR0 = 0 };
+enum OutMode : int { kOutRuntime = 0, kOutYes = 1, kOutNo = 2 };
 
 template <int G, int LPL, int PF, typename TT, bool FULL, bool HAS_THETA>
 struct AdjWalker {
@@ -546,9 +547,12 @@ struct AdjWalker {
             const float c = (FULL || lv[i]) ? cb[i] : 0.0f;
 #pragma unroll
             for (int k = 0; k < 5; ++k) t[k][i] = code == (unsigned)k ? c : 0.0f;
-            wpart = __builtin_fmaf(c, (float)((x >> 3) & 3u), wpart);
-            cpart += code == 5u ? c : 0.0f;
-            apart += c;
+            const float dist = (float)((x >> 3) & 3u);
+            const float cc = code == 5u ? c : 0.0f;
+            // sums start from their first term (equal to 0 + term up to the sign of zero)
+            wpart = i == 0 ? c * dist : __builtin_fmaf(c, dist, wpart);
+            cpart = i == 0 ? cc : cpart + cc;
+            apart = i == 0 ? c : apart + c;
         }
         // class of a target at offset d from its source: +2 -> 4, +1 -> 2, 0 -> 0, -1 -> 1, -2 -> 3
         constexpr int cls[5] = {3, 1, 0, 2, 4};  // indexed by d + 2, d = source - target
@@ -566,9 +570,11 @@ struct AdjWalker {
         const float rC = LPL >= 2 ? from_right(t[3][0], 0.0f) : 0.0f;
 #pragma unroll
         for (int j = 0; j < LPL; ++j) {
-            float acc = j == 0 ? fL0 : (j == 1 ? fL1 : 0.0f);
+            const int b0 = j - 2 > 0 ? j - 2 : 0;
+            float acc = j == 0 ? fL0 + t[cls[j - b0 + 2]][b0]
+                               : (j == 1 ? fL1 + t[cls[j - b0 + 2]][b0] : t[cls[j - b0 + 2]][b0]);
 #pragma unroll
-            for (int b = (j - 2 > 0 ? j - 2 : 0); b <= (j + 2 < LPL - 1 ? j + 2 : LPL - 1); ++b)
+            for (int b = b0 + 1; b <= (j + 2 < LPL - 1 ? j + 2 : LPL - 1); ++b)
                 acc += t[cls[j - b + 2]][b];
             if (j == LPL - 1) {
                 acc += rA;
@@ -598,16 +604,29 @@ struct AdjWalker {
             __builtin_amdgcn_sched_barrier(0);
         }
         int t0 = 0;
-        for (; t0 + PF <= n; t0 += PF) {
+        if (n >= PF) {
+            // first block: the first visited node (the forward pass's last) sends no
+            // message; the steady loop's nodes all do
 #pragma unroll
             for (int q = 0; q < PF; ++q) {
-                step_tape<FWD, KIND, IS_FIRST, MF>(ring[q], t0 + q, cbar, gamma, next_label, sc);
+                if (q == 0)
+                    step_tape<FWD, KIND, IS_FIRST, MF, kOutNo>(ring[q], q, cbar, gamma, next_label, sc);
+                else
+                    step_tape<FWD, KIND, IS_FIRST, MF, kOutYes>(ring[q], q, cbar, gamma, next_label, sc);
                 load_tape<FWD, KIND, IS_FIRST>(ring[q], lc);
+            }
+            for (t0 = PF; t0 + PF <= n; t0 += PF) {
+#pragma unroll
+                for (int q = 0; q < PF; ++q) {
+                    step_tape<FWD, KIND, IS_FIRST, MF, kOutYes>(ring[q], t0 + q, cbar, gamma, next_label, sc);
+                    load_tape<FWD, KIND, IS_FIRST>(ring[q], lc);
+                }
             }
         }
 #pragma unroll
         for (int q = 0; q < PF; ++q)
-            if (t0 + q < n) step_tape<FWD, KIND, IS_FIRST, MF>(ring[q], t0 + q, cbar, gamma, next_label, sc);
+            if (t0 + q < n)
+                step_tape<FWD, KIND, IS_FIRST, MF, kOutRuntime>(ring[q], t0 + q, cbar, gamma, next_label, sc);
     }
 
     template <bool FWD, int KIND, bool IS_FIRST>
@@ -620,10 +639,12 @@ struct AdjWalker {
 
     // Adjoint of the forward step at the node visited t-th, from the tape (the same
     // formulas as step()).
-    template <bool FWD, int KIND, bool IS_FIRST, int MF>
+    // OUTM: whether the node sends a message in the forward pass (kOutYes / kOutNo), or
+    // decided at run time (t != 0).
+    template <bool FWD, int KIND, bool IS_FIRST, int MF, int OUTM>
     __device__ __forceinline__ void step_tape(const Node& nd, int t, float (&cbar)[LPL], float gamma, int& next_label,
                                               Cursor& sc) {
-        const bool out = t != 0;
+        const bool out = OUTM == kOutYes ? true : (OUTM == kOutNo ? false : t != 0);
         const unsigned rs = FWD ? sc.f : sc.f - f_step;
         unsigned os[LPL];
         float ab[LPL], cb[LPL];
@@ -731,7 +752,7 @@ struct AdjWalker {
             label_offsets<4>(sc.f, os);
             store_f32<LPL, FULL>(r_abar, sc.f, os, rbar);
         }
-        if (ok && sub == 0 && out && wl != 0.0f) add_edge_grad(sc.w, wl);
+        if (ok && sub == 0 && out) add_edge_grad(sc.w, wl);
         advance<FWD>(sc);
     }
 
