@@ -1033,18 +1033,18 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
     adjoint_pass<TAPE, false, kAdjR0, false>(wk, a.tape[0], tb, 0.0f);
 }
 
-constexpr int kAdjPF = 4;
+constexpr int kAdjPF = 4;      // recomputing form: a node's ring slot holds cost, dual and two messages
+constexpr int kAdjTapePF = 8;  // tape form: a slot holds the tape word and two adjoints only
 
 template <int G, int LPL, typename TT, bool HAS_THETA, bool TAPE>
 hipError_t launch_adjoint_tt(const AdjArgs& a, hipStream_t st) {
     constexpr int CPW = 64 / G;
     const unsigned blocks = (unsigned)((a.n_chains + CPW - 1) / CPW);
+    constexpr int PF = TAPE ? kAdjTapePF : kAdjPF;
     if (a.K == G * LPL)
-        hipLaunchKernelGGL((adjoint_kernel<G, LPL, kAdjPF, TT, true, HAS_THETA, TAPE>), dim3(blocks), dim3(64), 0, st,
-                           a);
+        hipLaunchKernelGGL((adjoint_kernel<G, LPL, PF, TT, true, HAS_THETA, TAPE>), dim3(blocks), dim3(64), 0, st, a);
     else
-        hipLaunchKernelGGL((adjoint_kernel<G, LPL, kAdjPF, TT, false, HAS_THETA, TAPE>), dim3(blocks), dim3(64), 0, st,
-                           a);
+        hipLaunchKernelGGL((adjoint_kernel<G, LPL, PF, TT, false, HAS_THETA, TAPE>), dim3(blocks), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

@@ -265,6 +265,9 @@ struct Walker {
     unsigned th0, f0, w0, lab0, th_step, f_step, w_step, lab_step;
     int sub, n, K, T;
     float sign, inv_n, Tf;
+    // 1.0 that the compiler cannot see as a constant: cost - dual as fma(cost, one, -dual)
+    // (the same rounding as the subtraction) takes one mixed-precision FMA for FP16 cost
+    float one;
     bool ok;          // this group's chain exists
     bool lv[LPL];     // label exists (and the chain exists)
     int dt_steps;     // lanes the distance transform must reach across
@@ -282,6 +285,7 @@ struct Walker {
         : sub(sub_), n(args.n), K(args.K), T(args.T), sign(args.sign), inv_n(args.inv_n) {
         ok = chain < args.n_chains;
         Tf = (float)args.T;
+        one = args.sign * args.sign;
         const unsigned long long cpx = (unsigned long long)(ok ? chain : 0) * (unsigned long long)args.chain_px;
         const unsigned long long e0 = cpx * (unsigned long long)args.K + (unsigned long long)(sub * LPL);
         const unsigned long long nk = (unsigned long long)args.node_px * (unsigned long long)args.K;
@@ -687,7 +691,7 @@ struct Walker {
 #pragma unroll
         for (int i = 0; i < LPL; ++i) {
             lamv[i] = nd.lam.get(i);
-            const float x = HAS_THETA ? nd.th.get(i) - lamv[i] : lamv[i];
+            const float x = HAS_THETA ? __builtin_fmaf(nd.th.get(i), one, -lamv[i]) : lamv[i];
             r[i] = (FULL || lv[i]) ? x : kBig;
         }
         float v[LPL];
