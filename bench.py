@@ -147,8 +147,8 @@ def batched_extra(torch, ops, dev, n=64, seed=4000, n_iters=20, T=3, reps=3):
 
 def diff_extra(torch, ops, dev, n=8, W=960, H=320, K=96, n_iters=20, T=3, warps=5, iters=10, seed=5000, reps=2):
     """Differentiation workload: 8 frames 960x320, K=96, FP16 cost; forward (Dual_MM 20 its
-    with dual checkpoints + refinement 5 x 10 steps) and backward (dL/dcost, dL/dw) per frame,
-    against the plain FP32 forward of the same frames."""
+    keeping the selection tapes + refinement 5 x 10 steps) and backward (dL/dcost, dL/dw) per
+    frame, against the plain FP32 forward of the same frames."""
     import ctypes
     import synth
     import paper_1601_06274_amd as P
@@ -164,7 +164,7 @@ def diff_extra(torch, ops, dev, n=8, W=960, H=320, K=96, n_iters=20, T=3, warps=
     rkw = dict(C=3.0, n_warps=warps, n_iters=iters)
     lib = P.lib()
     shp = P._lib.DmShape(W, H, K)
-    dp = ops.discrete_params(keep_checkpoints=True, **dkw)
+    dp = ops.discrete_params(keep_checkpoints=2, **dkw)
     ws_d = torch.empty(lib.dm_solve_discrete_workspace(shp, P._lib.DM_F16, ctypes.byref(dp)), dtype=torch.uint8,
                        device=dev)
     ws_db = torch.empty(lib.dm_solve_discrete_backward_workspace(shp, ctypes.byref(dp)), dtype=torch.uint8, device=dev)
@@ -188,12 +188,13 @@ def diff_extra(torch, ops, dev, n=8, W=960, H=320, K=96, n_iters=20, T=3, warps=
         grad_lpw.clear()
         for c16, _, wh, wv in frames:
             ops.solve_discrete(c16, wh, wv, dual=dual, workspace=ws_d, labels=lab, minmarg=mm, want_bounds=True,
-                               keep_checkpoints=True, **dkw)
+                               keep_checkpoints=2, **dkw)
             ops.refine_continuous(c16, lab, wh, wv, workspace=ws_r, u_out=u, keep_tape=True, **rkw)
             ops.refine_continuous_backward(G_u, c16, wh, wv, ws_r, grad_cost=gc, grad_w_h=gwh, grad_w_v=gwv,
                                            accumulate=False, workspace=ws_rb, **rkw)
             ops.solve_discrete_backward(c16, wh, wv, dual, ws_d, grad_minmarg=G_m, grad_lb=1.0, grad_cost=gc,
-                                        grad_w_h=gwh, grad_w_v=gwv, accumulate=True, workspace=ws_db, **dkw)
+                                        grad_w_h=gwh, grad_w_v=gwv, accumulate=True, workspace=ws_db,
+                                        keep_checkpoints=2, **dkw)
             # dL/dlambda_pw: the weights are lambda_pw * exp(...), so sum(dL/dw * w) / lambda_pw
             grad_lpw.append((gwh * wh).sum() + (gwv * wv).sum())
 
@@ -210,7 +211,7 @@ def diff_extra(torch, ops, dev, n=8, W=960, H=320, K=96, n_iters=20, T=3, warps=
     ms_fb = _timed(fwd_bwd, reps, torch)
     ms_32 = _timed(plain32, reps, torch)
     finite = bool(all(torch.isfinite(g).item() for g in grad_lpw))
-    return {"workload": f"{n} frames {W}x{H}, K={K}, FP16 cost; Dual_MM {n_iters} its (dual checkpoints) + "
+    return {"workload": f"{n} frames {W}x{H}, K={K}, FP16 cost; Dual_MM {n_iters} its (tapes kept by the forward) + "
                         f"refinement {warps}x{iters}; backward dL/dcost, dL/dw (and dL/dlambda_pw)",
             "fwd_bwd_fp16_ms_per_batch": ms_fb, "fwd_bwd_fp16_ms_per_frame": ms_fb / n,
             "plain_fp32_forward_ms_per_batch": ms_32, "ratio_fwd_bwd_to_plain_fwd": ms_fb / ms_32,
@@ -221,7 +222,7 @@ def diff_extra(torch, ops, dev, n=8, W=960, H=320, K=96, n_iters=20, T=3, warps=
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); there is no multi-GPU path.",
               file=sys.stderr)
         return 2
     import torch

@@ -41,7 +41,7 @@ typedef enum {
     DM_ERR_PARAM = -3,       /* a parameter value is out of range                */
     DM_ERR_DTYPE = -4,       /* unknown dm_dtype                                 */
     DM_ERR_WORKSPACE = -5,   /* workspace NULL or smaller than the size query    */
-    DM_ERR_UNSUPPORTED = -6, /* valid but not supported by this build            */
+    DM_ERR_UNSUPPORTED = -6, /* valid but not compiled into this library        */
     DM_ERR_HIP = -7          /* HIP runtime error (launch or asynchronous fault) */
 } dm_status;
 

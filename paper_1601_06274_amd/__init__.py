@@ -11,6 +11,8 @@ streams).  Importing the package does not load the shared library; the first
 call does, and it raises if ``libdmatch.so`` has not been built.
 """
 from ._lib import DmError, lib  # noqa: F401
-from .ops import DiscreteResult, build_cost_volume, refine_continuous, solve_discrete, tile_for  # noqa: F401
+from .ops import (DiscreteResult, build_cost_volume, refine_continuous, refine_continuous_backward,  # noqa: F401
+                  solve_discrete, solve_discrete_backward, tile_for)
 
-__all__ = ["DmError", "lib", "DiscreteResult", "solve_discrete", "tile_for", "refine_continuous", "build_cost_volume"]
+__all__ = ["DmError", "lib", "DiscreteResult", "solve_discrete", "solve_discrete_backward", "tile_for",
+           "refine_continuous", "refine_continuous_backward", "build_cost_volume"]

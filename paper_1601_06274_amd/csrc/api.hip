@@ -136,7 +136,7 @@ extern "C" const char* dm_status_string(int status) {
         case DM_ERR_PARAM: return "DM_ERR_PARAM: parameter out of range";
         case DM_ERR_DTYPE: return "DM_ERR_DTYPE: unknown dtype";
         case DM_ERR_WORKSPACE: return "DM_ERR_WORKSPACE: workspace missing or too small";
-        case DM_ERR_UNSUPPORTED: return "DM_ERR_UNSUPPORTED: not supported by this build";
+        case DM_ERR_UNSUPPORTED: return "DM_ERR_UNSUPPORTED: not compiled into this library";
         case DM_ERR_HIP: return "DM_ERR_HIP: HIP runtime error";
         default: return "unknown dm_status";
     }
