@@ -7,20 +7,26 @@
 // 0, -1, +1, -2, +2, ... before the truncation term on ties), normalisations subtract
 // the summed adjoint at the argmin.
 //
-// One half-step of the forward is recomputed from its dual checkpoint by the record
-// mode of chain_kernel, which keeps the messages of every pass (M[0] .. M[P]) and the
-// dual after every update pass but the last (Lam[1] .. Lam[P-1]).  The adjoint kernel
-// then walks, per chain, the passes in reverse order and each pass against its
-// direction, carrying the adjoint of the in-register message and exchanging the
-// adjoints of stored messages through two ping-pong volumes.  The adjoint of the dual
-// (in units of the half-step's family unaries r) is updated in place in `lbar`.
+// The adjoint kernel walks, per chain, the passes of a half-step in reverse order and
+// each pass against its direction, carrying the adjoint of the in-register message and
+// exchanging the adjoints of stored messages through two ping-pong volumes.  The
+// adjoint of the dual (in units of the half-step's family unaries r) is updated in
+// place in `lbar`.  Two forms:
+//   * tape form (default): the record mode of chain_kernel (in the forward, or in a
+//     recompute from the dual checkpoint) wrote per pass, node and label which
+//     candidate each min took and the node's two argmins; the adjoint routes along
+//     those selections and reads no forward values;
+//   * recomputing form: the record mode kept every pass's messages (M[0] .. M[P]) and
+//     the duals between passes (Lam[1] .. Lam[P-1]); the adjoint replays each node's
+//     forward step with the same arithmetic and recomputes the selections (in-lane
+//     scans, or a window search in LDS).
+// Both give the same gradients bit for bit (up to the sign of zeros).
 //
 // Message adjoint: the adjoint of phi(b) = v(src(b)) + w*dist(b) - vmin goes to
 // v(src(b)) (window source or, for the truncation term, the argmin of v) and to w;
-// the subtraction of vmin sends minus the total to argmin v.  Sources are found in
-// LDS (the group's v), the gather back is a fixed-order sum (no atomics, bitwise
-// deterministic).  The kernel's workgroup is one wave, so LDS exchanges need only the
-// LDS wait, not a workgroup barrier.
+// the subtraction of vmin sends minus the total to argmin v.  The gather back is a
+// fixed-order sum (no atomics, bitwise deterministic).  The kernel's workgroup is one
+// wave, so LDS exchanges need only the LDS wait, not a workgroup barrier.
 #pragma once
 
 #include "dmm_kernels.h"

@@ -18,11 +18,15 @@
 //     branches around memory operations and the wait counters stay exact.
 //   * Min over labels = in-lane min + DPP butterfly (quad_perm, row mirrors) +
 //     gfx950 permlane16/32 swaps for groups of 32/64 lanes.
-//   * Message for the truncated-linear pairwise term w*min(|a-b|, T): the two-pass
-//     L1 distance transform (a forward and a backward lower-envelope scan, in-lane,
-//     extended across lane boundaries with wave_shr/wave_shl DPP for as many lanes as
-//     the truncation radius T-1 needs) followed by min(., min v + wT).  O(K) work per
-//     message for fixed T.
+//   * Message for the truncated-linear pairwise term w*min(|a-b|, T): for T <= 3 the
+//     window itself (the label and up to two labels on each side, neighbour lanes'
+//     values by wave_shr/wave_shl DPP, each candidate rounded once); for larger T the
+//     two-pass L1 distance transform (a forward and a backward lower-envelope scan,
+//     in-lane, extended across lane boundaries for as many lanes as the truncation
+//     radius T-1 needs); then min(., min v + wT).  O(K) work per message for fixed T.
+//   * Record mode (the backward's input): the same passes also write, per node and
+//     label, which candidate each min took (the selection tape), or keep every pass's
+//     messages and duals.
 //   * Messages are renormalised to minimum 0 at every step (they are defined up to a
 //     constant); the subtracted constants add up to the chain optimum, accumulated in
 //     FP64 for the lower bound.

@@ -108,3 +108,47 @@ def test_default_tile_host_query():
         assert g.value * l.value >= K
     assert lib.dm_default_tile(300, ctypes.byref(g), ctypes.byref(l)) == -2
     assert lib.dm_default_tile(8, None, ctypes.byref(l)) == -1
+
+
+def _al(x, a=256):
+    return (x + a - 1) // a * a
+
+
+def _tape_bytes(W, H, K, T, tile, recompute):
+    """One selection tape: G lanes x ceil(LPL/4) dwords per pixel, when the window reaches at
+    most one lane across (and the caller did not ask for recomputation)."""
+    G, lpl = tile
+    need = (T - 1 + lpl - 1) // lpl
+    if recompute or min(need, G - 1) > 1:
+        return 0
+    b = _al(W * H * G * ((lpl + 3) // 4) * 4)
+    return b if b <= 0xFE000000 else 0
+
+
+@pytest.mark.parametrize("keep", [0, 1, 2])
+@pytest.mark.parametrize("T,tile,recompute", [(3, (64, 3), False), (3, (64, 3), True), (5, (4, 1), False),
+                                              (5, (8, 4), False), (1, (4, 2), False)])
+def test_checkpoint_and_tape_workspace_sizes(keep, T, tile, recompute):
+    """Forward and backward workspace sizes for every checkpoint mode, with and without
+    selection tapes (the layouts the solver and its adjoint index into)."""
+    lib = L.lib()
+    W, H, K, it = 40, 24, tile[0] * tile[1] - 1, 3
+    P = 3  # update passes of the iterative minorant (1/4, 1/4, 1)
+    p = _params(T=T, n_iters=it, tile=tile, keep_checkpoints=keep, recompute_selections=recompute)
+    S = 2 * it
+    vol = _al(W * H * K * 4)
+    tb = _tape_bytes(W, H, K, T, tile, recompute)
+    head = _al(_al(_al(vol + (S + 2) * max(W, H) * 8) + 1024 * 8) + W * H * 4)
+    if keep == 0:
+        slab = 0
+    elif keep == 1:
+        slab = vol
+    else:
+        slab = vol + (P + 1) * tb if tb else (1 + (P + 1) + (P - 1)) * vol
+    assert lib.dm_solve_discrete_workspace(L.DmShape(W, H, K), L.DM_F16, ctypes.byref(p)) == head + S * slab
+    if keep == 0:
+        return
+    Pb = 1 if keep == 2 else P
+    body = ((1 if tb else Pb + 1) + (((1 if tb else Pb - 1)) if Pb > 1 else 0)) * vol + ((Pb + 1) * tb if tb else 0)
+    body += 3 * vol + _al(H * (W - 1) * 8) + _al((H - 1) * W * 8) + _al(W * H * 4)
+    assert lib.dm_solve_discrete_backward_workspace(L.DmShape(W, H, K), ctypes.byref(p)) == body
