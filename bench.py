@@ -145,10 +145,14 @@ def batched_extra(torch, ops, dev, n=64, seed=4000, n_iters=20, T=3, reps=3):
             "speedup_vs_plain_fp32": ms_p / ms_b}
 
 
-def diff_extra(torch, ops, dev, n=8, W=960, H=320, K=96, n_iters=20, T=3, warps=5, iters=10, seed=5000, reps=2):
-    """Differentiation workload: 8 frames 960x320, K=96, FP16 cost; forward (Dual_MM 20 its
-    keeping the selection tapes + refinement 5 x 10 steps) and backward (dL/dcost, dL/dw) per
-    frame, against the plain FP32 forward of the same frames."""
+def diff_extra(torch, ops, dev, n=8, W=960, H=320, K=96, n_iters=20, T=3, warps=5, iters=10, seed=5000, reps=2,
+               n_streams=8):
+    """Differentiation workload: a batch of 8 frames 960x320, K=96, FP16 cost; forward
+    (Dual_MM 20 its keeping the selection tapes + refinement 5 x 10 steps) and backward
+    (dL/dcost, dL/dw) per frame.  One frame fills only a few hundred waves, so the batch
+    runs on n_streams streams (default priority; frames round-robin, each stream with its
+    own workspaces).  Reported against the plain FP32 forward of the same frames, one
+    frame after another and on the same streams."""
     import ctypes
     import synth
     import paper_1601_06274_amd as P
@@ -165,57 +169,84 @@ def diff_extra(torch, ops, dev, n=8, W=960, H=320, K=96, n_iters=20, T=3, warps=
     lib = P.lib()
     shp = P._lib.DmShape(W, H, K)
     dp = ops.discrete_params(keep_checkpoints=2, **dkw)
-    ws_d = torch.empty(lib.dm_solve_discrete_workspace(shp, P._lib.DM_F16, ctypes.byref(dp)), dtype=torch.uint8,
-                       device=dev)
-    ws_db = torch.empty(lib.dm_solve_discrete_backward_workspace(shp, ctypes.byref(dp)), dtype=torch.uint8, device=dev)
     rp = ops.refine_params(keep_tape=True, **rkw)
-    ws_r = torch.empty(lib.dm_refine_continuous_workspace(shp, ctypes.byref(rp)), dtype=torch.uint8, device=dev)
-    ws_rb = torch.empty(lib.dm_refine_continuous_backward_workspace(shp, ctypes.byref(rp)), dtype=torch.uint8,
-                        device=dev)
     gen = torch.Generator(device=dev).manual_seed(seed)
     G_m = torch.randn((H, W, K), generator=gen, device=dev)
     G_u = torch.randn((H, W), generator=gen, device=dev)
-    dual = torch.empty((H, W, K), dtype=torch.float32, device=dev)
-    mm = torch.empty_like(dual)
-    lab = torch.empty((H, W), dtype=torch.int32, device=dev)
-    u = torch.empty((H, W), dtype=torch.float32, device=dev)
-    gc = torch.empty_like(dual)
-    gwh = torch.empty((H, W - 1), dtype=torch.float32, device=dev)
-    gwv = torch.empty((H - 1, W), dtype=torch.float32, device=dev)
-    grad_lpw = []
 
-    def fwd_bwd():
-        grad_lpw.clear()
-        for c16, _, wh, wv in frames:
-            ops.solve_discrete(c16, wh, wv, dual=dual, workspace=ws_d, labels=lab, minmarg=mm, want_bounds=True,
-                               keep_checkpoints=2, **dkw)
-            ops.refine_continuous(c16, lab, wh, wv, workspace=ws_r, u_out=u, keep_tape=True, **rkw)
-            ops.refine_continuous_backward(G_u, c16, wh, wv, ws_r, grad_cost=gc, grad_w_h=gwh, grad_w_v=gwv,
-                                           accumulate=False, workspace=ws_rb, **rkw)
-            ops.solve_discrete_backward(c16, wh, wv, dual, ws_d, grad_minmarg=G_m, grad_lb=1.0, grad_cost=gc,
-                                        grad_w_h=gwh, grad_w_v=gwv, accumulate=True, workspace=ws_db,
-                                        keep_checkpoints=2, **dkw)
-            # dL/dlambda_pw: the weights are lambda_pw * exp(...), so sum(dL/dw * w) / lambda_pw
-            grad_lpw.append((gwh * wh).sum() + (gwv * wv).sum())
+    def buffers():
+        b = dict(ws_d=torch.empty(lib.dm_solve_discrete_workspace(shp, P._lib.DM_F16, ctypes.byref(dp)),
+                                  dtype=torch.uint8, device=dev),
+                 ws_db=torch.empty(lib.dm_solve_discrete_backward_workspace(shp, ctypes.byref(dp)), dtype=torch.uint8,
+                                   device=dev),
+                 ws_r=torch.empty(lib.dm_refine_continuous_workspace(shp, ctypes.byref(rp)), dtype=torch.uint8,
+                                  device=dev),
+                 ws_rb=torch.empty(lib.dm_refine_continuous_backward_workspace(shp, ctypes.byref(rp)),
+                                   dtype=torch.uint8, device=dev))
+        b["dual"] = torch.empty((H, W, K), dtype=torch.float32, device=dev)
+        b["mm"] = torch.empty_like(b["dual"])
+        b["gc"] = torch.empty_like(b["dual"])
+        b["lab"] = torch.empty((H, W), dtype=torch.int32, device=dev)
+        b["u"] = torch.empty((H, W), dtype=torch.float32, device=dev)
+        b["gwh"] = torch.empty((H, W - 1), dtype=torch.float32, device=dev)
+        b["gwv"] = torch.empty((H - 1, W), dtype=torch.float32, device=dev)
+        b["ws32"] = None
+        return b
 
-    ws32 = None
+    bufs = [buffers() for _ in range(n_streams)]
+    streams = [torch.cuda.Stream(device=dev) for _ in range(n_streams)]
+    grad_lpw = [None] * n
 
-    def plain32():
-        nonlocal ws32
-        for _, c32, wh, wv in frames:
-            r = ops.solve_discrete(c32, wh, wv, dual=dual, workspace=ws32, labels=lab, want_bounds=False,
-                                   want_minmarg=False, **dkw)
-            ws32 = r.workspace
-            ops.refine_continuous(c32, lab, wh, wv, u_out=u, workspace=ws_r, **rkw)
+    def one_fwd_bwd(f, b):
+        c16, _, wh, wv = frames[f]
+        ops.solve_discrete(c16, wh, wv, dual=b["dual"], workspace=b["ws_d"], labels=b["lab"], minmarg=b["mm"],
+                           want_bounds=True, keep_checkpoints=2, **dkw)
+        ops.refine_continuous(c16, b["lab"], wh, wv, workspace=b["ws_r"], u_out=b["u"], keep_tape=True, **rkw)
+        ops.refine_continuous_backward(G_u, c16, wh, wv, b["ws_r"], grad_cost=b["gc"], grad_w_h=b["gwh"],
+                                       grad_w_v=b["gwv"], accumulate=False, workspace=b["ws_rb"], **rkw)
+        ops.solve_discrete_backward(c16, wh, wv, b["dual"], b["ws_d"], grad_minmarg=G_m, grad_lb=1.0,
+                                    grad_cost=b["gc"], grad_w_h=b["gwh"], grad_w_v=b["gwv"], accumulate=True,
+                                    workspace=b["ws_db"], keep_checkpoints=2, **dkw)
+        # dL/dlambda_pw: the weights are lambda_pw * exp(...), so sum(dL/dw * w) / lambda_pw
+        grad_lpw[f] = (b["gwh"] * wh).sum() + (b["gwv"] * wv).sum()
 
-    ms_fb = _timed(fwd_bwd, reps, torch)
-    ms_32 = _timed(plain32, reps, torch)
+    def one_plain32(f, b):
+        _, c32, wh, wv = frames[f]
+        r = ops.solve_discrete(c32, wh, wv, dual=b["dual"], workspace=b["ws32"], labels=b["lab"], want_bounds=False,
+                               want_minmarg=False, **dkw)
+        b["ws32"] = r.workspace
+        ops.refine_continuous(c32, b["lab"], wh, wv, u_out=b["u"], workspace=b["ws_r"], **rkw)
+
+    def concurrent(fn):
+        main = torch.cuda.current_stream(dev)
+        for st in streams:
+            st.wait_stream(main)
+        for f in range(n):
+            k = f % n_streams
+            with torch.cuda.stream(streams[k]):
+                fn(f, bufs[k])
+        for st in streams:
+            main.wait_stream(st)
+
+    def sequential(fn):
+        for f in range(n):
+            fn(f, bufs[0])
+
+    ms_fb = _timed(lambda: concurrent(one_fwd_bwd), reps, torch)
+    ms_fb_seq = _timed(lambda: sequential(one_fwd_bwd), reps, torch)
+    ms_32 = _timed(lambda: sequential(one_plain32), reps, torch)
+    ms_32_conc = _timed(lambda: concurrent(one_plain32), reps, torch)
     finite = bool(all(torch.isfinite(g).item() for g in grad_lpw))
-    return {"workload": f"{n} frames {W}x{H}, K={K}, FP16 cost; Dual_MM {n_iters} its (tapes kept by the forward) + "
-                        f"refinement {warps}x{iters}; backward dL/dcost, dL/dw (and dL/dlambda_pw)",
+    return {"workload": f"batch of {n} frames {W}x{H}, K={K}, FP16 cost; Dual_MM {n_iters} its (tapes kept by the "
+                        f"forward) + refinement {warps}x{iters}; backward dL/dcost, dL/dw (and dL/dlambda_pw); "
+                        f"{n_streams} streams",
             "fwd_bwd_fp16_ms_per_batch": ms_fb, "fwd_bwd_fp16_ms_per_frame": ms_fb / n,
-            "plain_fp32_forward_ms_per_batch": ms_32, "ratio_fwd_bwd_to_plain_fwd": ms_fb / ms_32,
-            "checkpoint_GB": ws_d.numel() / 1e9, "backward_workspace_GB": ws_db.numel() / 1e9,
+            "fwd_bwd_fp16_one_stream_ms_per_batch": ms_fb_seq,
+            "plain_fp32_forward_ms_per_batch": ms_32, "plain_fp32_forward_streams_ms_per_batch": ms_32_conc,
+            "ratio_fwd_bwd_to_plain_fwd": ms_fb / ms_32,
+            "ratio_fwd_bwd_to_plain_fwd_same_streams": ms_fb / ms_32_conc,
+            "checkpoint_GB_per_stream": bufs[0]["ws_d"].numel() / 1e9,
+            "backward_workspace_GB_per_stream": bufs[0]["ws_db"].numel() / 1e9,
             "grad_finite": finite}
 
 
