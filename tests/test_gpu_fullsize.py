@@ -1,0 +1,144 @@
+"""Parity at the full stereo frame (1242x375, K=192, FP16 cost, 20 dual iterations, T=3,
+iterative minorant 1/4, 1/4, 1, the tiles the bench's autotuner picks).
+
+The FP64 oracle cannot run the whole solve within a test's time, so it checks sampled chains
+one by one: a horizontal half-step on sampled rows and a vertical half-step on sampled
+columns, each from the GPU's own dual before it; the final pass's normalized min-marginals
+on sampled rows from the GPU's final dual; and the lower bound (every chain's optimum at the
+GPU's final dual).  The backward is checked through properties that hold at any size: the
+outputs are positively homogeneous of degree 1 in (cost, weights) (every step of Dual_MM
+commutes with scaling), so <cost, dL/dcost> + <w, dL/dw> = L (Euler); a constant added to one
+pixel's costs moves LB by that constant and leaves the normalized min-marginals unchanged, so
+the per-pixel sums of dL/dcost equal g_lb; and the tape form equals the recomputing form bit
+for bit.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import chain as och, dmm as odmm
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FRAME = dict(W=1242, H=375, K=192, seed=3000, slope=0.08, occlusion_bands=4, segments=16)
+T, ITERS, GAMMAS = 3, 20, (0.25, 0.25, 1.0)
+ROWS = [0, 187, 374]
+COLS = [0, 620, 1241]
+
+
+@pytest.fixture(scope="module")
+def frame():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1601_06274_amd import ops
+    W, H, K = FRAME["W"], FRAME["H"], FRAME["K"]
+    pair = synth.stereo_pair(W, H, K, seed=FRAME["seed"], segments=FRAME["segments"], slope=FRAME["slope"],
+                             occlusion_bands=FRAME["occlusion_bands"])
+    dev = torch.device("cuda:0")
+    cost, w_h, w_v = ops.build_cost_volume(torch.from_numpy(pair.left).to(dev), torch.from_numpy(pair.right).to(dev),
+                                           K, dtype=torch.float16)
+    tiles = ops.autotune_tiles((H, W, K), torch.float16, T=T, gammas=GAMMAS)
+    torch.cuda.synchronize()
+    print(f"[case] full frame {W}x{H}x{K} FP16, tiles {tiles}", flush=True)
+    return dict(ops=ops, cost=cost, w_h=w_h, w_v=w_v, kw=dict(T=T, gammas=GAMMAS, tile=tiles),
+                th=cost.float().cpu().numpy().astype(np.float64), wh=w_h.cpu().numpy().astype(np.float64),
+                wv=w_v.cpu().numpy().astype(np.float64))
+
+
+def _dual(f, half_steps):
+    r = f["ops"].solve_discrete(f["cost"], f["w_h"], f["w_v"], n_half_steps=half_steps, want_minmarg=False,
+                                want_bounds=False, **f["kw"])
+    return r.dual.cpu().numpy().astype(np.float64)
+
+
+def test_fullsize_half_steps_sampled(frame):
+    """One H half-step (rows) and one V half-step (columns) against the oracle on sampled
+    chains, from the GPU's dual after 2*ITERS - 2 and 2*ITERS - 1 half-steps."""
+    f = frame
+    k = 2 * ITERS - 2
+    lam_a, lam_b, lam_c = _dual(f, k), _dual(f, k + 1), _dual(f, k + 2)
+    scale = max(1.0, np.abs(lam_b).max())
+    h = och.iterative_minorant(f["th"][ROWS] - lam_a[ROWS], f["wh"][ROWS], T, GAMMAS)
+    err_h = np.abs(lam_a[ROWS] + h - lam_b[ROWS]).max() / scale
+    a = np.ascontiguousarray(np.transpose(lam_b[:, COLS], (1, 0, 2)))
+    hv = och.iterative_minorant(a, f["wv"][:, COLS].T, T, GAMMAS)
+    err_v = np.abs(lam_b[:, COLS] - np.transpose(hv, (1, 0, 2)) - lam_c[:, COLS]).max() / scale
+    print(f"[parity] full-size half-steps: H {err_h:.2e}, V {err_v:.2e} (relative to max |dual| {scale:.3f})",
+          flush=True)
+    assert err_h <= 1e-5 and err_v <= 1e-5
+    # the other chains moved too (not a no-op)
+    assert np.abs(lam_b - lam_a).max() > 1e-3
+
+
+def test_fullsize_final_pass_and_bound(frame):
+    """Final normalized row min-marginals on sampled rows, labels = their argmin everywhere,
+    LB against every chain's optimum at the GPU's final dual, LB <= E."""
+    f = frame
+    ops = f["ops"]
+    r = ops.solve_discrete(f["cost"], f["w_h"], f["w_v"], n_iters=ITERS, want_bounds=True, **f["kw"])
+    torch.cuda.synchronize()
+    lam = r.dual.cpu().numpy().astype(np.float64)
+    mm = r.minmarg.cpu().numpy().astype(np.float64)
+    labels = r.labels.cpu().numpy()
+    th = f["th"]
+    S = th.max() - th.min()
+    ref = och.min_marginals(th[ROWS] - lam[ROWS], f["wh"][ROWS], T)
+    rel = np.abs(mm[ROWS] - ref) / np.maximum(np.abs(ref), S)
+    # labels: argmin of the returned min-marginals (lowest label on ties), every pixel
+    same = np.array_equal(labels, np.argmin(mm, axis=2))
+    lb_gpu, e_gpu = (float(x) for x in r.bounds.cpu().numpy())
+    lb_ref = odmm.lower_bound(th, lam, f["wh"], f["wv"], T)
+    print(f"[parity] full-size final pass: min-marginal rel {rel.max():.2e}; LB {lb_gpu:.4f} vs {lb_ref:.4f}; "
+          f"E {e_gpu:.4f}", flush=True)
+    assert rel.max() <= 1e-5
+    assert same
+    assert abs(lb_gpu - lb_ref) <= 1e-5 * abs(lb_ref)
+    assert lb_gpu <= e_gpu + 1e-9 * abs(e_gpu)
+
+
+def _grads(f, keep, recompute, G_m, g_lb):
+    ops = f["ops"]
+    r = ops.solve_discrete(f["cost"], f["w_h"], f["w_v"], n_iters=ITERS, want_bounds=True, keep_checkpoints=keep,
+                           recompute_selections=recompute, **f["kw"])
+    g = ops.solve_discrete_backward(f["cost"], f["w_h"], f["w_v"], r.dual, r.workspace, grad_minmarg=G_m,
+                                    grad_lb=g_lb, n_iters=ITERS, keep_checkpoints=keep,
+                                    recompute_selections=recompute, **f["kw"])
+    torch.cuda.synchronize()
+    out = (r.minmarg.clone(), float(r.bounds[0]), [x.clone() for x in g])
+    del r, g
+    torch.cuda.empty_cache()
+    return out
+
+
+def test_fullsize_backward_properties(frame):
+    """Euler's identity and the constant-shift identity for L = <G_m, min-marginals> +
+    g_lb * LB at the full frame, with the tapes kept by the forward (the bench's step)."""
+    f = frame
+    g_lb = 0.5
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    G_m = torch.randn(f["cost"].shape, generator=gen, device="cuda", dtype=torch.float32)
+    mm, lb, (gc, gwh, gwv) = _grads(f, 2, False, G_m, g_lb)
+    L = float((G_m.double() * mm.double()).sum()) + g_lb * lb
+    euler = float((f["cost"].double() * gc.double()).sum() + (f["w_h"].double() * gwh.double()).sum()
+                  + (f["w_v"].double() * gwv.double()).sum())
+    scale = float((f["cost"].double() * gc.double()).abs().sum() + (f["w_h"].double() * gwh.double()).abs().sum()
+                  + (f["w_v"].double() * gwv.double()).abs().sum())
+    shift = (gc.double().sum(dim=2) - g_lb).abs().max().item()
+    print(f"[parity] full-size backward: Euler {euler:.6f} vs L {L:.6f} (scale {scale:.1f}); per-pixel sum of "
+          f"dL/dcost - g_lb: max {shift:.2e}", flush=True)
+    assert abs(euler - L) <= 1e-5 * scale
+    assert shift <= 1e-3
+    assert torch.isfinite(gc).all() and torch.isfinite(gwh).all() and torch.isfinite(gwv).all()
+
+
+def test_fullsize_tape_equals_recompute(frame):
+    """The backward from forward-kept tapes equals the backward that recomputes every
+    half-step and every selection (window search) bit for bit at the full frame."""
+    f = frame
+    gen = torch.Generator(device="cuda").manual_seed(12)
+    G_m = torch.randn(f["cost"].shape, generator=gen, device="cuda", dtype=torch.float32)
+    _, _, g_tape = _grads(f, 2, False, G_m, 1.0)
+    _, _, g_rec = _grads(f, 1, True, G_m, 1.0)
+    for a, b in zip(g_tape, g_rec):
+        assert torch.equal(a, b), float((a - b).abs().max())
