@@ -122,3 +122,43 @@ def test_autotuner_returns_valid_tiles():
     for shape in [(20, 40, 32), (30, 25, 192), (9, 9, 5)]:
         (gr, lr), (gc, lc) = ops.autotune_tiles(shape, torch.float16)
         assert gr * lr >= shape[2] and gc * lc >= shape[2]
+
+
+def test_batched_full_64_instances_sampled():
+    """The batched workload at its full size (64 uneven instances, W in [160, 1280], H in
+    [120, 720], K in {32, 64, 128, 192} from seed 4000, FP16 cost, 20 dual iterations, one
+    graph launch): the smallest and the largest instance of every K equal their
+    single-instance solves with the plan's tiles (autotuned per K on the largest instance
+    of that K) bit for bit.  The single-instance path is checked against the oracle at the
+    full frame size in test_gpu_fullsize."""
+    ops = _need()
+    specs = synth.batch_specs(64, seed=4000)
+    insts = []
+    for sp in specs:
+        pair = synth.stereo_pair(sp.W, sp.H, sp.K, seed=sp.seed)
+        c16, wh, wv = ops.build_cost_volume(_dev(pair.left), _dev(pair.right), sp.K, dtype=torch.float16)
+        insts.append(dict(cost=c16, w_h=wh, w_v=wv))
+    print(f"[case] batched full: {len(insts)} instances, "
+          f"{sum(sp.W * sp.H * sp.K for sp in specs) / 1e9:.2f} G label-nodes", flush=True)
+    plan = ops.BatchedPlan(insts, T=3, n_iters=20)
+    try:
+        plan.run()
+        torch.cuda.synchronize()
+        by_k = {}
+        for i, sp in enumerate(specs):
+            by_k.setdefault(sp.K, []).append(i)
+        checked = 0
+        for K, idx in sorted(by_k.items()):
+            area = lambda i: specs[i].W * specs[i].H
+            big = max(idx, key=area)
+            tiles = ops.autotune_tiles((specs[big].H, specs[big].W, K), torch.float16, T=3)
+            for i in sorted({min(idx, key=area), big}):
+                d = insts[i]
+                s = ops.solve_discrete(d["cost"], d["w_h"], d["w_v"], T=3, n_iters=20, tile=tiles)
+                torch.cuda.synchronize()
+                assert torch.equal(plan.instances[i]["labels"], s.labels), f"instance {i} labels"
+                assert torch.equal(plan.instances[i]["dual"], s.dual), f"instance {i} dual"
+                checked += 1
+        assert checked >= 4
+    finally:
+        plan.close()
