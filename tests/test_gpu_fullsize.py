@@ -142,3 +142,46 @@ def test_fullsize_tape_equals_recompute(frame):
     _, _, g_rec = _grads(f, 1, True, G_m, 1.0)
     for a, b in zip(g_tape, g_rec):
         assert torch.equal(a, b), float((a - b).abs().max())
+
+
+def test_config_640x480_fp32_with_refinement():
+    """The 640x480, K=128 stereo workload (FP32 cost, 20 dual iterations, then refinement
+    5 warps x 40 iterations): the whole cost volume, the final min-marginals of sampled rows
+    and the lower bound from the GPU's final dual, and the whole refinement from the GPU's
+    labels, against the oracle."""
+    from oracle import cost_volume as ocv, refine as oref
+    from paper_1601_06274_amd import ops
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    W, H, K = 640, 480, 128
+    pair = synth.stereo_pair(W, H, K, seed=2000, segments=12, slope=0.02)
+    dev = torch.device("cuda:0")
+    print(f"[case] stereo {W}x{H}x{K} FP32 + refinement", flush=True)
+    cost, w_h, w_v = ops.build_cost_volume(torch.from_numpy(pair.left).to(dev),
+                                           torch.from_numpy(pair.right).to(dev), K, dtype=torch.float32)
+    r = ops.solve_discrete(cost, w_h, w_v, T=T, n_iters=ITERS, gammas=GAMMAS, want_bounds=True)
+    u = ops.refine_continuous(cost, r.labels, w_h, w_v, C=3.0, n_warps=5, n_iters=40)
+    torch.cuda.synchronize()
+    th = cost.cpu().numpy().astype(np.float64)
+    wh, wv = w_h.cpu().numpy().astype(np.float64), w_v.cpu().numpy().astype(np.float64)
+    err_cv = np.abs(th - ocv.sad_cost_volume(pair.left, pair.right, K)).max()
+    lam = r.dual.cpu().numpy().astype(np.float64)
+    mm = r.minmarg.cpu().numpy().astype(np.float64)
+    rows = [0, 239, 479]
+    ref = och.min_marginals(th[rows] - lam[rows], wh[rows], T)
+    S = th.max() - th.min()
+    rel = (np.abs(mm[rows] - ref) / np.maximum(np.abs(ref), S)).max()
+    lb_gpu = float(r.bounds[0])
+    lb_ref = odmm.lower_bound(th, lam, wh, wv, T)
+    labels = r.labels.cpu().numpy()
+    f32 = lambda v: float(np.float32(v))  # the C ABI takes float32 parameters
+    u_ref = oref.refine_continuous(th, wh, wv, labels, oref.RefineParams(C=3.0, tau=f32(0.3), sigma=f32(0.3),
+                                                                          n_warps=5, n_iters=40))
+    err_u = np.abs(u.cpu().numpy() - u_ref).max()
+    print(f"[parity] 640x480: cost volume {err_cv:.2e}, min-marginals rel {rel:.2e}, LB {lb_gpu:.4f} vs "
+          f"{lb_ref:.4f}, refined u {err_u:.2e}", flush=True)
+    assert err_cv <= 2e-6
+    assert rel <= 1e-5
+    assert abs(lb_gpu - lb_ref) <= 1e-5 * abs(lb_ref)
+    assert np.array_equal(labels, np.argmin(mm, axis=2))
+    assert err_u <= 1e-4
