@@ -185,3 +185,21 @@ def test_config_640x480_fp32_with_refinement():
     assert abs(lb_gpu - lb_ref) <= 1e-5 * abs(lb_ref)
     assert np.array_equal(labels, np.argmin(mm, axis=2))
     assert err_u <= 1e-4
+
+
+def test_fullsize_refinement(frame):
+    """Refinement at the full frame (FP16 cost, 5 warps x 40 iterations, C = 3) from the
+    GPU's labels, against the oracle on the same labels."""
+    from oracle import refine as oref
+    f = frame
+    ops = f["ops"]
+    r = ops.solve_discrete(f["cost"], f["w_h"], f["w_v"], n_iters=ITERS, want_minmarg=False, want_bounds=False,
+                           **f["kw"])
+    u = ops.refine_continuous(f["cost"], r.labels, f["w_h"], f["w_v"], C=3.0, n_warps=5, n_iters=40)
+    torch.cuda.synchronize()
+    f32 = lambda v: float(np.float32(v))  # the C ABI takes float32 parameters
+    u_ref = oref.refine_continuous(f["th"], f["wh"], f["wv"], r.labels.cpu().numpy(),
+                                   oref.RefineParams(C=3.0, tau=f32(0.3), sigma=f32(0.3), n_warps=5, n_iters=40))
+    err = np.abs(u.cpu().numpy() - u_ref).max()
+    print(f"[parity] full-size refinement: max |u - u_ref| {err:.2e}", flush=True)
+    assert err <= 1e-4
