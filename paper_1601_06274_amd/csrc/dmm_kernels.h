@@ -408,10 +408,11 @@ struct Walker {
     // 0-2 which candidate the minimum took - the first in the order d = 0, -1, +1, -2,
     // +2 that attains it, the cap only when strictly lower (codes 0-4, 5 for the cap) -
     // and in bits 3-4 its distance (T for the cap).
-    template <bool TP>
+    // T3: T is 3 (both window distances enabled; no per-node selection of the weights).
+    template <bool TP, bool T3>
     __device__ __forceinline__ void message_direct(const float (&v)[LPL], float vmin, float wt, float (&out)[LPL],
                                                    uint32_t (&tw)[kTW]) {
-        const float w1 = T > 1 ? wt : kBig;          // disabled candidates sit above every window value
+        const float w1 = (T3 || T > 1) ? wt : kBig;  // disabled candidates sit above every window value
         const float w2 = T > 2 ? wt + wt : kBig;     // 2w is exact: v + 2w rounds like fma(w, 2, v)
         const float cap = __builtin_fmaf(wt, Tf, vmin);
         const float l1 = from_left_r(v[LPL - 1], dl);
@@ -424,7 +425,7 @@ struct Walker {
         auto val = [&](int a) -> float {
             return a < 0 ? (a == -1 ? l1 : l2) : (a >= LPL ? (a == LPL ? r1 : r2) : v[a]);
         };
-        const unsigned cap_code = 5u | ((unsigned)T << 3);
+        const unsigned cap_code = 5u | ((unsigned)(T3 ? 3 : T) << 3);
 #pragma unroll
         for (int j = 0; j < kTW; ++j) tw[j] = 0u;
 #pragma unroll
@@ -432,7 +433,8 @@ struct Walker {
             const bool valid = FULL || lv[i];
             const float s0 = v[i];
             const float cm1 = val(i - 1) + w1, cp1 = val(i + 1) + w1;
-            const float cm2 = val(i - 2) + w2, cp2 = val(i + 2) + w2;
+            const float cm2 = T3 ? __builtin_fmaf(wt, 2.0f, val(i - 2)) : val(i - 2) + w2;
+            const float cp2 = T3 ? __builtin_fmaf(wt, 2.0f, val(i + 2)) : val(i + 2) + w2;
             const float e = fminf(fminf(fminf(s0, cm1), cp1), fminf(cm2, cp2));
             out[i] = valid ? fminf(e, cap) - vmin : 0.0f;
             if constexpr (TP) {
@@ -623,7 +625,7 @@ struct Walker {
     // 2 = naive update, 3 = final min-marginals.  Adds the normalisation constants of a
     // message pass (= chain optimum) to `opt`.
     // MF: message form - 0 scans reaching several lanes, 1 scans reaching one lane (DT1),
-    // 2 direct window.
+    // 2 direct window, 3 direct window with T = 3.
     template <bool FWD, int KIND, int MF, bool TP>
     __device__ __forceinline__ void pass(float gamma, bool store_msg, double& opt) {
         constexpr bool WANT_REV = KIND != 0;
@@ -671,7 +673,10 @@ struct Walker {
     template <bool FWD, int KIND, bool TP = false>
     __device__ __forceinline__ void run_pass(float gamma, bool store_msg, double& opt) {
         if (direct) {
-            pass<FWD, KIND, 2, TP>(gamma, store_msg, opt);
+            if (T == 3)
+                pass<FWD, KIND, 3, TP>(gamma, store_msg, opt);
+            else
+                pass<FWD, KIND, 2, TP>(gamma, store_msg, opt);
         } else if constexpr (TP) {
             pass<FWD, KIND, 1, TP>(gamma, store_msg, opt);  // the host enables tapes for dt_steps <= 1 only
         } else {
@@ -764,9 +769,9 @@ struct Walker {
             if constexpr (KIND == 0) vmin = group_min<G>(lane_min(v));
             if constexpr (KIND == 0) opt += (double)vmin;
             if (has_next) {
-                if constexpr (MF == 2) {
+                if constexpr (MF >= 2) {
                     uint32_t tm[kTW];
-                    message_direct<TP>(v, vmin, nd.w, carry, tm);
+                    message_direct<TP, MF == 3>(v, vmin, nd.w, carry, tm);
                     if constexpr (TP) {
 #pragma unroll
                         for (int j = 0; j < kTW; ++j) tw[j] |= tm[j];
