@@ -3,7 +3,10 @@
 Gradients flow to the cost volume and to the edge weights (so to any torch expression
 that produced them, e.g. a scalar pairwise strength times contrast weights).  Labels
 are piecewise constant and carry no gradient.  The forward keeps what the backward
-needs (dual checkpoints per half-step, refinement branch masks) in its workspace.
+needs in its workspace: by default the selection tapes of every half-step
+(keep_checkpoints=2, no recompute in the backward); keep_checkpoints=1 keeps only the
+dual before every half-step and the backward recomputes (less memory); the refinement
+keeps its branch masks.
 """
 from __future__ import annotations
 
@@ -17,8 +20,10 @@ __all__ = ["solve_discrete_ad", "refine_continuous_ad", "DiscreteFn", "RefineFn"
 class DiscreteFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, cost, w_h, w_v, kw):
+        kw = dict(kw)
+        kw.setdefault("keep_checkpoints", 2)
         res = ops.solve_discrete(cost.detach(), w_h.detach().contiguous(), w_v.detach().contiguous(),
-                                 keep_checkpoints=True, want_bounds=True, **kw)
+                                 want_bounds=True, **kw)
         ctx.kw = kw
         ctx.res = res
         ctx.save_for_backward(cost, w_h, w_v)
@@ -30,7 +35,9 @@ class DiscreteFn(torch.autograd.Function):
     def backward(ctx, g_mm, g_lb, _g_labels):
         cost, w_h, w_v = ctx.saved_tensors
         res = ctx.res
-        kw = {k: v for k, v in ctx.kw.items() if k in ("T", "n_iters", "n_half_steps", "minorant", "gammas", "tile")}
+        kw = {k: v for k, v in ctx.kw.items()
+              if k in ("T", "n_iters", "n_half_steps", "minorant", "gammas", "tile", "keep_checkpoints",
+                       "recompute_selections")}
         glb = 0.0 if g_lb is None else float(g_lb.sum().item())
         gm = None if g_mm is None else g_mm.contiguous().to(torch.float32)
         gc, gwh, gwv = ops.solve_discrete_backward(cost.detach(), w_h.detach().contiguous(), w_v.detach().contiguous(),
@@ -61,7 +68,8 @@ class RefineFn(torch.autograd.Function):
 
 
 def solve_discrete_ad(cost, w_h, w_v, **kw):
-    """Differentiable Dual_MM: returns (normalized row min-marginals, lower bound [1], labels)."""
+    """Differentiable Dual_MM: returns (normalized row min-marginals, lower bound [1], labels).
+    keep_checkpoints (2 by default, or 1) selects what the forward keeps for the backward."""
     return DiscreteFn.apply(cost, w_h, w_v, kw)
 
 

@@ -229,8 +229,9 @@ def test_backward_deterministic():
 
 @pytest.mark.parametrize("minorant", ["iterative", "naive"])
 def test_record_all_checkpoints_match_recompute(minorant):
-    """keep_checkpoints=2 (the forward keeps every pass's messages) gives the same forward
-    results and bit-identical gradients as recomputing from dual checkpoints."""
+    """keep_checkpoints=2 (the forward keeps what the backward needs: the selection tapes)
+    gives the same forward results and bit-identical gradients as recomputing from dual
+    checkpoints."""
     ops = _need()
     theta, w_h, w_v = synth.tiny_instance(11, 13, 12, seed=31, w_max=0.5)
     th, wh, wv = _dev(theta, torch.float16), _dev(w_h), _dev(w_v)
