@@ -412,6 +412,16 @@ def main():
                 "avg_launch_ms": ms / n if n else None, "launches": n}
     n_h, ms_h, by_h = prof["sweep_h"]
     per_launch_gb = by_h / n_h / 1e9 if n_h else 0.0
+    # sweep kernel kinds of the timed step (the traffic file of each, its description)
+    STEP_KERNELS = {
+        "adjoint_h": ("adjoint_h_traffic.json",
+                      "adjoint of the horizontal half-step (R0 + 3 update passes in reverse, from the tapes)"),
+        "record_h": ("record_h_traffic.json",
+                     "horizontal half-step recording the selection tapes (R0 + 3 update passes, FP16 cost)"),
+        "adjoint_v": ("adjoint_v_traffic.json", "adjoint of the vertical half-step (from the tapes)"),
+        "record_v": ("record_v_traffic.json", "vertical half-step recording the selection tapes"),
+    }
+    dominant = max(STEP_KERNELS, key=lambda k: prof[k][1])
     del ws_d2, ws_db2
     torch.cuda.empty_cache()
 
@@ -463,12 +473,9 @@ def main():
                                       "half-step, recording its tapes"},
         "forward_only": {"ms_per_frame": fwd_ms, "label_node_updates_per_s": updates / (fwd_ms * 1e-3)},
         "grad_finite": grad_finite,
-        # the step's dominant kernel: the forward's horizontal half-step recording its tapes
-        "roofline": roof("record_h", "record_h_traffic.json",
-                         "horizontal half-step recording the selection tapes (R0 + 3 update passes, FP16 cost)"),
-        "roofline_adjoint": roof("adjoint_h", "adjoint_h_traffic.json",
-                                 "adjoint of the horizontal half-step (R0 + 3 update passes in reverse, from the "
-                                 "tapes)"),
+        # the step's dominant kernel (largest total time among the sweep kinds of the step)
+        "roofline": roof(dominant, STEP_KERNELS[dominant][0], STEP_KERNELS[dominant][1]),
+        "roofline_step_kernels": {k: roof(k, f, d) for k, (f, d) in STEP_KERNELS.items()},
         "roofline_forward_sweep": roof("sweep_h", "sweep_h_traffic.json",
                                        "horizontal half-step chain sweep (R0 + 3 update passes, FP16 cost)"),
         "stage_ms": {
