@@ -17,6 +17,7 @@ Modules
   dmm          dual decomposition and the Dual_MM loop (Sec. 2.3, Alg. Dual_MM)
   energy       the discrete energy and brute-force minimisation (Sec. 2.2)
   cost_volume  SAD cost volume and contrast edge weights (Sec. 2.2 "Stereo", Sec. 3.1)
+  census       Census + Hamming cost volume and the left-right check (Sec. 3.1)
   refine       continuous refinement by non-linear primal-dual (Sec. 2.4, Sec. 3.1)
 """
-from . import chain, dmm, energy, cost_volume, refine  # noqa: F401
+from . import chain, dmm, energy, cost_volume, census, refine  # noqa: F401
