@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="wall time of the oracle sample on all host workers")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (64 uneven instances) and differentiation (8 x 960x320x96) workloads")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -59,23 +60,27 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(pair, wl, target_s):
-    """The FP64 oracle, as it is, on a bounded sample of the same frame: horizontal
+def _oracle_band(job):
+    """One worker of the CPU baseline: the FP64 oracle, as it is, repeating horizontal
     half-steps on a band of rows and vertical half-steps on a band of columns of the
-    frame's cost volume.  Returns label-node updates / s (4 sweeps per half-step)."""
+    frame for about target_s seconds.  Returns (label-node updates, seconds, reps)."""
+    pair, wl, band, target_s = job
     from oracle import cost_volume as ocv, dmm as odmm
-    rows = 16
-    th_rows = ocv.sad_cost_volume(pair.left[:rows], pair.right[:rows], wl["K"])
-    w_h, _ = ocv.contrast_weights(pair.left[:rows])
-    cols = 32
-    th_cols = ocv.sad_cost_volume(pair.left[:, :cols], pair.right[:, :cols], wl["K"])
-    _, w_v = ocv.contrast_weights(pair.left[:, :cols])
+    rows, cols = 16, 32
+    r0 = (band * rows) % (wl["H"] - rows + 1)
+    c0 = (band * cols) % (wl["W"] - cols + 1)
+    L_r, R_r = pair.left[r0:r0 + rows], pair.right[r0:r0 + rows]
+    th_rows = ocv.sad_cost_volume(L_r, R_r, wl["K"])
+    w_h, _ = ocv.contrast_weights(L_r)
+    L_c, R_c = pair.left[:, c0:c0 + cols], pair.right[:, c0:c0 + cols]
+    th_cols = ocv.sad_cost_volume(L_c, R_c, wl["K"])
+    _, w_v = ocv.contrast_weights(L_c)
     updates = 0
-    t0 = time.perf_counter()
     reps = 0
+    t0 = time.perf_counter()
     while True:
         lam = np.zeros_like(th_rows)
-        lam = odmm.half_step(th_rows, lam, w_h, np.zeros((rows - 1, wl["W"])), wl["T"], "h", gammas=wl["gammas"])
+        odmm.half_step(th_rows, lam, w_h, np.zeros((rows - 1, wl["W"])), wl["T"], "h", gammas=wl["gammas"])
         updates += th_rows.size * 4
         lam = np.zeros_like(th_cols)
         odmm.half_step(th_cols, lam, np.zeros((wl["H"], cols - 1)), w_v, wl["T"], "v", gammas=wl["gammas"])
@@ -83,11 +88,41 @@ def cpu_baseline(pair, wl, target_s):
         reps += 1
         if time.perf_counter() - t0 >= target_s:
             break
-    el = time.perf_counter() - t0
-    return {"value": updates / el, "unit": "label-node updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps}x (horizontal half-step on {rows} rows x {wl['W']} + vertical half-step on "
-                      f"{cols} columns x {wl['H']}) of the frame's cost volume, K={wl['K']}, FP64 numpy, "
-                      f"{el:.1f} s, single thread"}
+    return updates, time.perf_counter() - t0, reps
+
+
+def host_workers():
+    """Worker processes for the CPU baseline: the host's CPUs available to this process,
+    at most 16 (the CPU share of one GPU on a shared multi-GPU host)."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(pair, wl, target_s):
+    """The FP64 oracle, as it is, on a bounded sample of the same frame (horizontal
+    half-steps on bands of 16 rows, vertical half-steps on bands of 32 columns), run by
+    one process per host CPU (each on its own bands) and then by one process alone.
+    Returns label-node updates / s (4 sweeps per half-step).  Runs before the GPU is
+    initialised: the worker processes are forked copies of this one."""
+    import multiprocessing as mp
+    n = host_workers()
+    with mp.get_context("fork").Pool(n) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_band, [(pair, wl, b, target_s) for b in range(n)])
+        wall = time.perf_counter() - t0
+    single_s = max(2.0, target_s / 2)
+    u1, el1, reps1 = _oracle_band((pair, wl, 0, single_s))
+    updates = sum(r[0] for r in res)
+    reps = sum(r[2] for r in res)
+    return {"value": updates / wall, "unit": "label-node updates/s", "cores": n, "kind": "oracle",
+            "sample": f"{n} processes, each repeating (horizontal half-step on 16 rows x {wl['W']} + vertical "
+                      f"half-step on 32 columns x {wl['H']}) of its own bands of the frame, K={wl['K']}, FP64 "
+                      f"numpy, {reps} repetitions in {wall:.1f} s wall",
+            "value_single_thread": u1 / el1,
+            "sample_single_thread": f"one process, {reps1} repetitions on the first bands in {el1:.1f} s"}
 
 
 def _timed(fn, reps, torch):
@@ -250,25 +285,89 @@ def diff_extra(torch, ops, dev, n=8, W=960, H=320, K=96, n_iters=20, T=3, warps=
             "grad_finite": finite}
 
 
+def census_lr_extra(torch, ops, dev, pair, wl, tiles, reps=3):
+    """The paper's data term and its two-sided check on the bench frame: the Census
+    (5 x 5) + Hamming cost volume, FP16, of the left and the right view, then one forward
+    (Dual_MM 20 iterations + refinement) per view and the left-right check of the two
+    refined disparity maps, against the left view alone."""
+    W, H, K = wl["W"], wl["H"], wl["K"]
+    IL = torch.from_numpy(pair.left).to(dev)
+    IR = torch.from_numpy(pair.right).to(dev)
+    views = {}
+    for v in ("left", "right"):
+        c, wh, wv = ops.build_cost_volume_census(IL, IR, K, window=5, view=v, dtype=torch.float16)
+        views[v] = dict(cost=c, w_h=wh, w_v=wv, dual=torch.empty((H, W, K), dtype=torch.float32, device=dev),
+                        ws=None, rws=None, u=torch.empty((H, W), dtype=torch.float32, device=dev))
+    ops.profiler_enable(["census", "lr_check"])
+    for _ in range(reps):
+        for v in ("left", "right"):
+            ops.build_cost_volume_census(IL, IR, K, window=5, view=v, cost_out=views[v]["cost"],
+                                         w_h=views[v]["w_h"], w_v=views[v]["w_v"])
+    torch.cuda.synchronize()
+    n_c, ms_c, by_c = ops.profiler_query("census")
+    out_u = torch.empty((H, W), dtype=torch.float32, device=dev)
+
+    def forward(v):
+        d = views[v]
+        r = ops.solve_discrete(d["cost"], d["w_h"], d["w_v"], T=wl["T"], n_iters=wl["n_iters"],
+                               gammas=wl["gammas"], dual=d["dual"], workspace=d["ws"], want_minmarg=False,
+                               want_bounds=False, tile=tiles)
+        d["ws"] = r.workspace
+        if d["rws"] is None:
+            d["rws"] = torch.empty(ops.refine_workspace_bytes((H, W, K), C=wl["C"], n_warps=wl["n_warps"],
+                                                              n_iters=wl["refine_iters"]),
+                                   dtype=torch.uint8, device=dev)
+        ops.refine_continuous(d["cost"], r.labels, d["w_h"], d["w_v"], C=wl["C"], n_warps=wl["n_warps"],
+                              n_iters=wl["refine_iters"], workspace=d["rws"], u_out=d["u"])
+
+    def left_only():
+        ops.build_cost_volume_census(IL, IR, K, window=5, view="left", cost_out=views["left"]["cost"],
+                                     w_h=views["left"]["w_h"], w_v=views["left"]["w_v"])
+        forward("left")
+
+    def both():
+        for v in ("left", "right"):
+            ops.build_cost_volume_census(IL, IR, K, window=5, view=v, cost_out=views[v]["cost"],
+                                         w_h=views[v]["w_h"], w_v=views[v]["w_v"])
+            forward(v)
+        ops.lr_check(views["left"]["u"], views["right"]["u"], max_diff=1.0, invalid=-1.0, out=out_u)
+
+    ms_left = _timed(left_only, reps, torch)
+    ms_both = _timed(both, reps, torch)
+    n_l, ms_l, _ = ops.profiler_query("lr_check")
+    ops.profiler_disable()
+    kept = float((out_u >= 0).float().mean().item())
+    gbs = by_c / (ms_c * 1e-3) / 1e9
+    return {"workload": f"{W}x{H}, K={K}: Census 5x5 + Hamming cost volume (FP16) of both views, Dual_MM "
+                        f"{wl['n_iters']} its + refinement per view, left-right check (max_diff 1)",
+            "census_ms_per_view": ms_c / n_c, "census_GBps": gbs, "census_hbm_frac": gbs / HBM_PEAK_GBS,
+            "census_alg_bytes_per_view": by_c / n_c,
+            "lr_check_ms": ms_l / max(n_l, 1),
+            "forward_left_view_ms": ms_left, "forward_both_views_and_check_ms": ms_both,
+            "ratio_both_to_left": ms_both / ms_left, "kept_fraction": kept}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); there is no multi-GPU path.",
               file=sys.stderr)
         return 2
-    import torch
-    if not torch.cuda.is_available():
-        print("no GPU available", file=sys.stderr)
-        return 1
     import synth
-    import paper_1601_06274_amd as P
-    from paper_1601_06274_amd import ops
-    from paper_1601_06274_amd.traffic import source_hash
 
     wl = WORKLOAD
     W, H, K = wl["W"], wl["H"], wl["K"]
     pair = synth.stereo_pair(W, H, K, seed=wl["seed"], segments=wl["segments"], slope=wl["slope"],
                              occlusion_bands=wl["occlusion_bands"])
+    # the CPU baseline forks its worker processes, so it runs before anything touches the GPU
+    cpu = None if args.no_cpu_baseline or args.traffic_probe else cpu_baseline(pair, wl, args.cpu_seconds)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        return 1
+    import paper_1601_06274_amd as P
+    from paper_1601_06274_amd import ops
+    from paper_1601_06274_amd.traffic import source_hash
     dev = torch.device("cuda:0")
     IL = torch.from_numpy(pair.left).to(dev)
     IR = torch.from_numpy(pair.right).to(dev)
@@ -500,8 +599,10 @@ def main():
         out["batched"] = batched_extra(torch, ops, dev)
         torch.cuda.empty_cache()
         out["differentiation"] = diff_extra(torch, ops, dev)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pair, wl, args.cpu_seconds)
+        torch.cuda.empty_cache()
+        out["census_left_right"] = census_lr_extra(torch, ops, dev, pair, wl, tiles)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
     return 0
 

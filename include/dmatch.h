@@ -76,6 +76,50 @@ int dm_build_cost_volume(const float* I_left, const float* I_right, dm_shape s,
                          float* w_h, float* w_v, void* hip_stream);
 
 /* ---------------------------------------------------------------------------------
+ * Census + Hamming cost volume: the paper's data term (Sec. 3.1 "Stereo
+ * Reconstruction": the Census transform of each image on a small patch, compared by
+ * the pixel-wise Hamming distance).  The paper fixes neither the patch nor the
+ * comparison; here
+ *
+ *   census(I)(x,y) = bits [I(q_b) < I(x,y)] over the non-centre positions q_b of the
+ *                    window x.+-r, y.+-r (raster order, dy outer; clamped to the
+ *                    image), n = (2r+1)^2 - 1 bits
+ *   view DM_VIEW_LEFT:  cost[y][x][d] = min(trunc, H(cL(x,y), cR(x-d,y)) / n) if x-d >= 0
+ *   view DM_VIEW_RIGHT: cost[y][x][d] = min(trunc, H(cR(x,y), cL(x+d,y)) / n) if x+d < W
+ *   (H = number of differing bits; a match outside the image costs trunc)
+ *
+ * Each value is the correctly rounded quotient, stored as out_dtype (FP16 rounded to
+ * nearest even).  w_h / w_v (may be NULL) are the contrast weights of dm_build_cost_volume
+ * computed from the view's own image (I_left for the left view, I_right for the right).
+ * p->window: 3, 5 or 7; 0 < p->trunc <= 1 (1: no truncation); lambda_pw >= 0,
+ * contrast_sigma > 0.  Arrays are device memory owned by the caller; the call only
+ * enqueues work on hip_stream.  Errors: DM_ERR_NULL, DM_ERR_SHAPE, DM_ERR_DTYPE,
+ * DM_ERR_PARAM (window, trunc, view), DM_ERR_HIP (pending or launch error).
+ * ------------------------------------------------------------------------------- */
+enum { DM_VIEW_LEFT = 0, DM_VIEW_RIGHT = 1 };
+int dm_build_cost_volume_census(const float* I_left, const float* I_right, dm_shape s,
+                                const dm_cost_params* p, int view, dm_dtype out_dtype,
+                                void* cost_out, float* w_h, float* w_v, void* hip_stream);
+
+/* ---------------------------------------------------------------------------------
+ * Left-right consistency check (the two-sided check of Sec. 4.1 that removes the
+ * outliers of one view; Table tab:timing notes that it doubles the time, since the
+ * right view is solved as well).
+ *
+ *   r = round half up of u_left(x,y);  x' = x - r
+ *   u_out(x,y) = u_left(x,y)  if 0 <= x' < W and |u_left(x,y) - u_right(x',y)| <= max_diff
+ *              = invalid      otherwise
+ *
+ * u_left, u_right, u_out: [H][W] float32 device arrays (disparities of the left view
+ * and of the right view, the latter as produced from the DM_VIEW_RIGHT cost volume),
+ * owned by the caller; u_out must not alias the inputs.  The rounding is exact; the
+ * difference and its comparison are FP32.  W <= 2^24, W*H <= 2^31, max_diff >= 0.
+ * Errors: DM_ERR_NULL, DM_ERR_SHAPE, DM_ERR_PARAM, DM_ERR_HIP.
+ * ------------------------------------------------------------------------------- */
+int dm_lr_check(const float* u_left, const float* u_right, int W, int H, float max_diff,
+                float invalid, float* u_out, void* hip_stream);
+
+/* ---------------------------------------------------------------------------------
  * Discrete stage: Dual_MM (paper Sec. 2.3, Alg. Dual_MM; minorants App. A.3).
  *
  * Energy (Sec. 2.2, eq. energy-pairwise):
@@ -299,6 +343,8 @@ typedef enum {
     DM_PROF_RECORD_H = 12,        /* record-mode horizontal half-step: the forward's with
                                      keep_checkpoints = 2, or the backward's recompute   */
     DM_PROF_RECORD_V = 13,        /* record-mode vertical half-step (likewise)          */
+    DM_PROF_CENSUS = 14,          /* Census + Hamming cost volume (without the weights) */
+    DM_PROF_LR_CHECK = 15,        /* left-right consistency check                       */
     DM_PROF_KINDS = 16
 } dm_prof_kind;
 

@@ -11,8 +11,9 @@ streams).  Importing the package does not load the shared library; the first
 call does, and it raises if ``libdmatch.so`` has not been built.
 """
 from ._lib import DmError, lib  # noqa: F401
-from .ops import (DiscreteResult, build_cost_volume, refine_continuous, refine_continuous_backward,  # noqa: F401
-                  solve_discrete, solve_discrete_backward, tile_for)
+from .ops import (DiscreteResult, build_cost_volume, build_cost_volume_census, lr_check,  # noqa: F401
+                  refine_continuous, refine_continuous_backward, solve_discrete, solve_discrete_backward, tile_for)
 
 __all__ = ["DmError", "lib", "DiscreteResult", "solve_discrete", "solve_discrete_backward", "tile_for",
-           "refine_continuous", "refine_continuous_backward", "build_cost_volume"]
+           "refine_continuous", "refine_continuous_backward", "build_cost_volume", "build_cost_volume_census",
+           "lr_check"]

@@ -19,7 +19,7 @@ DM_MINORANT_NAIVE = 1
 
 PROF_KINDS = {"sweep_h": 0, "sweep_v": 1, "sweep_final": 2, "sweep_opt": 3, "bounds": 4, "cost_volume": 5,
               "refine_linearize": 6, "refine_iter": 7, "other": 8, "adjoint_h": 9, "adjoint_v": 10,
-              "adjoint_final": 11, "record_h": 12, "record_v": 13}
+              "adjoint_final": 11, "record_h": 12, "record_v": 13, "census": 14, "lr_check": 15}
 
 STATUS_NAMES = {
     0: "DM_OK", -1: "DM_ERR_NULL", -2: "DM_ERR_SHAPE", -3: "DM_ERR_PARAM", -4: "DM_ERR_DTYPE",
@@ -68,6 +68,10 @@ _VP = ctypes.c_void_p
 _SIGNATURES = [
     ("dm_build_cost_volume", ctypes.c_int,
      [_VP, _VP, DmShape, ctypes.POINTER(DmCostParams), ctypes.c_int, _VP, _VP, _VP, _VP]),
+    ("dm_build_cost_volume_census", ctypes.c_int,
+     [_VP, _VP, DmShape, ctypes.POINTER(DmCostParams), ctypes.c_int, ctypes.c_int, _VP, _VP, _VP, _VP]),
+    ("dm_lr_check", ctypes.c_int,
+     [_VP, _VP, ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_float, _VP, _VP]),
     ("dm_solve_discrete_workspace", ctypes.c_size_t, [DmShape, ctypes.c_int, ctypes.POINTER(DmDiscreteParams)]),
     ("dm_solve_discrete", ctypes.c_int,
      [_VP, ctypes.c_int, _VP, _VP, DmShape, ctypes.POINTER(DmDiscreteParams), _VP, _VP, _VP, _VP, _VP, _VP,

@@ -14,7 +14,7 @@ import torch
 from . import _lib as L
 
 __all__ = ["DiscreteResult", "solve_discrete", "discrete_params", "tile_for", "refine_params", "refine_continuous",
-           "build_cost_volume"]
+           "build_cost_volume", "build_cost_volume_census", "lr_check"]
 
 
 def _ptr(t):
@@ -216,6 +216,47 @@ def build_cost_volume(I_left, I_right, K, *, window=3, trunc=0.3, lambda_pw=0.1,
                                       _cost_dtype(cost_out), _ptr(cost_out), _ptr(w_h), _ptr(w_v), _stream(stream))
     L.check("dm_build_cost_volume", st)
     return cost_out, w_h, w_v
+
+
+def build_cost_volume_census(I_left, I_right, K, *, window=5, trunc=1.0, view="left", lambda_pw=0.1,
+                             contrast_sigma=0.1, dtype=torch.float32, stream=None, cost_out=None, w_h=None,
+                             w_v=None):
+    """Census + Hamming cost volume of the left or right view and the view's contrast
+    weights (dm_build_cost_volume_census)."""
+    H, W = I_left.shape
+    _check_dev("I_left", I_left, torch.float32, (H, W))
+    _check_dev("I_right", I_right, torch.float32, (H, W))
+    if view not in ("left", "right"):
+        raise ValueError(f"view must be 'left' or 'right', got {view!r}")
+    dev = I_left.device
+    if cost_out is None:
+        cost_out = torch.empty((H, W, K), dtype=dtype, device=dev)
+    if w_h is None:
+        w_h = torch.empty((H, W - 1), dtype=torch.float32, device=dev)
+    if w_v is None:
+        w_v = torch.empty((H - 1, W), dtype=torch.float32, device=dev)
+    cp = L.DmCostParams(int(window), float(trunc), float(lambda_pw), float(contrast_sigma))
+    st = L.lib().dm_build_cost_volume_census(_ptr(I_left), _ptr(I_right), L.DmShape(W, H, K), ctypes.byref(cp),
+                                             0 if view == "left" else 1, _cost_dtype(cost_out), _ptr(cost_out),
+                                             _ptr(w_h), _ptr(w_v), _stream(stream))
+    L.check("dm_build_cost_volume_census", st)
+    return cost_out, w_h, w_v
+
+
+def lr_check(u_left, u_right, *, max_diff=1.0, invalid=-1.0, stream=None, out=None):
+    """Left disparities kept where the right view agrees, `invalid` elsewhere (dm_lr_check)."""
+    H, W = u_left.shape
+    _check_dev("u_left", u_left, torch.float32, (H, W))
+    _check_dev("u_right", u_right, torch.float32, (H, W))
+    if out is None:
+        out = torch.empty_like(u_left)
+    _check_dev("out", out, torch.float32, (H, W))
+    if out.data_ptr() in (u_left.data_ptr(), u_right.data_ptr()):
+        raise ValueError("out must not alias u_left or u_right")
+    st = L.lib().dm_lr_check(_ptr(u_left), _ptr(u_right), W, H, float(max_diff), float(invalid), _ptr(out),
+                             _stream(stream))
+    L.check("dm_lr_check", st)
+    return out
 
 
 def profiler_enable(kinds=None):

@@ -152,3 +152,21 @@ def test_checkpoint_and_tape_workspace_sizes(keep, T, tile, recompute):
     body = ((1 if tb else Pb + 1) + (((1 if tb else Pb - 1)) if Pb > 1 else 0)) * vol + ((Pb + 1) * tb if tb else 0)
     body += 3 * vol + _al(H * (W - 1) * 8) + _al((H - 1) * W * 8) + _al(W * H * 4)
     assert lib.dm_solve_discrete_backward_workspace(L.DmShape(W, H, K), ctypes.byref(p)) == body
+
+
+def test_census_and_lr_check_validation():
+    lib = L.lib()
+    fake = ctypes.c_void_p(4096)  # never dereferenced: validation fails first
+    s = L.DmShape(8, 8, 4)
+    for window, trunc, view, dtype, code in [(9, 1.0, 0, 0, -3), (4, 1.0, 0, 0, -3), (5, 0.0, 0, 0, -3),
+                                             (5, 1.5, 0, 0, -3), (5, 1.0, 2, 0, -3), (5, 1.0, 0, 3, -4)]:
+        cp = L.DmCostParams(window, trunc, 0.1, 0.1)
+        assert lib.dm_build_cost_volume_census(fake, fake, s, ctypes.byref(cp), view, dtype, fake, None, None,
+                                               None) == code
+    cp = L.DmCostParams(5, 1.0, 0.1, 0.1)
+    assert lib.dm_build_cost_volume_census(fake, None, s, ctypes.byref(cp), 0, 0, fake, None, None, None) == -1
+    assert lib.dm_build_cost_volume_census(fake, fake, L.DmShape(8, 8, 0), ctypes.byref(cp), 0, 0, fake, None, None,
+                                           None) == -2
+    assert lib.dm_lr_check(fake, None, 8, 8, 1.0, -1.0, fake, None) == -1
+    assert lib.dm_lr_check(fake, fake, 0, 8, 1.0, -1.0, fake, None) == -2
+    assert lib.dm_lr_check(fake, fake, 8, 8, -1.0, -1.0, fake, None) == -3
