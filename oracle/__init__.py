@@ -13,7 +13,7 @@ itself declares independent (all rows of one half-step, all columns of the
 other); along a chain every step is taken in the paper's order.
 
 Modules
-  chain        messages, min-marginals, iterative / naive minorants (App. A.1, A.3.2)
+  chain        messages, min-marginals, iterative / naive / hierarchical minorants (App. A.1, A.3)
   dmm          dual decomposition and the Dual_MM loop (Sec. 2.3, Alg. Dual_MM)
   energy       the discrete energy and brute-force minimisation (Sec. 2.2)
   cost_volume  SAD cost volume and contrast edge weights (Sec. 2.2 "Stereo", Sec. 3.1)

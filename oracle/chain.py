@@ -26,6 +26,8 @@ __all__ = [
     "chain_energy",
     "iterative_minorant",
     "naive_minorant",
+    "hierarchical_minorant",
+    "hierarchical_split",
 ]
 
 
@@ -173,3 +175,69 @@ def naive_minorant(a: np.ndarray, w: np.ndarray, T: int) -> np.ndarray:
     a = np.asarray(a, dtype=np.float64)
     n = a.shape[1]
     return min_marginals(a, w, T, normalized=True) / float(n)
+
+
+def hierarchical_split(s: int, e: int) -> int:
+    """Split node of the segment s..e (e > s): the segment breaks at the edge (i, i+1),
+    the left part holding half of the nodes, rounded down (App. A.3.3: a chain of 32 is
+    split into two chains of 16)."""
+    return s + (e - s + 1) // 2 - 1
+
+
+def hierarchical_minorant(a: np.ndarray, w: np.ndarray, T: int) -> np.ndarray:
+    """Hierarchical minorant of chains a (App. A.3.3, Alg. Handshake and its figure).
+
+    The chain is cut at the edge (i, i+1) in its middle.  With the message into i from
+    the left part and the message into i+1 from the right part, the Handshake over that
+    edge gives the left part half of the min-marginal at i (passed to the right as the
+    message phi_ij into i+1) and bounces back, as phi_ji into i, what cannot be
+    passed.  From then on the two parts are separate chains whose boundary unaries
+    include these messages, and each is cut again in its middle; in a part, the
+    messages computed at the level above stay valid on the side whose boundary did not
+    change, and only the other side's messages are recomputed up to the new cut.  The
+    recursion ends with single nodes; node k's minorant is its unary plus the two
+    Handshake messages it received, its minimum subtracted (so h >= 0, as for the other
+    minorants here, and the remainder a - h keeps the chain optimum when the minorant
+    is exact).
+
+    Arrays: a (C, n, K), w (C, n-1); returns h with the shape of a.
+    """
+    a = np.asarray(a, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    C, n, K = a.shape
+    L = np.zeros((C, n, K))  # L[:, k]: message into k from the left, within k's current part
+    R = np.zeros((C, n, K))  # R[:, k]: message into k from the right
+
+    def handshake(i):
+        j = i + 1
+        phi_ji = message(a[:, j] + R[:, j], w[:, i], T)  # from j to i
+        m_i = L[:, i] + a[:, i] + phi_ji                  # min-marginal at i
+        phi_ij = message(m_i / 2.0 - phi_ji, w[:, i], T)  # a half of it shared to the right
+        phi_ji = message(-phi_ij, w[:, i], T)             # what cannot be shared comes back
+        R[:, i] = phi_ji
+        L[:, j] = phi_ij
+
+    def process(s, e):
+        # on entry L is valid on s..i and R on i+1..e, i the split of s..e
+        i = hierarchical_split(s, e)
+        handshake(i)
+        if i > s:
+            i2 = hierarchical_split(s, i)
+            for k in range(i, i2 + 1, -1):
+                R[:, k - 1] = message(R[:, k] + a[:, k], w[:, k - 1], T)
+            process(s, i)
+        if e > i + 1:
+            j2 = hierarchical_split(i + 1, e)
+            for k in range(i + 1, j2):
+                L[:, k + 1] = message(L[:, k] + a[:, k], w[:, k], T)
+            process(i + 1, e)
+
+    if n >= 2:
+        i = hierarchical_split(0, n - 1)
+        for k in range(0, i):
+            L[:, k + 1] = message(L[:, k] + a[:, k], w[:, k], T)
+        for k in range(n - 1, i + 1, -1):
+            R[:, k - 1] = message(R[:, k] + a[:, k], w[:, k - 1], T)
+        process(0, n - 1)
+    m = a + L + R
+    return m - m.min(axis=2, keepdims=True)

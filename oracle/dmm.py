@@ -53,6 +53,8 @@ def _minorant(a, w, T, minorant, gammas):
         return chain.iterative_minorant(a, w, T, gammas)
     if minorant == "naive":
         return chain.naive_minorant(a, w, T)
+    if minorant == "hierarchical":
+        return chain.hierarchical_minorant(a, w, T)
     raise ValueError(minorant)
 
 
