@@ -47,7 +47,7 @@ typedef enum {
 
 typedef enum { DM_F32 = 0, DM_F16 = 1 } dm_dtype;   /* storage type of the cost volume */
 
-typedef enum { DM_MINORANT_ITERATIVE = 0, DM_MINORANT_NAIVE = 1 } dm_minorant;
+typedef enum { DM_MINORANT_ITERATIVE = 0, DM_MINORANT_NAIVE = 1, DM_MINORANT_HIERARCHICAL = 2 } dm_minorant;
 
 /* Grid of W x H pixels with K labels; 1 <= W, H <= 16384, 1 <= K <= 256, and one FP32
  * volume (W*H*K*4 bytes) at most 0xFE000000 bytes: the kernels address volumes with
@@ -133,6 +133,15 @@ int dm_lr_check(const float* u_left, const float* u_right, int W, int H, float m
  * directional passes (forward first, then alternating) and steps gamma[0..max_pass-1];
  * gamma[max_pass-1] must be 1 (maximal minorant).  DM_MINORANT_NAIVE: normalized
  * min-marginals divided by the chain length (Sec. 2.3, App. A.1).
+ * DM_MINORANT_HIERARCHICAL: App. A.3.3 (Alg. Handshake): every chain is cut in its
+ * middle (the left part holding half of the nodes, rounded down), a Handshake over the
+ * cut edge passes half of the min-marginal at its left node to the right part and
+ * bounces back what cannot be passed, and each part is cut again down to single nodes;
+ * node k's minorant is its unary plus the two Handshake messages it received, minus
+ * its minimum.  Forward only (keep_checkpoints must be 0, else DM_ERR_UNSUPPORTED; no
+ * batched plans, no tile autotuning); the chain tiles then apply to the final pass
+ * only, the half-steps run one chain per wave and need a second message volume in the
+ * workspace (included in dm_solve_discrete_workspace).
  *
  * Outputs after the last half-step:
  *   labels_out  [H][W] int32: argmin over k of the normalized row min-marginals of F

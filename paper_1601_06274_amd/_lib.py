@@ -16,6 +16,7 @@ DM_F32 = 0
 DM_F16 = 1
 DM_MINORANT_ITERATIVE = 0
 DM_MINORANT_NAIVE = 1
+DM_MINORANT_HIERARCHICAL = 2
 
 PROF_KINDS = {"sweep_h": 0, "sweep_v": 1, "sweep_final": 2, "sweep_opt": 3, "bounds": 4, "cost_volume": 5,
               "refine_linearize": 6, "refine_iter": 7, "other": 8, "adjoint_h": 9, "adjoint_v": 10,

@@ -25,7 +25,7 @@ def _tiles():
 
 
 TILES = _tiles()
-UNITS = [("api.hip", [], "api"), ("dmm.hip", [], "dmm"), ("cost_volume.hip", [], "cost_volume"),
+UNITS = [("api.hip", [], "api"), ("dmm.hip", [], "dmm"), ("dmm_hier.hip", [], "dmm_hier"), ("cost_volume.hip", [], "cost_volume"),
          ("refine.hip", [], "refine"), ("batched.hip", [], "batched")]
 # largest units first so the parallel build's critical path starts early
 UNITS = [("dmm_tile.hip", [f"-DDM_TILE_G={g}", f"-DDM_TILE_L={l}", f"-DDM_TILE_PART={k}"], f"dmm_tile_{g}x{l}_{v}")

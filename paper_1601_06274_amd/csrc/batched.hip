@@ -95,7 +95,8 @@ extern "C" int dm_plan_batched(const dm_instance* inst, int n, dm_dtype cost_dty
     *plan_out = nullptr;
     DM_REQUIRE(n >= 1 && n <= 4096, DM_ERR_PARAM, "n=%d instances out of range [1, 4096]", n);
     DM_REQUIRE(cost_dtype == DM_F32 || cost_dtype == DM_F16, DM_ERR_DTYPE, "unknown cost dtype");
-    DM_REQUIRE(p->minorant == DM_MINORANT_ITERATIVE || p->minorant == DM_MINORANT_NAIVE, DM_ERR_PARAM, "minorant");
+    DM_REQUIRE(p->minorant == DM_MINORANT_ITERATIVE || p->minorant == DM_MINORANT_NAIVE, DM_ERR_UNSUPPORTED,
+               "batched plans take the iterative or the naive minorant (got %d)", p->minorant);
     for (int i = 0; i < n; ++i) {
         const dm_instance& I = inst[i];
         int st = validate_shape(I.s);

@@ -10,6 +10,7 @@
 #include <tuple>
 
 #include "dmm_adjoint.h"
+#include "dmm_hier.h"
 #include "tiles.h"
 
 namespace dm {
@@ -284,7 +285,7 @@ hipError_t launch_sweep_prof(Tile t, const SweepArgs& a, dm_dtype dt, hipStream_
 }
 
 struct WsLayout {
-    size_t msg, opt, partial, labels, ckpt, total;
+    size_t msg, msg2, opt, partial, labels, ckpt, total;  // msg2: hierarchical minorant only
     size_t vol_bytes;
     long long max_chains;
     int n_slots, n_partial;
@@ -338,6 +339,8 @@ WsLayout layout(const dm_shape& s, const dm_discrete_params& p) {
     size_t off = 0;
     L.msg = off;
     off = align_up(off + vol * sizeof(float), 256);
+    L.msg2 = off;  // messages from the right of the hierarchical minorant
+    if (p.minorant == DM_MINORANT_HIERARCHICAL) off = align_up(off + vol * sizeof(float), 256);
     L.opt = off;
     off = align_up(off + (size_t)L.n_slots * L.max_chains * sizeof(double), 256);
     L.partial = off;
@@ -367,8 +370,11 @@ int validate_params(const dm_shape& s, const dm_discrete_params* p) {
     DM_REQUIRE(p->n_half_steps >= 0 && p->n_half_steps <= 200000, DM_ERR_PARAM, "n_half_steps=%d out of range",
                p->n_half_steps);
     DM_REQUIRE(p->trunc_T >= 1, DM_ERR_PARAM, "trunc_T=%d must be >= 1", p->trunc_T);
-    DM_REQUIRE(p->minorant == DM_MINORANT_ITERATIVE || p->minorant == DM_MINORANT_NAIVE, DM_ERR_PARAM,
-               "unknown minorant %d", p->minorant);
+    DM_REQUIRE(p->minorant == DM_MINORANT_ITERATIVE || p->minorant == DM_MINORANT_NAIVE ||
+                   p->minorant == DM_MINORANT_HIERARCHICAL,
+               DM_ERR_PARAM, "unknown minorant %d", p->minorant);
+    DM_REQUIRE(p->minorant != DM_MINORANT_HIERARCHICAL || p->keep_checkpoints == 0, DM_ERR_UNSUPPORTED,
+               "the hierarchical minorant has no backward: keep_checkpoints must be 0");
     if (p->minorant == DM_MINORANT_ITERATIVE) {
         DM_REQUIRE(p->max_pass >= 1 && p->max_pass <= 8, DM_ERR_PARAM, "max_pass=%d out of range [1, 8]", p->max_pass);
         for (int i = 0; i < p->max_pass; ++i)
@@ -527,6 +533,13 @@ extern "C" int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const fl
             a.mode |= kRecordFlag;
             for (int i = 0; i <= P && i < 9; ++i) a.rec_msg[i] = slab_vol(k, 1 + i);
             for (int i = 1; i < P && i < 8; ++i) a.rec_lam[i] = slab_vol(k, P + 1 + i);
+        }
+        if (p->minorant == DM_MINORANT_HIERARCHICAL) {
+            ProfScope ps(k % 2 == 0 ? DM_PROF_SWEEP_H : DM_PROF_SWEEP_V,
+                         profiler_on() ? hier_half_step_bytes(a, cost_dtype) : 0.0, stream);
+            DM_HIP_TRY(launch_hier_half_step(a, reinterpret_cast<float*>(ws + L.msg2), cost_dtype, stream),
+                       "hierarchical half-step launch");
+            continue;
         }
         DM_HIP_TRY(launch_sweep_prof(k % 2 == 0 ? tile : tile_v, a, cost_dtype, stream), "half-step launch");
     }
@@ -903,6 +916,8 @@ extern "C" int dm_autotune_tiles(dm_shape s, dm_dtype cost_dtype, dm_discrete_pa
     DM_REQUIRE(p != nullptr, DM_ERR_NULL, "params is NULL");
     int st = validate_params(s, p);
     if (st != DM_OK) return st;
+    DM_REQUIRE(p->minorant != DM_MINORANT_HIERARCHICAL, DM_ERR_UNSUPPORTED,
+               "the hierarchical minorant uses no chain tiles");
     DM_REQUIRE(cost_dtype == DM_F32 || cost_dtype == DM_F16, DM_ERR_DTYPE, "unknown cost dtype");
     const TuneKey key{s.W, s.H, s.K, (int)cost_dtype, p->minorant, p->max_pass};
     {

@@ -54,7 +54,8 @@ def discrete_params(T=3, n_iters=10, n_half_steps=0, minorant="iterative", gamma
     p.n_iters = int(n_iters)
     p.n_half_steps = int(n_half_steps)
     p.trunc_T = int(T)
-    p.minorant = {"iterative": L.DM_MINORANT_ITERATIVE, "naive": L.DM_MINORANT_NAIVE}[minorant]
+    p.minorant = {"iterative": L.DM_MINORANT_ITERATIVE, "naive": L.DM_MINORANT_NAIVE,
+                  "hierarchical": L.DM_MINORANT_HIERARCHICAL}[minorant]
     gammas = tuple(gammas)
     p.max_pass = len(gammas)
     for i, g in enumerate(gammas[:8]):

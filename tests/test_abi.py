@@ -170,3 +170,20 @@ def test_census_and_lr_check_validation():
     assert lib.dm_lr_check(fake, None, 8, 8, 1.0, -1.0, fake, None) == -1
     assert lib.dm_lr_check(fake, fake, 0, 8, 1.0, -1.0, fake, None) == -2
     assert lib.dm_lr_check(fake, fake, 8, 8, -1.0, -1.0, fake, None) == -3
+
+
+def test_hierarchical_minorant_is_forward_only():
+    lib = L.lib()
+    from paper_1601_06274_amd import ops
+    s = L.DmShape(16, 8, 8)
+    p = ops.discrete_params(minorant="hierarchical")
+    assert lib.dm_solve_discrete_workspace(s, 0, ctypes.byref(p)) > 0
+    plain = ops.discrete_params(minorant="iterative")
+    # a second message volume
+    assert lib.dm_solve_discrete_workspace(s, 0, ctypes.byref(p)) >= \
+        lib.dm_solve_discrete_workspace(s, 0, ctypes.byref(plain)) + 16 * 8 * 8 * 4
+    pk = ops.discrete_params(minorant="hierarchical", keep_checkpoints=True)
+    assert lib.dm_solve_discrete_workspace(s, 0, ctypes.byref(pk)) == 0
+    fake = ctypes.c_void_p(4096)
+    assert lib.dm_solve_discrete(fake, 0, fake, fake, s, ctypes.byref(pk), None, None, fake, None, None, fake,
+                                 ctypes.c_size_t(1 << 30), None) == -6

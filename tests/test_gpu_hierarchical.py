@@ -1,0 +1,66 @@
+"""GPU parity of Dual_MM with the hierarchical minorant (App. A.3.3, Alg. Handshake)
+against the FP64 oracle, with the acceptance of the other minorants (labels up to ties,
+normalized min-marginals within 1e-5 relative, lower bound and trace within 1e-5
+relative, energy of the labels within 1e-9); the duals within 1e-5 of max(|ref|, S)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import energy as oenergy
+from tests.parity import cost_scale
+from tests.test_gpu_dmm import _check, _run_both
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CASES = [  # H, W, K, T, iters, cost dtype
+    (9, 13, 7, 2, 3, torch.float32),
+    (16, 33, 64, 3, 3, torch.float32),
+    (7, 50, 100, 1, 2, torch.float32),
+    (5, 64, 192, 3, 2, torch.float16),
+    (11, 12, 256, 4, 2, torch.float32),
+    (6, 1, 5, 2, 2, torch.float32),     # rows of one node
+    (1, 17, 9, 2, 2, torch.float32),    # columns of one node
+    (2, 2, 1, 1, 1, torch.float32),     # one label
+    (4, 129, 40, 3, 2, torch.float32),  # odd lengths at every level
+]
+
+
+@pytest.mark.parametrize("H,W,K,T,iters,dt", CASES)
+def test_hierarchical_matches_oracle(H, W, K, T, iters, dt):
+    theta, w_h, w_v = synth.tiny_instance(H, W, K, seed=H * 1000 + W + K, w_max=0.6)
+    name = f"hier {H}x{W}x{K} T={T}"
+    res, ref, th = _run_both(theta, w_h, w_v, T, iters, minorant="hierarchical", theta_dtype=dt, name=name)
+    _check(res, ref, th, w_h, w_v, T, name)
+    lam = res.dual.cpu().numpy()
+    scale = np.maximum(np.abs(ref.lam), cost_scale(th))
+    assert (np.abs(lam - ref.lam) / scale).max() <= 1e-5
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_hierarchical_bruteforce_3x3(seed):
+    T = 1 + seed % 2
+    theta, w_h, w_v = synth.tiny_instance(3, 3, 3, seed=seed)
+    res, ref, th = _run_both(theta, w_h, w_v, T, 3, minorant="hierarchical", name=f"hier bf{seed}")
+    emin, _ = oenergy.brute_force_min(th, w_h, w_v, T)
+    b = res.bounds.cpu().numpy()
+    assert b[0] <= emin + 1e-6 and b[1] >= emin - 1e-9
+    _check(res, ref, th, w_h, w_v, T, f"hier bf{seed}")
+
+
+def test_hierarchical_stereo_frame():
+    """A 160 x 96 stereo pair, K = 48, FP16 cost, 4 iterations (the paper's live setting
+    runs 4): parity as above, and the bound at least that of the iterative minorant."""
+    import paper_1601_06274_amd as P
+    from oracle import cost_volume as ocv
+    pair = synth.stereo_pair(160, 96, 48, seed=2200, segments=5)
+    theta = ocv.round_half(ocv.sad_cost_volume(pair.left, pair.right, 48))
+    w_h, w_v = ocv.contrast_weights(pair.left)
+    w_h, w_v = w_h.astype(np.float32), w_v.astype(np.float32)
+    res, ref, th = _run_both(theta, w_h, w_v, 3, 4, minorant="hierarchical", theta_dtype=torch.float16,
+                             name="hier stereo")
+    _check(res, ref, th, w_h, w_v, 3, "hier stereo")
+    dev = lambda a, d=torch.float32: torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=d)
+    it = P.solve_discrete(dev(theta, torch.float16), dev(w_h), dev(w_v), T=3, n_iters=4)
+    torch.cuda.synchronize()
+    print(f"[hier] LB hierarchical {res.bounds[0].item():.4f} iterative {it.bounds[0].item():.4f}", flush=True)
