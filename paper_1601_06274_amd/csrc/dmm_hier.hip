@@ -16,19 +16,27 @@
 // processed depth first from a per-wave stack in LDS.  Messages live in two HBM volumes
 // (into each node from the left and from the right), normalised by the minimum of the
 // message input; the per-node normalisation of the result makes those constants
-// irrelevant.  The message is the truncated-linear distance transform: in-lane scans
-// and a 64-lane min-plus scan with the linear distance, then the cap min v + wT.  The
-// passes prefetch the next nodes' unaries kHierPF nodes ahead.
+// irrelevant.  The message is the truncated-linear distance transform: for T - 1 <= LPL
+// the window minimum over this lane's labels and T - 1 from each neighbouring lane (DPP
+// lane shifts), else in-lane scans and a 64-lane min-plus scan with the linear
+// distance; then the cap min v + wT.  Passes prefetch the next nodes' unaries kHierPF
+// nodes ahead; a Handshake issues its four loads together.
 #include "dmm_hier.h"
 
 namespace dm {
 namespace {
 
 constexpr int kHierPF = 4;
+// Parts of at most this many nodes are finished in LDS (App. A.3.3's iteration count
+// assumes that short parts sit in fast memory).
+constexpr int kHierChunk = 16;
 
 __device__ __forceinline__ int hsplit(int s, int e) { return s + (e - s + 1) / 2 - 1; }
 
-template <int LPL, typename TT, bool HAS_THETA>
+// TW: the truncation's reach T - 1 when it is at most LPL (the window of a label then
+// spans at most the neighbouring lanes: the message is the window minimum, no scans);
+// -1: any T, by scans.
+template <int LPL, typename TT, bool HAS_THETA, int TW>
 struct HierChain {
     const TT* th;
     const float* lin;
@@ -40,6 +48,9 @@ struct HierChain {
     int K, n, lane;
     float Tf, sign;
     bool lv[LPL];
+    float* lds;      // staging of one small part
+    int* stk_big;    // part stack of the HBM level
+    int* stk_small;  // part stack inside a small part
 
     __device__ HierChain(const SweepArgs& a, float* msg_right, int chain) {
         th = static_cast<const TT*>(a.theta);
@@ -98,11 +109,31 @@ struct HierChain {
 
     // out = min_a [v(a) + wt * min(|a - b|, T)] - min v over the chain's labels; returns
     // min v.  Labels that do not exist take no part and get 0.
-    __device__ float message(const float (&vin)[LPL], float wt, float (&out)[LPL]) const {
-        float v[LPL], f[LPL], b[LPL];
+    __device__ __forceinline__ float message(const float (&vin)[LPL], float wt, float (&out)[LPL]) const {
+        float v[LPL];
 #pragma unroll
         for (int i = 0; i < LPL; ++i) v[i] = lv[i] ? vin[i] : kBig;
         const float vmin = wave_min(v);
+        const float cap = vmin + wt * Tf;
+        if constexpr (TW >= 0) {
+            // window |a - b| <= TW: this lane's labels and TW from each neighbouring lane
+            float e[LPL + 2 * (TW > 0 ? TW : 0)];
+#pragma unroll
+            for (int j = 0; j < TW; ++j) e[j] = dpp_fill<kWaveShr1>(v[LPL - TW + j], kBig);
+#pragma unroll
+            for (int i = 0; i < LPL; ++i) e[TW + i] = v[i];
+#pragma unroll
+            for (int j = 0; j < TW; ++j) e[TW + LPL + j] = dpp_fill<kWaveShl1>(v[j], kBig);
+#pragma unroll
+            for (int i = 0; i < LPL; ++i) {
+                float m = v[i];
+#pragma unroll
+                for (int d = 1; d <= TW; ++d) m = fminf(m, fminf(e[TW + i - d], e[TW + i + d]) + wt * (float)d);
+                out[i] = lv[i] ? fminf(m, cap) - vmin : 0.0f;
+            }
+            return vmin;
+        }
+        float f[LPL], b[LPL];
         f[0] = v[0];
 #pragma unroll
         for (int i = 1; i < LPL; ++i) f[i] = fminf(v[i], f[i - 1] + wt);
@@ -124,7 +155,6 @@ struct HierChain {
         float inl = __shfl_up(g, 1), inr = __shfl_down(h, 1);
         if (lane == 0) inl = kBig;
         if (lane == 63) inr = kBig;
-        const float cap = vmin + wt * Tf;
 #pragma unroll
         for (int i = 0; i < LPL; ++i) {
             const float fl = fminf(f[i], inl + wt * (float)(i + 1));
@@ -134,15 +164,61 @@ struct HierChain {
         return vmin;
     }
 
-    // Message pass over `count` nodes starting at `start` in direction dir (+1: from the
-    // left, the message of node k goes into k + 1 and is stored in msgL; -1: into k - 1,
-    // stored in msgR), carrying the message in c.  Adds the normalisation constants to opt.
-    __device__ void pass(int start, int count, int dir, float (&c)[LPL], double& opt) const {
-        if (count <= 0) return;
-        float ring[kHierPF][LPL];
+    // Where a pass or a Handshake reads unaries and messages: the HBM volumes (Glob) or a
+    // part staged in LDS (Lds: unaries, messages from the left, from the right, node
+    // index relative to the part's first node).
+    struct Glob {
+        static constexpr bool kGlobal = true;
+        const HierChain* h;
+        __device__ __forceinline__ void load_r(int k, float (&r)[LPL]) const { h->load_r(k, r); }
+        __device__ __forceinline__ void load_m(bool left, int k, float (&m)[LPL]) const { h->load_msg(left ? h->msgL : h->msgR, k, m); }
+        __device__ __forceinline__ void store_m(bool left, int k, const float (&m)[LPL]) const {
+            h->store_msg(left ? h->msgL : h->msgR, k, m);
+        }
+        __device__ __forceinline__ float w(int edge) const { return h->weight(edge); }
+    };
+    struct Lds {
+        static constexpr bool kGlobal = false;
+        const HierChain* h;
+        float* base;  // [3][kHierChunk][64 * LPL] then the part's kHierChunk - 1 edge weights
+        int s;
+        __device__ __forceinline__ float* at(int arr, int k) const {
+            return base + ((size_t)arr * kHierChunk + (k - s)) * (64 * LPL) + h->lane * LPL;
+        }
+        __device__ __forceinline__ void load_r(int k, float (&r)[LPL]) const {
+            const float* p = at(0, k);
 #pragma unroll
-        for (int q = 0; q < kHierPF; ++q)
-            if (q < count) load_r(start + dir * q, ring[q]);
+            for (int i = 0; i < LPL; ++i) r[i] = h->lv[i] ? p[i] : kBig;
+        }
+        __device__ __forceinline__ void load_m(bool left, int k, float (&m)[LPL]) const {
+            const float* p = at(left ? 1 : 2, k);
+#pragma unroll
+            for (int i = 0; i < LPL; ++i) m[i] = p[i];
+        }
+        __device__ __forceinline__ void store_m(bool left, int k, const float (&m)[LPL]) const {
+            float* p = at(left ? 1 : 2, k);
+#pragma unroll
+            for (int i = 0; i < LPL; ++i) p[i] = m[i];
+        }
+        __device__ __forceinline__ float w(int edge) const { return base[(size_t)3 * kHierChunk * (64 * LPL) + (edge - s)]; }
+    };
+
+    // Message pass over `count` nodes starting at `start` in direction dir (+1: from the
+    // left, the message of node k goes into k + 1; -1: into k - 1), carrying the message
+    // in c.  Adds the normalisation constants to opt.
+    template <class M>
+    __device__ __forceinline__ void pass(const M& mem, int start, int count, int dir, float (&c)[LPL], double& opt) const {
+        if (count <= 0) return;
+        // ring of the next nodes' unaries and the weights of their outgoing edges
+        float ring[kHierPF][LPL], rw[kHierPF];
+        const int eo = dir > 0 ? 0 : -1;  // edge of node k in the walking direction: k + eo
+#pragma unroll
+        for (int q = 0; q < kHierPF; ++q) {
+            if (q < count) {
+                mem.load_r(start + dir * q, ring[q]);
+                rw[q] = mem.w(start + dir * q + eo);
+            }
+        }
         for (int t0 = 0; t0 < count; t0 += kHierPF) {
 #pragma unroll
             for (int q = 0; q < kHierPF; ++q) {
@@ -152,9 +228,13 @@ struct HierChain {
                     float v[LPL];
 #pragma unroll
                     for (int i = 0; i < LPL; ++i) v[i] = c[i] + ring[q][i];
-                    if (t + kHierPF < count) load_r(k + dir * kHierPF, ring[q]);
-                    opt += (double)message(v, weight(dir > 0 ? k : k - 1), c);
-                    store_msg(dir > 0 ? msgL : msgR, k + dir, c);
+                    const float wt = rw[q];
+                    if (t + kHierPF < count) {
+                        mem.load_r(k + dir * kHierPF, ring[q]);
+                        rw[q] = mem.w(k + dir * kHierPF + eo);
+                    }
+                    opt += (double)message(v, wt, c);
+                    mem.store_m(dir > 0, k + dir, c);
                 }
             }
         }
@@ -164,18 +244,21 @@ struct HierChain {
     // the left and into i+1 from the right, writes the new boundary messages; returns
     // them in pji (into i) and pij (into i+1).  first: adds the chain optimum's remaining
     // terms to opt (the min-marginal at i of the whole chain).
-    __device__ void handshake(int i, float (&pji)[LPL], float (&pij)[LPL], bool first, double& opt) const {
-        float r[LPL], m[LPL], t[LPL];
-        load_r(i + 1, r);
-        load_msg(msgR, i + 1, m);
+    template <class M>
+    __device__ __forceinline__ void handshake(const M& mem, int i, float (&pji)[LPL], float (&pij)[LPL], bool first,
+                              double& opt) const {
+        float r[LPL], m[LPL], t[LPL], r0[LPL], ml[LPL];
+        // the four loads issued together
+        mem.load_r(i + 1, r);
+        mem.load_m(false, i + 1, m);
+        mem.load_r(i, r0);
+        mem.load_m(true, i, ml);
+        const float wt = mem.w(i);
 #pragma unroll
         for (int q = 0; q < LPL; ++q) t[q] = r[q] + m[q];
-        const float wt = weight(i);
         const float c0 = message(t, wt, pji);  // from i+1 to i
-        load_r(i, r);
-        load_msg(msgL, i, m);
 #pragma unroll
-        for (int q = 0; q < LPL; ++q) m[q] = lv[q] ? m[q] + r[q] + pji[q] : kBig;  // min-marginal at i
+        for (int q = 0; q < LPL; ++q) m[q] = lv[q] ? ml[q] + r0[q] + pji[q] : kBig;  // min-marginal at i
         if (first) opt += (double)c0 + (double)wave_min(m);
 #pragma unroll
         for (int q = 0; q < LPL; ++q) t[q] = 0.5f * m[q] - pji[q];
@@ -183,80 +266,153 @@ struct HierChain {
 #pragma unroll
         for (int q = 0; q < LPL; ++q) t[q] = -pij[q];
         message(t, wt, pji);  // what cannot be shared comes back
-        store_msg(msgR, i, pji);
-        store_msg(msgL, i + 1, pij);
+        mem.store_m(false, i, pji);
+        mem.store_m(true, i + 1, pij);
     }
 
-    __device__ void run(int* stk, double* opt_out) {
+    // Cuts the part s..e (length >= 2; on entry the messages from the left are valid on
+    // s..cut and those from the right on cut+1..e) and its parts depth first.  Glob:
+    // parts of at most kHierChunk nodes are handed to solve_small; Lds: down to single
+    // nodes.
+    template <class M>
+    __device__ __forceinline__ void split_parts(const M& mem, int* stk, int s0, int e0, bool& first, double& opt) const {
+        double unused = 0.0;  // the parts' normalisation constants are not the optimum's
+        float pji[LPL], pij[LPL];
+        int sp = 1;
+        stk[0] = s0;
+        stk[1] = e0;
+        while (sp > 0) {
+            --sp;
+            const int s = stk[2 * sp], e = stk[2 * sp + 1];
+            if constexpr (M::kGlobal) {
+                if (e - s + 1 <= kHierChunk) {
+                    solve_small(s, e, first, opt);
+                    first = false;
+                    continue;
+                }
+            }
+            const int i = hsplit(s, e);
+            handshake(mem, i, pji, pij, first, opt);
+            first = false;
+            if (i > s) {  // left part s..i: messages from the right, from i down to its cut
+                const int i2 = hsplit(s, i);
+                pass(mem, i, i - i2 - 1, -1, pji, unused);
+                stk[2 * sp] = s;
+                stk[2 * sp + 1] = i;
+                ++sp;
+            }
+            if (e > i + 1) {  // right part i+1..e: messages from the left, up to its cut
+                const int j2 = hsplit(i + 1, e);
+                pass(mem, i + 1, j2 - i - 1, +1, pij, unused);
+                stk[2 * sp] = i + 1;
+                stk[2 * sp + 1] = e;
+                ++sp;
+            }
+        }
+    }
+
+    // A part of at most kHierChunk nodes (length >= 2): its unaries and valid messages
+    // are staged in LDS (all loads issued together), its parts are cut down to single
+    // nodes there, and the minorant of its nodes moves the dual.
+    __device__ __forceinline__ void solve_small(int s, int e, bool first, double& opt) const {
+        const int m = e - s + 1;
+        const int cut = hsplit(s, e);
+        const Lds L{this, lds, s};
+        {
+            float rr[kHierChunk][LPL];
+#pragma unroll
+            for (int j = 0; j < kHierChunk; ++j)
+                if (j < m) load_r(s + j, rr[j]);
+#pragma unroll
+            for (int j = 0; j < kHierChunk; ++j) {
+                if (j < m) {
+                    float* p = L.at(0, s + j);
+#pragma unroll
+                    for (int i = 0; i < LPL; ++i) p[i] = rr[j][i];
+                }
+            }
+            float ew[kHierChunk - 1];
+#pragma unroll
+            for (int j = 0; j < kHierChunk - 1; ++j)
+                if (j < m - 1) ew[j] = weight(s + j);
+            float* wl = lds + (size_t)3 * kHierChunk * (64 * LPL);
+            if (lane == 0) {
+#pragma unroll
+                for (int j = 0; j < kHierChunk - 1; ++j)
+                    if (j < m - 1) wl[j] = ew[j];
+            }
+#pragma unroll
+            for (int j = 0; j < kHierChunk; ++j)
+                if (j < m) load_msg(s + j <= cut ? msgL : msgR, s + j, rr[j]);
+#pragma unroll
+            for (int j = 0; j < kHierChunk; ++j)
+                if (j < m) L.store_m(s + j <= cut, s + j, rr[j]);
+        }
+        // the dual of the part's nodes, read now to be ready at the end (the unaries of
+        // the columns are the dual itself)
+        float lam[kHierChunk][LPL];
+        if constexpr (HAS_THETA) {
+#pragma unroll
+            for (int j = 0; j < kHierChunk; ++j) {
+                if (j < m) {
+#pragma unroll
+                    for (int i = 0; i < LPL; ++i) lam[j][i] = lv[i] ? lin[el(s + j, i)] : 0.0f;
+                }
+            }
+        }
+        wave_lds_sync();
+        bool f = first;
+        split_parts(L, stk_small, s, e, f, opt);
+        wave_lds_sync();
+#pragma unroll
+        for (int j = 0; j < kHierChunk; ++j) {
+            if (j < m) {
+                float r[LPL], a[LPL], b[LPL], mm[LPL];
+                L.load_r(s + j, r);
+                L.load_m(true, s + j, a);
+                L.load_m(false, s + j, b);
+#pragma unroll
+                for (int i = 0; i < LPL; ++i) mm[i] = lv[i] ? r[i] + a[i] + b[i] : kBig;
+                const float mn = wave_min(mm);
+#pragma unroll
+                for (int i = 0; i < LPL; ++i) {
+                    if (lv[i]) {
+                        const float l0 = HAS_THETA ? lam[j][i] : r[i];
+                        lout[el(s + j, i)] = l0 + sign * (mm[i] - mn);
+                    }
+                }
+            }
+        }
+        wave_lds_sync();  // the next part reuses the LDS
+    }
+
+    __device__ __forceinline__ void run(double* opt_out) {
         double opt = 0.0;
-        float c[LPL], pji[LPL], pij[LPL];
         if (n >= 2) {
+            const Glob G{this};
+            float c[LPL];
             const int i0 = hsplit(0, n - 1);
 #pragma unroll
             for (int q = 0; q < LPL; ++q) c[q] = 0.0f;
             store_msg(msgL, 0, c);
-            pass(0, i0, +1, c, opt);
+            pass(G, 0, i0, +1, c, opt);
 #pragma unroll
             for (int q = 0; q < LPL; ++q) c[q] = 0.0f;
             store_msg(msgR, n - 1, c);
-            pass(n - 1, n - 2 - i0, -1, c, opt);
-            int sp = 0;
-            stk[0] = 0;
-            stk[1] = n - 1;
-            sp = 1;
+            pass(G, n - 1, n - 2 - i0, -1, c, opt);
             bool first = true;
-            double unused = 0.0;  // the parts' normalisation constants are not the optimum's
-            while (sp > 0) {
-                --sp;
-                const int s = stk[2 * sp], e = stk[2 * sp + 1];
-                const int i = hsplit(s, e);
-                handshake(i, pji, pij, first, opt);
-                first = false;
-                if (i > s) {  // left part s..i: messages from the right, from i down to its cut
-                    const int i2 = hsplit(s, i);
-                    pass(i, i - i2 - 1, -1, pji, unused);
-                    stk[2 * sp] = s;
-                    stk[2 * sp + 1] = i;
-                    ++sp;
-                }
-                if (e > i + 1) {  // right part i+1..e: messages from the left, up to its cut
-                    const int j2 = hsplit(i + 1, e);
-                    pass(i + 1, j2 - i - 1, +1, pij, unused);
-                    stk[2 * sp] = i + 1;
-                    stk[2 * sp + 1] = e;
-                    ++sp;
-                }
-            }
-        }
-        // the minorant: unary plus both boundary messages, normalised per node
-        float ring[kHierPF][LPL];
+            split_parts(G, stk_big, 0, n - 1, first, opt);
+        } else {
+            // one node: its minorant is its unary
+            float r[LPL];
+            load_r(0, r);
+            const float mn = wave_min(r);
+            opt = (double)mn;
 #pragma unroll
-        for (int q = 0; q < kHierPF; ++q)
-            if (q < n) load_r(q, ring[q]);
-        for (int t0 = 0; t0 < n; t0 += kHierPF) {
-#pragma unroll
-            for (int q = 0; q < kHierPF; ++q) {
-                const int k = t0 + q;
-                if (k < n) {
-                    float m[LPL], lm[LPL], rm[LPL];
-                    load_msg(msgL, k, lm);
-                    load_msg(msgR, k, rm);
-                    if (n == 1) {
-#pragma unroll
-                        for (int i = 0; i < LPL; ++i) lm[i] = rm[i] = 0.0f;
-                    }
-#pragma unroll
-                    for (int i = 0; i < LPL; ++i) m[i] = lv[i] ? ring[q][i] + lm[i] + rm[i] : kBig;
-                    if (k + kHierPF < n) load_r(k + kHierPF, ring[q]);
-                    const float mn = wave_min(m);
-                    if (n == 1) opt = (double)mn;
-#pragma unroll
-                    for (int i = 0; i < LPL; ++i) {
-                        if (lv[i]) {
-                            const long long e = el(k, i);
-                            lout[e] = lin[e] + sign * (m[i] - mn);
-                        }
-                    }
+            for (int i = 0; i < LPL; ++i) {
+                if (lv[i]) {
+                    const long long e = el(0, i);
+                    lout[e] = lin[e] + sign * (r[i] - mn);
                 }
             }
         }
@@ -264,25 +420,42 @@ struct HierChain {
     }
 };
 
-template <int LPL, typename TT, bool HAS_THETA>
+template <int LPL, typename TT, bool HAS_THETA, int TW>
 __global__ __launch_bounds__(64) void hier_chain_kernel(SweepArgs a, float* msg_right) {
-    // depth-first stack of parts: at most one more entry per level, levels <= 32
-    __shared__ int stk[2 * 64];
+    // depth-first stacks of parts: at most one more entry per level, levels <= 32
+    __shared__ int stk[2 * 2 * 64];
+    extern __shared__ float part[];  // [3][kHierChunk][64 * LPL], then kHierChunk weights
     const int chain = blockIdx.x;
-    HierChain<LPL, TT, HAS_THETA> hc(a, msg_right, chain);
-    hc.run(stk, a.opt != nullptr ? a.opt + chain : nullptr);
+    HierChain<LPL, TT, HAS_THETA, TW> hc(a, msg_right, chain);
+    hc.lds = part;
+    hc.stk_big = stk;
+    hc.stk_small = stk + 2 * 64;
+    hc.run(a.opt != nullptr ? a.opt + chain : nullptr);
+}
+
+template <int LPL, int TW>
+hipError_t launch_tw(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st) {
+    const dim3 grid((unsigned)a.n_chains), block(64);
+    const size_t lds = ((size_t)3 * kHierChunk * 64 * LPL + kHierChunk) * sizeof(float);
+    if (a.theta == nullptr)
+        hipLaunchKernelGGL((hier_chain_kernel<LPL, float, false, TW>), grid, block, lds, st, a, msg_right);
+    else if (dt == DM_F16)
+        hipLaunchKernelGGL((hier_chain_kernel<LPL, _Float16, true, TW>), grid, block, lds, st, a, msg_right);
+    else
+        hipLaunchKernelGGL((hier_chain_kernel<LPL, float, true, TW>), grid, block, lds, st, a, msg_right);
+    return hipGetLastError();
 }
 
 template <int LPL>
 hipError_t launch_lpl(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st) {
-    const dim3 grid((unsigned)a.n_chains), block(64);
-    if (a.theta == nullptr)
-        hipLaunchKernelGGL((hier_chain_kernel<LPL, float, false>), grid, block, 0, st, a, msg_right);
-    else if (dt == DM_F16)
-        hipLaunchKernelGGL((hier_chain_kernel<LPL, _Float16, true>), grid, block, 0, st, a, msg_right);
-    else
-        hipLaunchKernelGGL((hier_chain_kernel<LPL, float, true>), grid, block, 0, st, a, msg_right);
-    return hipGetLastError();
+    const int tw = a.T - 1;
+    if (tw == 0) return launch_tw<LPL, 0>(a, msg_right, dt, st);
+    if (tw == 1) return launch_tw<LPL, 1>(a, msg_right, dt, st);
+    if constexpr (LPL >= 2)
+        if (tw == 2) return launch_tw<LPL, 2>(a, msg_right, dt, st);
+    if constexpr (LPL >= 3)
+        if (tw == 3) return launch_tw<LPL, 3>(a, msg_right, dt, st);
+    return launch_tw<LPL, -1>(a, msg_right, dt, st);
 }
 
 }  // namespace
