@@ -285,6 +285,32 @@ def diff_extra(torch, ops, dev, n=8, W=960, H=320, K=96, n_iters=20, T=3, warps=
             "grad_finite": finite}
 
 
+def hierarchical_extra(torch, ops, cost, w_h, w_v, wl, tiles, reps=2):
+    """The hierarchical minorant (Handshake) against the iterative one on the bench frame's
+    FP16 cost volume: Dual_MM forward time, per half-step kernel time and algorithmic
+    GB/s, and the lower bound and labeling energy reached after 4 (the paper's live
+    setting) and 20 dual iterations."""
+    res = {}
+    for mino in ("iterative", "hierarchical"):
+        for its in (4, wl["n_iters"]):
+            kw = dict(T=wl["T"], n_iters=its, minorant=mino, gammas=wl["gammas"], tile=tiles)
+            r = ops.solve_discrete(cost, w_h, w_v, **kw)
+            ws = r.workspace
+            torch.cuda.synchronize()
+            ops.profiler_enable(["sweep_h", "sweep_v"])
+            ms = _timed(lambda: ops.solve_discrete(cost, w_h, w_v, workspace=ws, **kw), reps, torch)
+            nh, msh, bh = ops.profiler_query("sweep_h")
+            nv, msv, bv = ops.profiler_query("sweep_v")
+            ops.profiler_disable()
+            b = r.bounds.cpu().numpy()
+            res[f"{mino}_{its}_its"] = {
+                "forward_ms": ms, "lower_bound": float(b[0]), "energy": float(b[1]),
+                "half_step_h_ms": msh / nh, "half_step_v_ms": msv / nv,
+                "half_step_h_GBps": bh / (msh * 1e-3) / 1e9, "half_step_v_GBps": bv / (msv * 1e-3) / 1e9}
+    return {"workload": f"{wl['W']}x{wl['H']}, K={wl['K']}, FP16 SAD cost, T={wl['T']}: Dual_MM with the iterative "
+                        f"and the hierarchical minorant (labels, bounds, no refinement)", **res}
+
+
 def census_lr_extra(torch, ops, dev, pair, wl, tiles, reps=3):
     """The paper's data term and its two-sided check on the bench frame: the Census
     (5 x 5) + Hamming cost volume, FP16, of the left and the right view, then one forward
@@ -601,6 +627,8 @@ def main():
         out["differentiation"] = diff_extra(torch, ops, dev)
         torch.cuda.empty_cache()
         out["census_left_right"] = census_lr_extra(torch, ops, dev, pair, wl, tiles)
+        torch.cuda.empty_cache()
+        out["hierarchical_minorant"] = hierarchical_extra(torch, ops, cost, w_h, w_v, wl, tiles)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -27,17 +27,21 @@ namespace dm {
 namespace {
 
 constexpr int kHierPF = 4;
-// Parts of at most this many nodes are finished in LDS (App. A.3.3's iteration count
-// assumes that short parts sit in fast memory).
-constexpr int kHierChunk = 16;
+// Parts of at most this many nodes are finished in LDS by one wave (App. A.3.3's
+// iteration count assumes that short parts sit in fast memory): 16 with one wave per
+// chain, 8 with several (their LDS regions share the workgroup's).
+constexpr int hier_chunk(int nw) { return nw > 1 ? 8 : 16; }
 
 __device__ __forceinline__ int hsplit(int s, int e) { return s + (e - s + 1) / 2 - 1; }
 
 // TW: the truncation's reach T - 1 when it is at most LPL (the window of a label then
 // spans at most the neighbouring lanes: the message is the window minimum, no scans);
 // -1: any T, by scans.
-template <int LPL, typename TT, bool HAS_THETA, int TW>
+// NW: waves per chain (a workgroup of NW waves).
+template <int LPL, typename TT, bool HAS_THETA, int TW, int NW>
 struct HierChain {
+    static constexpr int kHierChunk = hier_chunk(NW);
+    static constexpr int kLdsFloats = 3 * kHierChunk * 64 * LPL + kHierChunk;  // per wave
     const TT* th;
     const float* lin;
     float* lout;
@@ -45,12 +49,11 @@ struct HierChain {
     float* msgR;  // message into a node from the right
     const float* w;
     long long px0, npx, w0, wn;
-    int K, n, lane;
+    int K, n, lane, wv;
     float Tf, sign;
     bool lv[LPL];
-    float* lds;      // staging of one small part
-    int* stk_big;    // part stack of the HBM level
-    int* stk_small;  // part stack inside a small part
+    float* lds;      // this wave's staging of one small part
+    int* stk_small;  // this wave's part stack inside a small part
 
     __device__ HierChain(const SweepArgs& a, float* msg_right, int chain) {
         th = static_cast<const TT*>(a.theta);
@@ -65,7 +68,8 @@ struct HierChain {
         wn = a.w_node;
         K = a.K;
         n = a.n;
-        lane = (int)threadIdx.x;
+        lane = (int)threadIdx.x & 63;
+        wv = (int)threadIdx.x >> 6;
         Tf = (float)a.T;
         sign = a.sign;
 #pragma unroll
@@ -271,9 +275,8 @@ struct HierChain {
     }
 
     // Cuts the part s..e (length >= 2; on entry the messages from the left are valid on
-    // s..cut and those from the right on cut+1..e) and its parts depth first.  Glob:
-    // parts of at most kHierChunk nodes are handed to solve_small; Lds: down to single
-    // nodes.
+    // s..cut and those from the right on cut+1..e) and its parts depth first, down to
+    // single nodes.
     template <class M>
     __device__ __forceinline__ void split_parts(const M& mem, int* stk, int s0, int e0, bool& first, double& opt) const {
         double unused = 0.0;  // the parts' normalisation constants are not the optimum's
@@ -284,13 +287,6 @@ struct HierChain {
         while (sp > 0) {
             --sp;
             const int s = stk[2 * sp], e = stk[2 * sp + 1];
-            if constexpr (M::kGlobal) {
-                if (e - s + 1 <= kHierChunk) {
-                    solve_small(s, e, first, opt);
-                    first = false;
-                    continue;
-                }
-            }
             const int i = hsplit(s, e);
             handshake(mem, i, pji, pij, first, opt);
             first = false;
@@ -386,23 +382,83 @@ struct HierChain {
         wave_lds_sync();  // the next part reuses the LDS
     }
 
-    __device__ __forceinline__ void run(double* opt_out) {
+    // The part at `depth` with index p (its path from the whole chain: bit depth-1-d of
+    // p chooses the right part at depth d); false if an ancestor was at most
+    // kHierChunk long (finished in LDS, not cut further).
+    __device__ __forceinline__ bool part_at(int depth, int p, int& s, int& e) const {
+        s = 0;
+        e = n - 1;
+        for (int d = depth - 1; d >= 0; --d) {
+            if (e - s + 1 <= kHierChunk) return false;
+            const int i = hsplit(s, e);
+            if ((p >> d) & 1)
+                s = i + 1;
+            else
+                e = i;
+        }
+        return true;
+    }
+
+    // Level order: at each depth, first the cuts of the parts (Handshakes; parts of at
+    // most kHierChunk nodes are finished in LDS instead), then the messages of their two
+    // parts up to the parts' own cuts, the work spread over the workgroup's waves with a
+    // barrier after each step.  The whole chain's optimum is measured by the level-0
+    // passes (waves 0 and 1) and the first cut (wave 0).
+    __device__ __forceinline__ void run(double* opt_out, double* opt_share) {
         double opt = 0.0;
         if (n >= 2) {
             const Glob G{this};
-            float c[LPL];
             const int i0 = hsplit(0, n - 1);
+            float c[LPL];
+            if (wv == 0) {
 #pragma unroll
-            for (int q = 0; q < LPL; ++q) c[q] = 0.0f;
-            store_msg(msgL, 0, c);
-            pass(G, 0, i0, +1, c, opt);
+                for (int q = 0; q < LPL; ++q) c[q] = 0.0f;
+                store_msg(msgL, 0, c);
+                pass(G, 0, i0, +1, c, opt);
+            }
+            if (wv == (NW > 1 ? 1 : 0)) {
 #pragma unroll
-            for (int q = 0; q < LPL; ++q) c[q] = 0.0f;
-            store_msg(msgR, n - 1, c);
-            pass(G, n - 1, n - 2 - i0, -1, c, opt);
-            bool first = true;
-            split_parts(G, stk_big, 0, n - 1, first, opt);
-        } else {
+                for (int q = 0; q < LPL; ++q) c[q] = 0.0f;
+                store_msg(msgR, n - 1, c);
+                pass(G, n - 1, n - 2 - i0, -1, c, opt);
+            }
+            __syncthreads();
+            int maxlen = n;  // longest part at this depth
+            for (int depth = 0;; ++depth) {
+                const int np = 1 << depth;
+                for (int p = wv; p < np; p += NW) {
+                    int s0, e0;
+                    if (!part_at(depth, p, s0, e0)) continue;
+                    if (e0 - s0 + 1 <= kHierChunk) {
+                        solve_small(s0, e0, depth == 0, opt);
+                    } else {
+                        float pji[LPL], pij[LPL];
+                        handshake(G, hsplit(s0, e0), pji, pij, depth == 0, opt);
+                    }
+                }
+                __syncthreads();
+                if (maxlen <= kHierChunk) break;
+                // item 2p: the left part's messages from the right, from the cut down to
+                // its own cut; 2p + 1: the right part's from the left, up to its cut
+                for (int q = wv; q < 2 * np; q += NW) {
+                    int s0, e0;
+                    if (!part_at(depth, q >> 1, s0, e0) || e0 - s0 + 1 <= kHierChunk) continue;
+                    const int i = hsplit(s0, e0);
+                    double unused = 0.0;  // the parts' normalisation constants are not the optimum's
+                    if ((q & 1) == 0) {
+                        if (i > s0) {
+                            load_msg(msgR, i, c);
+                            pass(G, i, i - hsplit(s0, i) - 1, -1, c, unused);
+                        }
+                    } else if (e0 > i + 1) {
+                        load_msg(msgL, i + 1, c);
+                        pass(G, i + 1, hsplit(i + 1, e0) - i - 1, +1, c, unused);
+                    }
+                }
+                __syncthreads();
+                maxlen = (maxlen + 1) / 2;
+            }
+        } else if (wv == 0) {
             // one node: its minorant is its unary
             float r[LPL];
             load_r(0, r);
@@ -416,34 +472,46 @@ struct HierChain {
                 }
             }
         }
-        if (opt_out != nullptr && lane == 0) *opt_out = opt;
+        if constexpr (NW > 1) {
+            if (wv == 1 && lane == 0) *opt_share = opt;
+            __syncthreads();
+            if (wv == 0) opt += *opt_share;
+        }
+        if (opt_out != nullptr && wv == 0 && lane == 0) *opt_out = opt;
     }
 };
 
-template <int LPL, typename TT, bool HAS_THETA, int TW>
-__global__ __launch_bounds__(64) void hier_chain_kernel(SweepArgs a, float* msg_right) {
-    // depth-first stacks of parts: at most one more entry per level, levels <= 32
-    __shared__ int stk[2 * 2 * 64];
-    extern __shared__ float part[];  // [3][kHierChunk][64 * LPL], then kHierChunk weights
+template <int LPL, typename TT, bool HAS_THETA, int TW, int NW>
+__global__ __launch_bounds__(64 * NW) void hier_chain_kernel(SweepArgs a, float* msg_right) {
+    using HC = HierChain<LPL, TT, HAS_THETA, TW, NW>;
+    __shared__ int stk[NW][2 * 64];  // each wave's part stack (depth <= 32)
+    __shared__ double opt_share[1];
+    extern __shared__ float part[];  // per wave: [3][chunk][64 * LPL], then chunk weights
     const int chain = blockIdx.x;
-    HierChain<LPL, TT, HAS_THETA, TW> hc(a, msg_right, chain);
-    hc.lds = part;
-    hc.stk_big = stk;
-    hc.stk_small = stk + 2 * 64;
-    hc.run(a.opt != nullptr ? a.opt + chain : nullptr);
+    HC hc(a, msg_right, chain);
+    hc.lds = part + (size_t)hc.wv * HC::kLdsFloats;
+    hc.stk_small = stk[hc.wv];
+    hc.run(a.opt != nullptr ? a.opt + chain : nullptr, opt_share);
 }
 
+template <int LPL, int TW, int NW>
+hipError_t launch_nw(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st) {
+    const dim3 grid((unsigned)a.n_chains), block(64 * NW);
+    const size_t lds = (size_t)NW * HierChain<LPL, float, false, TW, NW>::kLdsFloats * sizeof(float);
+    if (a.theta == nullptr)
+        hipLaunchKernelGGL((hier_chain_kernel<LPL, float, false, TW, NW>), grid, block, lds, st, a, msg_right);
+    else if (dt == DM_F16)
+        hipLaunchKernelGGL((hier_chain_kernel<LPL, _Float16, true, TW, NW>), grid, block, lds, st, a, msg_right);
+    else
+        hipLaunchKernelGGL((hier_chain_kernel<LPL, float, true, TW, NW>), grid, block, lds, st, a, msg_right);
+    return hipGetLastError();
+}
+
+// Several waves per chain when the chains alone leave most SIMDs idle (1024 SIMDs).
 template <int LPL, int TW>
 hipError_t launch_tw(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st) {
-    const dim3 grid((unsigned)a.n_chains), block(64);
-    const size_t lds = ((size_t)3 * kHierChunk * 64 * LPL + kHierChunk) * sizeof(float);
-    if (a.theta == nullptr)
-        hipLaunchKernelGGL((hier_chain_kernel<LPL, float, false, TW>), grid, block, lds, st, a, msg_right);
-    else if (dt == DM_F16)
-        hipLaunchKernelGGL((hier_chain_kernel<LPL, _Float16, true, TW>), grid, block, lds, st, a, msg_right);
-    else
-        hipLaunchKernelGGL((hier_chain_kernel<LPL, float, true, TW>), grid, block, lds, st, a, msg_right);
-    return hipGetLastError();
+    if (a.n_chains <= 512 && a.n >= 64) return launch_nw<LPL, TW, 4>(a, msg_right, dt, st);
+    return launch_nw<LPL, TW, 1>(a, msg_right, dt, st);
 }
 
 template <int LPL>
