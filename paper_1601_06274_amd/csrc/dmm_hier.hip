@@ -28,9 +28,9 @@ namespace {
 
 constexpr int kHierPF = 4;
 // Parts of at most this many nodes are finished in LDS by one wave (App. A.3.3's
-// iteration count assumes that short parts sit in fast memory): 16 with one wave per
-// chain, 8 with several (their LDS regions share the workgroup's).
-constexpr int hier_chunk(int nw) { return nw > 1 ? 8 : 16; }
+// iteration count assumes that short parts sit in fast memory); 8 keeps a wave's
+// staging at 18.4 KB for K = 192, so every column chain of a frame stays resident.
+constexpr int hier_chunk(int) { return 8; }
 
 __device__ __forceinline__ int hsplit(int s, int e) { return s + (e - s + 1) / 2 - 1; }
 
