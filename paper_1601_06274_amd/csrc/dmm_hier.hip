@@ -20,13 +20,14 @@
 // the window minimum over this lane's labels and T - 1 from each neighbouring lane (DPP
 // lane shifts), else in-lane scans and a 64-lane min-plus scan with the linear
 // distance; then the cap min v + wT.  Passes prefetch the next nodes' unaries kHierPF
-// nodes ahead; a Handshake issues its four loads together.
+// nodes ahead (with the weights of their edges); a Handshake issues its four loads
+// together.
 #include "dmm_hier.h"
 
 namespace dm {
 namespace {
 
-constexpr int kHierPF = 4;
+constexpr int kHierPF = 8;
 // Parts of at most this many nodes are finished in LDS by one wave (App. A.3.3's
 // iteration count assumes that short parts sit in fast memory); 8 keeps a wave's
 // staging at 18.4 KB for K = 192, so every column chain of a frame stays resident.
@@ -250,26 +251,39 @@ struct HierChain {
     // terms to opt (the min-marginal at i of the whole chain).
     template <class M>
     __device__ __forceinline__ void handshake(const M& mem, int i, float (&pji)[LPL], float (&pij)[LPL], bool first,
-                              double& opt) const {
-        float r[LPL], m[LPL], t[LPL], r0[LPL], ml[LPL];
-        // the four loads issued together
-        mem.load_r(i + 1, r);
-        mem.load_m(false, i + 1, m);
-        mem.load_r(i, r0);
-        mem.load_m(true, i, ml);
-        const float wt = mem.w(i);
+                                              double& opt) const {
+        HsIn in;
+        hs_load(mem, i, in);  // the four loads issued together
+        hs_compute(mem, i, in, pji, pij, first, opt);
+    }
+    // A Handshake's inputs: the unaries of i and i+1, the messages into them, the weight.
+    struct HsIn {
+        float r1[LPL], mr[LPL], r0[LPL], ml[LPL], wt;
+    };
+    template <class M>
+    __device__ __forceinline__ void hs_load(const M& mem, int i, HsIn& in) const {
+        mem.load_r(i + 1, in.r1);
+        mem.load_m(false, i + 1, in.mr);
+        mem.load_r(i, in.r0);
+        mem.load_m(true, i, in.ml);
+        in.wt = mem.w(i);
+    }
+    template <class M>
+    __device__ __forceinline__ void hs_compute(const M& mem, int i, const HsIn& in, float (&pji)[LPL],
+                                               float (&pij)[LPL], bool first, double& opt) const {
+        float m[LPL], t[LPL];
 #pragma unroll
-        for (int q = 0; q < LPL; ++q) t[q] = r[q] + m[q];
-        const float c0 = message(t, wt, pji);  // from i+1 to i
+        for (int q = 0; q < LPL; ++q) t[q] = in.r1[q] + in.mr[q];
+        const float c0 = message(t, in.wt, pji);  // from i+1 to i
 #pragma unroll
-        for (int q = 0; q < LPL; ++q) m[q] = lv[q] ? ml[q] + r0[q] + pji[q] : kBig;  // min-marginal at i
+        for (int q = 0; q < LPL; ++q) m[q] = lv[q] ? in.ml[q] + in.r0[q] + pji[q] : kBig;  // min-marginal at i
         if (first) opt += (double)c0 + (double)wave_min(m);
 #pragma unroll
         for (int q = 0; q < LPL; ++q) t[q] = 0.5f * m[q] - pji[q];
-        message(t, wt, pij);  // a half of it shared to the right
+        message(t, in.wt, pij);  // a half of it shared to the right
 #pragma unroll
         for (int q = 0; q < LPL; ++q) t[q] = -pij[q];
-        message(t, wt, pji);  // what cannot be shared comes back
+        message(t, in.wt, pji);  // what cannot be shared comes back
         mem.store_m(false, i, pji);
         mem.store_m(true, i + 1, pij);
     }
@@ -314,39 +328,18 @@ struct HierChain {
         const int m = e - s + 1;
         const int cut = hsplit(s, e);
         const Lds L{this, lds, s};
-        {
-            float rr[kHierChunk][LPL];
+        // every load of the part issued before the first LDS store: one memory latency
+        float rr[kHierChunk][LPL], mg[kHierChunk][LPL], ew[kHierChunk - 1];
+        float lam[kHierChunk][LPL];  // the dual, for the end (the columns' unaries are the dual)
 #pragma unroll
-            for (int j = 0; j < kHierChunk; ++j)
-                if (j < m) load_r(s + j, rr[j]);
+        for (int j = 0; j < kHierChunk; ++j)
+            if (j < m) load_r(s + j, rr[j]);
 #pragma unroll
-            for (int j = 0; j < kHierChunk; ++j) {
-                if (j < m) {
-                    float* p = L.at(0, s + j);
+        for (int j = 0; j < kHierChunk - 1; ++j)
+            if (j < m - 1) ew[j] = weight(s + j);
 #pragma unroll
-                    for (int i = 0; i < LPL; ++i) p[i] = rr[j][i];
-                }
-            }
-            float ew[kHierChunk - 1];
-#pragma unroll
-            for (int j = 0; j < kHierChunk - 1; ++j)
-                if (j < m - 1) ew[j] = weight(s + j);
-            float* wl = lds + (size_t)3 * kHierChunk * (64 * LPL);
-            if (lane == 0) {
-#pragma unroll
-                for (int j = 0; j < kHierChunk - 1; ++j)
-                    if (j < m - 1) wl[j] = ew[j];
-            }
-#pragma unroll
-            for (int j = 0; j < kHierChunk; ++j)
-                if (j < m) load_msg(s + j <= cut ? msgL : msgR, s + j, rr[j]);
-#pragma unroll
-            for (int j = 0; j < kHierChunk; ++j)
-                if (j < m) L.store_m(s + j <= cut, s + j, rr[j]);
-        }
-        // the dual of the part's nodes, read now to be ready at the end (the unaries of
-        // the columns are the dual itself)
-        float lam[kHierChunk][LPL];
+        for (int j = 0; j < kHierChunk; ++j)
+            if (j < m) load_msg(s + j <= cut ? msgL : msgR, s + j, mg[j]);
         if constexpr (HAS_THETA) {
 #pragma unroll
             for (int j = 0; j < kHierChunk; ++j) {
@@ -355,6 +348,21 @@ struct HierChain {
                     for (int i = 0; i < LPL; ++i) lam[j][i] = lv[i] ? lin[el(s + j, i)] : 0.0f;
                 }
             }
+        }
+#pragma unroll
+        for (int j = 0; j < kHierChunk; ++j) {
+            if (j < m) {
+                float* p = L.at(0, s + j);
+#pragma unroll
+                for (int i = 0; i < LPL; ++i) p[i] = rr[j][i];
+                L.store_m(s + j <= cut, s + j, mg[j]);
+            }
+        }
+        float* wl = lds + (size_t)3 * kHierChunk * (64 * LPL);
+        if (lane == 0) {
+#pragma unroll
+            for (int j = 0; j < kHierChunk - 1; ++j)
+                if (j < m - 1) wl[j] = ew[j];
         }
         wave_lds_sync();
         bool f = first;
@@ -426,14 +434,33 @@ struct HierChain {
             int maxlen = n;  // longest part at this depth
             for (int depth = 0;; ++depth) {
                 const int np = 1 << depth;
+                // this wave's cuts, the inputs of the next one loaded while the current
+                // one is computed
+                HsIn nxt;
+                int nxt_i = -1;
+                auto next_big = [&](int from) -> int {  // the next part of this wave longer than the chunk
+                    for (int p = from; p < np; p += NW) {
+                        int s1, e1;
+                        if (part_at(depth, p, s1, e1) && e1 - s1 + 1 > kHierChunk) return hsplit(s1, e1);
+                    }
+                    return -1;
+                };
+                if (maxlen > kHierChunk) {
+                    nxt_i = next_big(wv);
+                    if (nxt_i >= 0) hs_load(G, nxt_i, nxt);
+                }
                 for (int p = wv; p < np; p += NW) {
                     int s0, e0;
                     if (!part_at(depth, p, s0, e0)) continue;
                     if (e0 - s0 + 1 <= kHierChunk) {
                         solve_small(s0, e0, depth == 0, opt);
                     } else {
+                        const int i = nxt_i;  // == hsplit(s0, e0): parts are visited in order
+                        const HsIn cur = nxt;
+                        nxt_i = next_big(p + NW);
+                        if (nxt_i >= 0) hs_load(G, nxt_i, nxt);
                         float pji[LPL], pij[LPL];
-                        handshake(G, hsplit(s0, e0), pji, pij, depth == 0, opt);
+                        hs_compute(G, i, cur, pji, pij, depth == 0, opt);
                     }
                 }
                 __syncthreads();
