@@ -140,8 +140,8 @@ int dm_lr_check(const float* u_left, const float* u_right, int W, int H, float m
  * node k's minorant is its unary plus the two Handshake messages it received, minus
  * its minimum.  Forward only (keep_checkpoints must be 0, else DM_ERR_UNSUPPORTED; no
  * batched plans, no tile autotuning); the chain tiles then apply to the final pass
- * only, the half-steps run one chain per wave and need a second message volume in the
- * workspace (included in dm_solve_discrete_workspace).
+ * only, the half-steps run one workgroup of one or four waves per chain and need a
+ * second message volume in the workspace (included in dm_solve_discrete_workspace).
  *
  * Outputs after the last half-step:
  *   labels_out  [H][W] int32: argmin over k of the normalized row min-marginals of F

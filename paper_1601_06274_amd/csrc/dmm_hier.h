@@ -8,7 +8,7 @@ namespace dm {
 // One half-step of the family described by `a` (as for the chain sweeps: theta null for
 // the vertical family, lam_in / lam the dual read and written, opt the per-chain optima)
 // with the hierarchical minorant.  a.msg and msg_right are two message volumes of the
-// volume's size.  One wave per chain; K <= 256.
+// volume's size.  A workgroup of one or four waves per chain; K <= 256.
 hipError_t launch_hier_half_step(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st);
 
 // Algorithmic HBM bytes of one such launch.

@@ -23,6 +23,9 @@ CASES = [  # H, W, K, T, iters, cost dtype
     (1, 17, 9, 2, 2, torch.float32),    # columns of one node
     (2, 2, 1, 1, 1, torch.float32),     # one label
     (4, 129, 40, 3, 2, torch.float32),  # odd lengths at every level
+    (3, 70, 256, 3, 2, torch.float32),  # four waves per chain with 4 labels per lane
+    (5, 90, 200, 4, 2, torch.float16),
+    (2, 300, 130, 2, 1, torch.float32),  # several depths above the LDS parts
 ]
 
 
