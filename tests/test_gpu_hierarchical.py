@@ -67,3 +67,36 @@ def test_hierarchical_stereo_frame():
     it = P.solve_discrete(dev(theta, torch.float16), dev(w_h), dev(w_v), T=3, n_iters=4)
     torch.cuda.synchronize()
     print(f"[hier] LB hierarchical {res.bounds[0].item():.4f} iterative {it.bounds[0].item():.4f}", flush=True)
+
+
+def test_hierarchical_full_frame_sampled_chains():
+    """1242 x 375, K = 192, FP16 cost (four waves per row chain, seven cut levels above
+    the LDS parts): the GPU's dual after one row half-step and after the following
+    column half-step, on sampled rows and columns, against the oracle's hierarchical
+    minorant of those chains taken from the GPU's dual before the half-step."""
+    import paper_1601_06274_amd as P
+    from oracle import chain, cost_volume as ocv
+    W, H, K, T = 1242, 375, 192, 3
+    pair = synth.stereo_pair(W, H, K, seed=3000, segments=16, slope=0.08, occlusion_bands=4)
+    dev = lambda a, d=torch.float32: torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=d)
+    cost, w_h, w_v = P.build_cost_volume(dev(pair.left), dev(pair.right), K, dtype=torch.float16)
+    th = cost.float().cpu().numpy().astype(np.float64)
+    wh = w_h.cpu().numpy().astype(np.float64)
+    wv = w_v.cpu().numpy().astype(np.float64)
+    S = cost_scale(th)
+    print("[case] hierarchical full frame, one row and one column half-step", flush=True)
+    r1 = P.solve_discrete(cost, w_h, w_v, T=T, n_half_steps=1, minorant="hierarchical")
+    r2 = P.solve_discrete(cost, w_h, w_v, T=T, n_half_steps=2, minorant="hierarchical")
+    torch.cuda.synchronize()
+    lam1 = r1.dual.cpu().numpy().astype(np.float64)
+    lam2 = r2.dual.cpu().numpy().astype(np.float64)
+    rows = [0, 187, 374]
+    h = chain.hierarchical_minorant(th[rows], wh[rows], T)  # rows start from lambda = 0
+    err = np.abs(lam1[rows] - h) / np.maximum(np.abs(h), S)
+    cols = [0, 621, 1241]
+    a = np.transpose(lam1[:, cols], (1, 0, 2))  # column chains: unaries lambda
+    g = chain.hierarchical_minorant(a, wv[:, cols].T, T)
+    ref2 = a - g
+    err2 = np.abs(np.transpose(lam2[:, cols], (1, 0, 2)) - ref2) / np.maximum(np.abs(ref2), S)
+    print(f"[hier] full frame rows {err.max():.3e} columns {err2.max():.3e}", flush=True)
+    assert err.max() <= 1e-5 and err2.max() <= 1e-5
