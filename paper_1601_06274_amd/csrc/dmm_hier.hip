@@ -214,33 +214,45 @@ struct HierChain {
     template <class M>
     __device__ __forceinline__ void pass(const M& mem, int start, int count, int dir, float (&c)[LPL], double& opt) const {
         if (count <= 0) return;
-        // ring of the next nodes' unaries and the weights of their outgoing edges
+        // ring of the next nodes' unaries and the weights of their outgoing edges; the
+        // loads go unconditionally to a node of the pass (clamped to its last), so the
+        // full blocks have no branches and the waits stay exact
         float ring[kHierPF][LPL], rw[kHierPF];
         const int eo = dir > 0 ? 0 : -1;  // edge of node k in the walking direction: k + eo
+        auto node_of = [&](int t) { return start + dir * (t < count ? t : count - 1); };
 #pragma unroll
         for (int q = 0; q < kHierPF; ++q) {
-            if (q < count) {
-                mem.load_r(start + dir * q, ring[q]);
-                rw[q] = mem.w(start + dir * q + eo);
-            }
+            const int k = node_of(q);
+            mem.load_r(k, ring[q]);
+            rw[q] = mem.w(k + eo);
         }
-        for (int t0 = 0; t0 < count; t0 += kHierPF) {
+        int t0 = 0;
+        for (; t0 + kHierPF <= count; t0 += kHierPF) {
 #pragma unroll
             for (int q = 0; q < kHierPF; ++q) {
                 const int t = t0 + q;
-                if (t < count) {
-                    const int k = start + dir * t;
-                    float v[LPL];
+                const int k = start + dir * t;
+                float v[LPL];
 #pragma unroll
-                    for (int i = 0; i < LPL; ++i) v[i] = c[i] + ring[q][i];
-                    const float wt = rw[q];
-                    if (t + kHierPF < count) {
-                        mem.load_r(k + dir * kHierPF, ring[q]);
-                        rw[q] = mem.w(k + dir * kHierPF + eo);
-                    }
-                    opt += (double)message(v, wt, c);
-                    mem.store_m(dir > 0, k + dir, c);
-                }
+                for (int i = 0; i < LPL; ++i) v[i] = c[i] + ring[q][i];
+                const float wt = rw[q];
+                const int kn = node_of(t + kHierPF);
+                mem.load_r(kn, ring[q]);
+                rw[q] = mem.w(kn + eo);
+                opt += (double)message(v, wt, c);
+                mem.store_m(dir > 0, k + dir, c);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kHierPF; ++q) {
+            const int t = t0 + q;
+            if (t < count) {
+                const int k = start + dir * t;
+                float v[LPL];
+#pragma unroll
+                for (int i = 0; i < LPL; ++i) v[i] = c[i] + ring[q][i];
+                opt += (double)message(v, rw[q], c);
+                mem.store_m(dir > 0, k + dir, c);
             }
         }
     }
