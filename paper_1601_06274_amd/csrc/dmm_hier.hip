@@ -173,17 +173,17 @@ struct HierChain {
     // part staged in LDS (Lds: unaries, messages from the left, from the right, node
     // index relative to the part's first node).
     struct Glob {
-        static constexpr bool kGlobal = true;
         const HierChain* h;
         __device__ __forceinline__ void load_r(int k, float (&r)[LPL]) const { h->load_r(k, r); }
-        __device__ __forceinline__ void load_m(bool left, int k, float (&m)[LPL]) const { h->load_msg(left ? h->msgL : h->msgR, k, m); }
+        __device__ __forceinline__ void load_m(bool left, int k, float (&m)[LPL]) const {
+            h->load_msg(left ? h->msgL : h->msgR, k, m);
+        }
         __device__ __forceinline__ void store_m(bool left, int k, const float (&m)[LPL]) const {
             h->store_msg(left ? h->msgL : h->msgR, k, m);
         }
         __device__ __forceinline__ float w(int edge) const { return h->weight(edge); }
     };
     struct Lds {
-        static constexpr bool kGlobal = false;
         const HierChain* h;
         float* base;  // [3][kHierChunk][64 * LPL] then the part's kHierChunk - 1 edge weights
         int s;
@@ -205,7 +205,9 @@ struct HierChain {
 #pragma unroll
             for (int i = 0; i < LPL; ++i) p[i] = m[i];
         }
-        __device__ __forceinline__ float w(int edge) const { return base[(size_t)3 * kHierChunk * (64 * LPL) + (edge - s)]; }
+        __device__ __forceinline__ float w(int edge) const {
+            return base[(size_t)3 * kHierChunk * (64 * LPL) + (edge - s)];
+        }
     };
 
     // Message pass over `count` nodes starting at `start` in direction dir (+1: from the
