@@ -22,8 +22,8 @@ the comparison, the normalisation nor the check's rule; the readings taken here:
     left-right check: a left pixel with disparity u_L is kept iff its match
     x' = x - round(u_L) (round half up) lies in the image and
     |u_L(x, y) - u_R(x', y)| <= max_diff; otherwise it gets `invalid`.  The
-    disparities are FP32 values and the difference and comparison are taken in FP32
-    (the precision of the GPU path), so both sides keep the same pixels.
+    difference and the comparison are taken in FP64 (exact for FP32 disparities of
+    the same magnitude), i.e. the plain definition.
 
 The right view's edge weights are the contrast weights of the right image.
 """
@@ -85,15 +85,14 @@ def census_cost_volume(I_left, I_right, K: int, window: int = 5, trunc: float = 
 
 def lr_check(u_left, u_right, max_diff: float = 1.0, invalid: float = -1.0) -> np.ndarray:
     """Left disparities kept where the right view agrees (see the module text)."""
-    uL = np.asarray(u_left, np.float32)
-    uR = np.asarray(u_right, np.float32)
+    uL = np.asarray(u_left, np.float64)
+    uR = np.asarray(u_right, np.float64)
     H, W = uL.shape
-    md = np.float32(max_diff)
+    md = float(max_diff)
     out = np.full((H, W), float(invalid))
     for y in range(H):
         for x in range(W):
-            # an FP32 value plus 0.5 is exact in float64: floor gives round half up
-            xr = x - int(np.floor(np.float64(uL[y, x]) + 0.5))
+            xr = x - int(np.floor(uL[y, x] + 0.5))  # round half up
             if 0 <= xr < W and abs(uL[y, x] - uR[y, xr]) <= md:
-                out[y, x] = float(uL[y, x])
+                out[y, x] = uL[y, x]
     return out

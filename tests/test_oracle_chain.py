@@ -117,3 +117,100 @@ def test_naive_minorant_is_minorant(n, K, T):
     assert np.all(hx <= e - e.min() + 1e-9)
     mm = np.array([[e[xs[:, j] == k].min() for k in range(K)] for j in range(n)])
     np.testing.assert_allclose(h, (mm - mm.min(axis=1, keepdims=True)) / n, atol=1e-12)
+
+
+# ---------------------------------------------------------------- Alg. Iterative Minorant, step by step
+#
+# A 3-node chain with 2 labels, Potts (T = 1), w = 2 on both edges, unaries (label 0, label 1):
+#   node 0: (1, 4)   node 1: (0, 2)   node 2: (0, 3)
+# f(x) = sum_j a_j(x_j) + 2 [x0 != x1] + 2 [x1 != x2].  All eight labelings (x0 x1 x2):
+#   000: 1  001: 6  010: 7  011: 8  100: 6  101: 11  110: 8  111: 9
+# Alg. Iterative Minorant (App. A.3.2) with gamma = (1/4, 1): pass 1 visits nodes 0, 1, 2 (the
+# chain in its given order), pass 2 the reversed chain 2, 1, 0.  At each node the min-marginal of
+# the current remainder f - h is taken (normalized to minimum 0) and the fraction gamma_s of it
+# is moved into h_j:
+#   pass 1, node 0: m = (1, 6) -> (0, 5);   h0 += (0, 5/4)
+#           node 1: remainder 100: 19/4, 101: 39/4, 110: 27/4, 111: 31/4, others as above;
+#                   m = (1, 27/4) -> (0, 23/4); h1 += (0, 23/16)
+#           node 2: remainder 010: 89/16, 110: 85/16, 011: 105/16, 111: 101/16;
+#                   m = (1, 6) -> (0, 5);   h2 += (0, 5/4)
+#   pass 2, node 2: remainder 001: 19/4, 101: 17/2, 011: 85/16, 111: 81/16;
+#                   m = (1, 19/4) -> (0, 15/4); h2 += (0, 15/4)
+#           node 1: remainder 011: 25/16, 111: 21/16, 001: 1;
+#                   m = (1, 21/16) -> (0, 5/16); h1 += (0, 5/16)
+#           node 0: m = (1, 1) -> (0, 0)
+#   h = [(0, 5/4), (0, 7/4), (0, 5)]
+# With gamma = (1/4, 1/4, 1) (a third pass in the original order) the same steps give
+#   h = [(0, 115/32), (0, 71/32), (0, 35/16)].
+# Visiting the reversed chain first would give the mirror images [(0, 5), (0, 7/4), (0, 5/4)] and
+# [(0, 35/16), (0, 71/32), (0, 115/32)]: the pass order matters here, so these values pin it.
+PIN_A = np.array([[1.0, 4.0], [0.0, 2.0], [0.0, 3.0]])
+PIN_W = np.array([2.0, 2.0])
+PIN_H = {
+    (0.25, 1.0): np.array([[0, 5 / 4], [0, 7 / 4], [0, 5]]),
+    (0.25, 0.25, 1.0): np.array([[0, 115 / 32], [0, 71 / 32], [0, 35 / 16]]),
+}
+
+
+def _iterative_by_enumeration(a, w, T, gammas, first_forward=True):
+    """Alg. Iterative Minorant with every min-marginal taken from its definition (App. A.1:
+    the minimum of the remainder over all labelings through (j, k)), by enumeration."""
+    n, K = a.shape
+    r = a.astype(np.float64).copy()
+    h = np.zeros_like(r)
+    for s, g in enumerate(gammas):
+        forward = (s % 2 == 0) == first_forward
+        for j in (range(n) if forward else range(n - 1, -1, -1)):
+            xs, e = _enumerate_chain(r, w, T)
+            m = np.array([e[xs[:, j] == k].min() for k in range(K)])
+            d = g * (m - m.min())
+            r[j] -= d
+            h[j] += d
+    return h
+
+
+@pytest.mark.parametrize("gammas", list(PIN_H))
+def test_iterative_minorant_hand_worked(gammas):
+    """The oracle reproduces the hand-worked steps exactly (dyadic values, exact in FP64)."""
+    h = chain.iterative_minorant(PIN_A[None], PIN_W[None], 1, gammas)[0]
+    np.testing.assert_array_equal(h, PIN_H[gammas])
+    # the enumeration form of the algorithm agrees, and visiting the reversed chain first
+    # does not: the pin discriminates the pass order
+    np.testing.assert_array_equal(_iterative_by_enumeration(PIN_A, PIN_W, 1, gammas), PIN_H[gammas])
+    back = _iterative_by_enumeration(PIN_A, PIN_W, 1, gammas, first_forward=False)
+    np.testing.assert_array_equal(back, PIN_H[gammas][::-1])
+    assert not np.array_equal(back, PIN_H[gammas])
+
+
+@pytest.mark.parametrize("n,K,T", [(2, 3, 1), (3, 3, 2), (4, 2, 1), (4, 3, 3), (5, 3, 2)])
+@pytest.mark.parametrize("gammas", [(0.25, 1.0), (0.25, 0.25, 1.0), (0.5, 0.25, 0.75, 1.0)])
+def test_iterative_minorant_equals_enumeration_form(n, K, T, gammas):
+    """Message recursion (the oracle) vs min-marginals by enumeration, on random chains."""
+    g = np.random.default_rng(11 * n + 5 * K + T + len(gammas))
+    for _ in range(3):
+        a = np.round(g.random((n, K)) * 8) / 2
+        w = np.round(g.random(n - 1) * 6) / 4
+        h = chain.iterative_minorant(a[None], w[None], T, gammas)[0]
+        np.testing.assert_allclose(h, _iterative_by_enumeration(a, w, T, gammas), rtol=0, atol=1e-12)
+
+
+ITERATIVE_MUTATIONS = {
+    "reversed chain first": ("order = range(n)\n        else:\n            order = range(n - 1, -1, -1)",
+                             "order = range(n - 1, -1, -1)\n        else:\n            order = range(n)"),
+    "gamma schedule reversed": ("for s, g in enumerate(gammas):", "for s, g in enumerate(tuple(gammas)[::-1]):"),
+    "message from the unmodified unary": ("L[:, j + 1] = message(L[:, j] + r[:, j]",
+                                          "L[:, j + 1] = message(L[:, j] + a[:, j]"),
+    "min-marginal not normalized": ("d = g * (m - m.min(axis=1, keepdims=True))", "d = g * m"),
+}
+
+
+@pytest.mark.parametrize("name", list(ITERATIVE_MUTATIONS))
+def test_iterative_minorant_pin_catches_mutation(name):
+    """Each planted mistake in a copy of the oracle fails the hand-worked pin."""
+    from tests.mutation import mutated
+    mut = mutated(chain, ITERATIVE_MUTATIONS[name])
+    failed = 0
+    for gammas, want in PIN_H.items():
+        h = mut.iterative_minorant(PIN_A[None], PIN_W[None], 1, gammas)[0]
+        failed += not np.array_equal(h, want)
+    assert failed >= 1, f"mutation '{name}' passes the pin"

@@ -167,3 +167,133 @@ def test_convex_case_reaches_lp_optimum():
         gh, gv = refine.grad_op(uu)
         return data + (w_h * np.abs(gh)).sum() + (w_v * np.abs(gv)).sum()
     assert obj(u) == pytest.approx(lp.fun, abs=1e-4)
+
+
+# ---------------------------------------------------------------- NL-PDHG, step by step
+#
+# A 1 x 3 grid (two horizontal edges), K = 8 labels, labels x = (1, 1, 5), C = 2, eps = 1,
+# delta = 0, h = 1, tau = sigma = 1/4, w = (1/2, 1).  The costs give the slopes of the two-slope
+# model (Sec. 3.1) s_L = D(x) - D(x-1), s_R = D(x+1) - D(x):
+#   pixel 0: (s_L, s_R) = (-1, 2)   pixel 1: (-1/2, 1/4)   pixel 2: (-1, 2)
+# (Au)_e = u_i - u_j, A^T y = (y0, y1 - y0, -y1).  R_- has alpha = 0, beta = C + delta - eps*delta
+# = 2, so its conjugate prox (eq. pprox, step tau) is a soft threshold by tau*2 = 1/2 clamped to
+# [-w, w]; R_+ has alpha = 1, beta = 0: a clamp to [-w, w].  One iteration (eq. cont_iterates):
+#   u+ = prox_{tau D~}(u - tau A^T (p - q)),  q+ = prox(q + tau A u),  p+ = prox(p + sigma A(2u+ - u)).
+# Iteration 1 (p = q = 0, u = u0 = (1, 1, 5)):
+#   u_hat = u; every pixel lies in its dead zone [u0 + tau s_L, u0 + tau s_R]  ->  u+ = (1, 1, 5)
+#   Au = (0, -4): q_hat = (0, -1) -> q = (0, -1/2);  p_hat = (0, -1) -> p = (0, -1)
+# Iteration 2:
+#   p - q = (0, -1/2), A^T(p - q) = (0, -1/2, 1/2), u_hat = (1, 9/8, 39/8)
+#   pixel 1: 9/8 > u0 + tau s_R = 17/16 -> 9/8 - 1/16 = 17/16;  pixel 2: 39/8 in [19/4, 11/2] -> 5
+#   u+ = (1, 17/16, 5)
+#   q_hat = q + tau A u (the iterate before the step, Au = (0, -4)) = (0, -3/2) -> q = (0, -1)
+#   2u+ - u = (1, 9/8, 5), A(.) = (-1/8, -31/8), p_hat = (-1/32, -1 - 31/32) -> p = (-1/32, -1)
+PDHG_THETA = np.full((1, 3, 8), 5.0)
+PDHG_THETA[0, 0, :3] = (2.0, 1.0, 3.0)
+PDHG_THETA[0, 1, :3] = (1.5, 1.0, 1.25)
+PDHG_THETA[0, 2, 4:7] = (2.0, 1.0, 3.0)
+PDHG_LABELS = np.array([[1, 1, 5]])
+PDHG_WH = np.array([[0.5, 1.0]])
+PDHG_WV = np.zeros((0, 3))
+PDHG_WANT = dict(u=np.array([[1.0, 17 / 16, 5.0]]), qh=np.array([[0.0, -1.0]]), ph=np.array([[-1 / 32, -1.0]]))
+
+
+def _pdhg_two_iterations(mod):
+    P = mod.RefineParams(C=2.0, eps=1.0, delta=0.0, h=1.0, tau=0.25, sigma=0.25, n_warps=1, n_iters=2)
+    u, st = mod.refine_continuous(PDHG_THETA, PDHG_WH, PDHG_WV, PDHG_LABELS, P, return_state=True)
+    return dict(u=u, qh=st["qh"], ph=st["ph"])
+
+
+def test_pdhg_two_iterations_by_hand():
+    """Two iterations from the labels, with the R_- (q) branch active on the edge across the
+    step: every value is dyadic, so FP64 reproduces the hand computation exactly."""
+    sL, sR = refine.linearize(PDHG_THETA, PDHG_LABELS.astype(np.float64), 1.0)
+    np.testing.assert_array_equal(sL, [[-1.0, -0.5, -1.0]])
+    np.testing.assert_array_equal(sR, [[2.0, 0.25, 2.0]])
+    got = _pdhg_two_iterations(refine)
+    for k, want in PDHG_WANT.items():
+        np.testing.assert_array_equal(got[k], want, err_msg=k)
+
+
+PDHG_MUTATIONS = {
+    "q step with the wrong sign": [("qh = prox_conj(qh + P.tau * gh", "qh = prox_conj(qh - P.tau * gh"),
+                                   ("qv = prox_conj(qv + P.tau * gv", "qv = prox_conj(qv - P.tau * gv")],
+    "q step at u+ instead of u": [("gh, gv = grad_op(u)\n", "gh, gv = grad_op(u_new)\n")],
+    "p step at u+ instead of 2u+ - u": [("grad_op(2.0 * u_new - u)", "grad_op(u_new)")],
+    "A^T applied to p + q": [("grad_op_T(ph - qh, pv - qv", "grad_op_T(ph + qh, pv + qv")],
+    "R_- threshold without the step": [("qh = prox_conj(qh + P.tau * gh, w_h, 0.0, beta_minus, P.tau)",
+                                        "qh = prox_conj(qh + P.tau * gh, w_h, 0.0, beta_minus, 1.0)")],
+}
+
+
+@pytest.mark.parametrize("name", list(PDHG_MUTATIONS))
+def test_pdhg_pin_catches_mutation(name):
+    from tests.mutation import mutated
+    got = _pdhg_two_iterations(mutated(refine, *PDHG_MUTATIONS[name]))
+    assert any(not np.array_equal(got[k], v) for k, v in PDHG_WANT.items()), f"mutation '{name}' passes the pin"
+
+
+def _criticality_violation(theta, w_h, w_v, labels, u, st, C, h=1.0):
+    """Largest violation of the first-order conditions of min D~(u) + R_+(Au) - R_-(Au) at a
+    fixed point (u, p, q) of the iteration, with eps = 1, delta = 0 (so R_+ = w|t| and
+    R_- = w max(0, |t| - C)):  p in dR_+(Au), q in dR_-(Au), -A^T(p - q) in dD~(u) + N_box(u)."""
+    K = theta.shape[2]
+    u0 = labels.astype(np.float64)
+    sL, sR = refine.linearize(theta, u0, h)
+    lo, hi = np.maximum(u0 - h, 0.0), np.minimum(u0 + h, K - 1.0)
+    viol = 0.0
+    tol = 1e-9
+    for t, p, q, w in ((refine.grad_op(u)[0], st["ph"], st["qh"], w_h), (refine.grad_op(u)[1], st["pv"], st["qv"], w_v)):
+        a = np.abs(t)
+        sgn = np.sign(t)
+        # p in w * d|t|
+        viol = max(viol, float(np.max(np.where(a > tol, np.abs(p - w * sgn), np.maximum(np.abs(p) - w, 0.0)), initial=0)))
+        # q in w * d max(0, |t| - C): 0 inside, w sign(t) outside, between on the boundary
+        inside = a < C - tol
+        outside = a > C + tol
+        qv = np.where(inside, np.abs(q), np.where(outside, np.abs(q - w * sgn),
+                                                   np.maximum(np.maximum(-q * sgn, q * sgn - w), 0.0)))
+        viol = max(viol, float(np.max(qv, initial=0)))
+    g = -refine.grad_op_T(st["ph"] - st["qh"], st["pv"] - st["qv"], u.shape)
+    # subdifferential of the two-slope model plus the box's normal cone, as an interval [gl, gu]
+    gl = np.where(u > u0 + tol, sR, sL)
+    gu = np.where(u < u0 - tol, sL, sR)
+    gu = np.where(u >= hi - tol, np.inf, gu)
+    gl = np.where(u <= lo + tol, -np.inf, gl)
+    viol = max(viol, float(np.max(np.maximum(np.maximum(gl - g, g - gu), 0.0))))
+    return viol
+
+
+def _step_instance(seed=0):
+    """3 x 4 grid, K = 10: two flat halves 5 labels apart (edges across the step keep |Au| > C),
+    convex piecewise-linear costs with small random slopes, weights U[0.2, 0.6]."""
+    g = np.random.default_rng(seed)
+    H, W, K = 3, 4, 10
+    x = np.where(np.arange(W)[None, :] < 2, 2, 7) + g.integers(0, 2, (H, W))
+    sl = g.uniform(0.02, 0.2, (H, W, 1))
+    sr = g.uniform(0.02, 0.2, (H, W, 1))
+    d = np.arange(K)[None, None, :] - x[:, :, None]
+    theta = np.where(d < 0, -d * sl, d * sr)
+    return theta, g.uniform(0.2, 0.6, (H, W - 1)), g.uniform(0.2, 0.6, (H - 1, W)), x
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_pdhg_fixed_point_is_critical(seed):
+    """Non-convex case (C = 2): the iteration reaches a fixed point that satisfies the
+    first-order conditions of the DC problem (Sec. 2.4); with the q step's sign flipped it
+    does not."""
+    from tests.mutation import mutated
+    theta, w_h, w_v, x = _step_instance(seed)
+    bad = mutated(refine, *PDHG_MUTATIONS["q step with the wrong sign"])
+    for mod, ok in ((refine, True), (bad, False)):
+        P = mod.RefineParams(C=2.0, tau=0.25, sigma=0.25, n_warps=1, n_iters=800)
+        u, st = mod.refine_continuous(theta, w_h, w_v, x, P, return_state=True)
+        P.n_iters += 1
+        u1, st1 = mod.refine_continuous(theta, w_h, w_v, x, P, return_state=True)
+        residual = max(float(np.abs(u1 - u).max()), *(float(np.abs(st1[k] - st[k]).max()) for k in st))
+        v = _criticality_violation(theta, w_h, w_v, x, u, st, 2.0)
+        if ok:
+            assert residual <= 1e-12 and v <= 1e-9, (residual, v)
+            assert np.abs(refine.grad_op(u)[0]).max() > 2.0  # the truncation is active somewhere
+        else:
+            assert residual > 1e-12 or v > 1e-3, "sign-flipped q step passes the criticality check"
