@@ -213,7 +213,11 @@ int dm_autotune_tiles(dm_shape s, dm_dtype cost_dtype, dm_discrete_params* p, vo
  * the exact derivative of the piecewise-linear Dual_MM map as computed: minimisations
  * route the adjoint to the selected candidate, lowest label on exact ties).
  * Loss inputs: grad_minmarg [H][W][K] = dL/d(normalized row min-marginals) (may be NULL)
- * and grad_lb = dL/d(lower bound).  A half-step leaves its own family's chain optima
+ * and grad_bounds, a device double[2] = {dL/dLB, dL/dE} matching bounds_out of the forward
+ * (may be NULL: both 0; it is read on the device, so the call never waits for it).
+ * E(labels) depends on the cost and the weights only through its terms at the output
+ * labeling (the labels are piecewise constant): dE/dcost is the one-hot of the labels and
+ * dE/dw the truncated label distance of each edge.  A half-step leaves its own family's chain optima
  * unchanged as functions of the inputs (the subtracted minorant vanishes on the optimal
  * labeling) but leaves that family's min-marginals tied; so the bound's derivative is the
  * one-hot of the optimal labelings of the family of the last half-step taken at the dual
@@ -234,7 +238,7 @@ int dm_autotune_tiles(dm_shape s, dm_dtype cost_dtype, dm_discrete_params* p, vo
  * FP64 edge accumulators. */
 size_t dm_solve_discrete_backward_workspace(dm_shape s, const dm_discrete_params* p);
 
-int dm_solve_discrete_backward(const float* grad_minmarg, double grad_lb, const void* cost,
+int dm_solve_discrete_backward(const float* grad_minmarg, const double* grad_bounds, const void* cost,
                                dm_dtype cost_dtype, const float* w_h, const float* w_v, dm_shape s,
                                const dm_discrete_params* p, const float* dual,
                                const void* fwd_workspace, size_t fwd_workspace_bytes,

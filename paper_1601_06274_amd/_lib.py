@@ -81,7 +81,7 @@ _SIGNATURES = [
     ("dm_autotune_tiles", ctypes.c_int, [DmShape, ctypes.c_int, ctypes.POINTER(DmDiscreteParams), _VP]),
     ("dm_solve_discrete_backward_workspace", ctypes.c_size_t, [DmShape, ctypes.POINTER(DmDiscreteParams)]),
     ("dm_solve_discrete_backward", ctypes.c_int,
-     [_VP, ctypes.c_double, _VP, ctypes.c_int, _VP, _VP, DmShape, ctypes.POINTER(DmDiscreteParams), _VP, _VP,
+     [_VP, _VP, _VP, ctypes.c_int, _VP, _VP, DmShape, ctypes.POINTER(DmDiscreteParams), _VP, _VP,
       ctypes.c_size_t, _VP, _VP, _VP, ctypes.c_int, _VP, ctypes.c_size_t, _VP]),
     ("dm_refine_continuous_workspace", ctypes.c_size_t, [DmShape, ctypes.POINTER(DmRefineParams)]),
     ("dm_refine_continuous", ctypes.c_int,

@@ -38,10 +38,14 @@ class DiscreteFn(torch.autograd.Function):
         kw = {k: v for k, v in ctx.kw.items()
               if k in ("T", "n_iters", "n_half_steps", "minorant", "gammas", "tile", "keep_checkpoints",
                        "recompute_selections")}
-        glb = 0.0 if g_lb is None else float(g_lb.sum().item())
+        # the bound gradient stays on the device (no host synchronisation in the backward)
+        gb = None
+        if g_lb is not None:
+            gb = torch.zeros(2, dtype=torch.float64, device=cost.device)
+            gb[0:1] = g_lb.to(torch.float64).sum(0, keepdim=True)
         gm = None if g_mm is None else g_mm.contiguous().to(torch.float32)
         gc, gwh, gwv = ops.solve_discrete_backward(cost.detach(), w_h.detach().contiguous(), w_v.detach().contiguous(),
-                                                   res.dual, res.workspace, grad_minmarg=gm, grad_lb=glb, **kw)
+                                                   res.dual, res.workspace, grad_minmarg=gm, grad_bounds=gb, **kw)
         return gc.to(cost.dtype), gwh, gwv, None
 
 

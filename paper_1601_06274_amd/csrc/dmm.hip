@@ -39,8 +39,9 @@ __global__ void copy_f32_kernel(const float* __restrict__ a, float* __restrict__
 // chain optimum with respect to its unaries is the one-hot of its (unique) optimal
 // labeling `lab`, and with respect to an edge weight the truncated distance of the two
 // labels.  Rows have unaries cost - lambda (cost gets +g, dual -g), columns lambda (+g).
-__global__ void lb_inject_kernel(const int* __restrict__ lab, int W, int H, int K, int T, double g, int rows,
-                                 float* __restrict__ lbar, float* __restrict__ gcost, double* __restrict__ gw) {
+__global__ void lb_inject_kernel(const int* __restrict__ lab, int W, int H, int K, int T, const double* __restrict__ gp,
+                                 int rows, float* __restrict__ lbar, float* __restrict__ gcost, double* __restrict__ gw) {
+    const double g = gp[0];
     const long long n = (long long)W * H;
     for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
         const int l = min(max(lab[p], 0), K - 1);
@@ -58,6 +59,29 @@ __global__ void lb_inject_kernel(const int* __restrict__ lab, int W, int H, int 
                 const int d = abs(l - min(max(lab[p + W], 0), K - 1));
                 gw[p] += g * (double)(d < T ? d : T);
             }
+        }
+    }
+}
+
+// Adjoint of the energy of the output labeling, E(x) = sum_i cost_i(x_i) + sum_edges w rho(x_i - x_j):
+// the labels are piecewise constant in the inputs, so dE/dcost is the one-hot of x and
+// dE/dw the truncated label distance of each edge.
+__global__ void energy_adjoint_kernel(const int* __restrict__ lab, int W, int H, int K, int T,
+                                      const double* __restrict__ gp, float* __restrict__ gcost,
+                                      double* __restrict__ gwh, double* __restrict__ gwv) {
+    const double g = gp[1];
+    const long long n = (long long)W * H;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
+        const int l = min(max(lab[p], 0), K - 1);
+        const int x = (int)(p % W), y = (int)(p / W);
+        gcost[p * K + l] += (float)g;
+        if (x + 1 < W) {
+            const int d = abs(l - min(max(lab[p + 1], 0), K - 1));
+            gwh[(long long)y * (W - 1) + x] += g * (double)(d < T ? d : T);
+        }
+        if (y + 1 < H) {
+            const int d = abs(l - min(max(lab[p + W], 0), K - 1));
+            gwv[p] += g * (double)(d < T ? d : T);
         }
     }
 }
@@ -635,7 +659,7 @@ extern "C" size_t dm_solve_discrete_backward_workspace(dm_shape s, const dm_disc
     return bwd_layout(s, *p).total;
 }
 
-extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad_lb, const void* cost,
+extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, const double* grad_bounds, const void* cost,
                                           dm_dtype cost_dtype, const float* w_h, const float* w_v, dm_shape s,
                                           const dm_discrete_params* p, const float* dual, const void* fwd_workspace,
                                           size_t fwd_workspace_bytes, float* grad_cost, float* grad_w_h,
@@ -780,7 +804,9 @@ extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad
     // family X of the last half-step contributes the one-hot of its optimum at the dual
     // before that half-step; the other family at the final dual.
     const int lb_last = S >= 1 ? ((S - 1) % 2 == 0 ? 0 : 1) : -1;  // 0 rows, 1 columns, -1 none
-    auto lb_inject = [&](bool rows_family, const float* lam_k) -> int {
+    // optimal labels of one family's chains at a dual (argmin of the normalized
+    // min-marginals, lowest label on ties) into `lab`
+    auto labels_at = [&](bool rows_family, const float* lam_k) -> int {
         SweepArgs a = rows_family ? rows : cols;
         a.mode = kModeFinal;
         a.lam = const_cast<float*>(lam_k);
@@ -790,8 +816,13 @@ extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad
         a.labels = lab;
         a.opt = nullptr;
         DM_HIP_TRY(launch_sweep(rows_family ? tile : tile_v, a, cost_dtype, stream), "optimum labels");
-        hipLaunchKernelGGL(lb_inject_kernel, dim3(1024), dim3(256), 0, stream, lab, s.W, s.H, s.K, p->trunc_T, grad_lb,
-                           rows_family ? 1 : 0, lbar, grad_cost, rows_family ? gwh : gwv);
+        return DM_OK;
+    };
+    auto lb_inject = [&](bool rows_family, const float* lam_k) -> int {
+        const int st_l = labels_at(rows_family, lam_k);
+        if (st_l != DM_OK) return st_l;
+        hipLaunchKernelGGL(lb_inject_kernel, dim3(1024), dim3(256), 0, stream, lab, s.W, s.H, s.K, p->trunc_T,
+                           grad_bounds, rows_family ? 1 : 0, lbar, grad_cost, rows_family ? gwh : gwv);
         DM_HIP_TRY(hipGetLastError(), "bound adjoint");
         return DM_OK;
     };
@@ -808,12 +839,20 @@ extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad
         b.mode = kModeFinal;
         b.lam0 = dual;
         b.grad_mm = grad_minmarg;
-        b.g_lb = lb_last == 0 ? 0.0 : grad_lb;
+        b.g_lb = lb_last == 0 ? nullptr : grad_bounds;
         ProfScope ps(DM_PROF_ADJOINT_FINAL, profiler_on() ? adjoint_bytes(b, cost_dtype) : 0.0, stream);
         DM_HIP_TRY(launch_adjoint(tile, b, cost_dtype, stream), "final adjoint");
+        // dL/dE(labels): the output labels are the row family's optimal labels at the final dual
+        if (grad_bounds != nullptr) {
+            st = labels_at(true, dual);
+            if (st != DM_OK) return st;
+            hipLaunchKernelGGL(energy_adjoint_kernel, dim3(1024), dim3(256), 0, stream, lab, s.W, s.H, s.K,
+                               p->trunc_T, grad_bounds, grad_cost, gwh, gwv);
+            DM_HIP_TRY(hipGetLastError(), "energy adjoint");
+        }
     }
     // 2. column part of dL/dLB at the final dual
-    if (grad_lb != 0.0 && lb_last != 1) {
+    if (grad_bounds != nullptr && lb_last != 1) {
         st = lb_inject(false, dual);
         if (st != DM_OK) return st;
     }
@@ -853,7 +892,7 @@ extern "C" int dm_solve_discrete_backward(const float* grad_minmarg, double grad
             DM_HIP_TRY(launch_adjoint(h ? tile : tile_v, b, cost_dtype, stream), "half-step adjoint");
         }
         // the last half-step's family enters dL/dLB at the dual before that half-step
-        if (k == S - 1 && grad_lb != 0.0) {
+        if (k == S - 1 && grad_bounds != nullptr) {
             st = lb_inject(h, ck);
             if (st != DM_OK) return st;
         }

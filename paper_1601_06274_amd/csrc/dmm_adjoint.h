@@ -48,7 +48,7 @@ struct AdjArgs {
     float* grad_theta;        // horizontal family: dL/dcost accumulated (may be null)
     double* grad_w;           // dL/dw accumulated in FP64, indexed like w
     const float* grad_mm;     // final mode: dL/d(normalized row min-marginals), may be null
-    double g_lb;              // final mode: dL/d(lower bound)
+    const double* g_lb;       // final mode: device dL/d(lower bound), nullptr = 0
     long long chain_px, node_px, w_chain, w_node;
     unsigned vol_bytes_f32, vol_bytes_theta, w_bytes;
     int K, n, n_chains, T, mode, n_pass;
@@ -981,7 +981,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
     const unsigned tb = a.tape_bytes;
     if (a.mode == kModeFinal) {
         // final row pass: forward min-marginal pass (messages M[1], reverse M[0]), then R0
-        wk.g_lb_f = (float)a.g_lb;
+        wk.g_lb_f = a.g_lb != nullptr ? (float)a.g_lb[0] : 0.0f;
         wk.r_lam = make_rsrc(a.lam0, vb);
         wk.r_cmsg = make_rsrc(a.rec_msg[1], vb);
         wk.r_rmsg = make_rsrc(a.rec_msg[0], vb);

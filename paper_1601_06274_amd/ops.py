@@ -137,16 +137,22 @@ def solve_discrete(cost, w_h, w_v, *, T=3, n_iters=10, n_half_steps=0, minorant=
                           lb_trace=None if trace is None else trace[:S], workspace=workspace)
 
 
-def solve_discrete_backward(cost, w_h, w_v, dual, fwd_workspace, *, grad_minmarg=None, grad_lb=0.0, T=3,
-                            n_iters=10, n_half_steps=0, minorant="iterative", gammas=(0.25, 0.25, 1.0), tile=None,
-                            grad_cost=None, grad_w_h=None, grad_w_v=None, accumulate=False, workspace=None,
-                            stream=None, keep_checkpoints=True, recompute_selections=False):
+def solve_discrete_backward(cost, w_h, w_v, dual, fwd_workspace, *, grad_minmarg=None, grad_lb=0.0, grad_energy=0.0,
+                            grad_bounds=None, T=3, n_iters=10, n_half_steps=0, minorant="iterative",
+                            gammas=(0.25, 0.25, 1.0), tile=None, grad_cost=None, grad_w_h=None, grad_w_v=None,
+                            accumulate=False, workspace=None, stream=None, keep_checkpoints=True,
+                            recompute_selections=False):
     """Adjoint of solve_discrete (dm_solve_discrete_backward); the forward must have run with
-    keep_checkpoints=True and the same parameters.  Returns (grad_cost, grad_w_h, grad_w_v)."""
+    keep_checkpoints=True and the same parameters.  The bound gradients come either as a
+    device float64 tensor ``grad_bounds`` = [dL/dLB, dL/dE] (read on the device) or as the
+    numbers ``grad_lb`` and ``grad_energy``.  Returns (grad_cost, grad_w_h, grad_w_v)."""
     H, W, K = cost.shape
     dev = cost.device
     _check_dev("dual", dual, torch.float32, (H, W, K))
     _check_dev("grad_minmarg", grad_minmarg, torch.float32, (H, W, K))
+    if grad_bounds is None and (float(grad_lb) != 0.0 or float(grad_energy) != 0.0):
+        grad_bounds = torch.tensor([float(grad_lb), float(grad_energy)], dtype=torch.float64, device=dev)
+    _check_dev("grad_bounds", grad_bounds, torch.float64, (2,))
     p = discrete_params(T, n_iters, n_half_steps, minorant, gammas, False, tile, keep_checkpoints or True,
                         recompute_selections)
     shape = L.DmShape(W, H, K)
@@ -160,7 +166,7 @@ def solve_discrete_backward(cost, w_h, w_v, dual, fwd_workspace, *, grad_minmarg
         grad_w_h = torch.empty((H, W - 1), dtype=torch.float32, device=dev)
     if grad_w_v is None:
         grad_w_v = torch.empty((H - 1, W), dtype=torch.float32, device=dev)
-    st = lib.dm_solve_discrete_backward(_ptr(grad_minmarg), ctypes.c_double(float(grad_lb)), _ptr(cost),
+    st = lib.dm_solve_discrete_backward(_ptr(grad_minmarg), _ptr(grad_bounds), _ptr(cost),
                                         _cost_dtype(cost), _ptr(w_h), _ptr(w_v), shape, ctypes.byref(p), _ptr(dual),
                                         _ptr(fwd_workspace), ctypes.c_size_t(fwd_workspace.numel()), _ptr(grad_cost),
                                         _ptr(grad_w_h), _ptr(grad_w_v), 1 if accumulate else 0, _ptr(workspace),

@@ -59,6 +59,11 @@ def _check(res, ref, theta_used, w_h, w_v, T, name):
               lam_err=float(np.abs(res.dual.cpu().numpy() - ref.lam).max()))
     assert rel.max() <= MM_RTOL, f"min-marginal rel err {rel.max():.3e}"
     assert nbad == 0, f"{nbad} label mismatches that are not ties"
+    # the dual state itself, with the min-marginals' bar
+    lam = res.dual.cpu().numpy().astype(np.float64)
+    S = max(float(theta_used.max() - theta_used.min()), 1e-12)
+    lam_rel = np.abs(lam - ref.lam) / np.maximum(np.abs(ref.lam), S)
+    assert lam_rel.max() <= MM_RTOL, f"dual rel err {lam_rel.max():.3e}"
     assert b[1] == pytest.approx(e_lab, rel=1e-9, abs=1e-9)
     scale = max(abs(ref.lower_bound), 1.0)
     assert abs(b[0] - ref.lower_bound) <= 1e-5 * scale

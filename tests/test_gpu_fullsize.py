@@ -23,8 +23,8 @@ pytestmark = pytest.mark.gpu
 
 FRAME = dict(W=1242, H=375, K=192, seed=3000, slope=0.08, occlusion_bands=4, segments=16)
 T, ITERS, GAMMAS = 3, 20, (0.25, 0.25, 1.0)
-ROWS = [0, 187, 374]
-COLS = [0, 620, 1241]
+ROWS = sorted(set(np.linspace(0, 374, 16).round().astype(int).tolist()))    # 16 rows, both borders included
+COLS = sorted(set(np.linspace(0, 1241, 32).round().astype(int).tolist()))   # 32 columns
 
 
 @pytest.fixture(scope="module")
@@ -52,20 +52,22 @@ def _dual(f, half_steps):
     return r.dual.cpu().numpy().astype(np.float64)
 
 
-def test_fullsize_half_steps_sampled(frame):
-    """One H half-step (rows) and one V half-step (columns) against the oracle on sampled
-    chains, from the GPU's dual after 2*ITERS - 2 and 2*ITERS - 1 half-steps."""
+@pytest.mark.parametrize("k", [0, 2 * ITERS - 2])
+def test_fullsize_half_steps_sampled(frame, k):
+    """One H half-step (16 sampled rows) and the V half-step after it (32 sampled columns)
+    against the oracle, from the GPU's dual after k and k + 1 half-steps: the first two
+    half-steps of the solve (from the zero dual) and the last two."""
     f = frame
-    k = 2 * ITERS - 2
-    lam_a, lam_b, lam_c = _dual(f, k), _dual(f, k + 1), _dual(f, k + 2)
+    lam_a = _dual(f, k) if k > 0 else np.zeros(f["th"].shape)
+    lam_b, lam_c = _dual(f, k + 1), _dual(f, k + 2)
     scale = max(1.0, np.abs(lam_b).max())
     h = och.iterative_minorant(f["th"][ROWS] - lam_a[ROWS], f["wh"][ROWS], T, GAMMAS)
     err_h = np.abs(lam_a[ROWS] + h - lam_b[ROWS]).max() / scale
     a = np.ascontiguousarray(np.transpose(lam_b[:, COLS], (1, 0, 2)))
     hv = och.iterative_minorant(a, f["wv"][:, COLS].T, T, GAMMAS)
     err_v = np.abs(lam_b[:, COLS] - np.transpose(hv, (1, 0, 2)) - lam_c[:, COLS]).max() / scale
-    print(f"[parity] full-size half-steps: H {err_h:.2e}, V {err_v:.2e} (relative to max |dual| {scale:.3f})",
-          flush=True)
+    print(f"[parity] full-size half-steps {k}, {k + 1}: H {err_h:.2e} ({len(ROWS)} rows), V {err_v:.2e} "
+          f"({len(COLS)} columns), relative to max |dual| {scale:.3f}", flush=True)
     assert err_h <= 1e-5 and err_v <= 1e-5
     # the other chains moved too (not a no-op)
     assert np.abs(lam_b - lam_a).max() > 1e-3
@@ -97,39 +99,62 @@ def test_fullsize_final_pass_and_bound(frame):
     assert lb_gpu <= e_gpu + 1e-9 * abs(e_gpu)
 
 
-def _grads(f, keep, recompute, G_m, g_lb):
+def _grads(f, keep, recompute, G_m, g_lb, g_e=0.0, n_iters=ITERS):
     ops = f["ops"]
-    r = ops.solve_discrete(f["cost"], f["w_h"], f["w_v"], n_iters=ITERS, want_bounds=True, keep_checkpoints=keep,
+    r = ops.solve_discrete(f["cost"], f["w_h"], f["w_v"], n_iters=n_iters, want_bounds=True, keep_checkpoints=keep,
                            recompute_selections=recompute, **f["kw"])
     g = ops.solve_discrete_backward(f["cost"], f["w_h"], f["w_v"], r.dual, r.workspace, grad_minmarg=G_m,
-                                    grad_lb=g_lb, n_iters=ITERS, keep_checkpoints=keep,
+                                    grad_lb=g_lb, grad_energy=g_e, n_iters=n_iters, keep_checkpoints=keep,
                                     recompute_selections=recompute, **f["kw"])
     torch.cuda.synchronize()
-    out = (r.minmarg.clone(), float(r.bounds[0]), [x.clone() for x in g])
+    out = (r.minmarg.clone(), [float(x) for x in r.bounds.cpu()], [x.clone() for x in g])
     del r, g
     torch.cuda.empty_cache()
     return out
 
 
-def test_fullsize_backward_properties(frame):
+def _backward_properties(f, name, g_lb=0.5, g_e=0.25, seed=11):
     """Euler's identity and the constant-shift identity for L = <G_m, min-marginals> +
-    g_lb * LB at the full frame, with the tapes kept by the forward (the bench's step)."""
-    f = frame
-    g_lb = 0.5
-    gen = torch.Generator(device="cuda").manual_seed(11)
+    g_lb * LB + g_e * E(labels), with the tapes kept by the forward.  Every output is
+    positively homogeneous of degree 1 in (cost, weights), so <cost, dL/dcost> +
+    <w, dL/dw> = L; a constant added to one pixel's costs leaves the normalized
+    min-marginals unchanged and moves LB and E by that constant, so every pixel's
+    dL/dcost sums to g_lb + g_e."""
+    gen = torch.Generator(device="cuda").manual_seed(seed)
     G_m = torch.randn(f["cost"].shape, generator=gen, device="cuda", dtype=torch.float32)
-    mm, lb, (gc, gwh, gwv) = _grads(f, 2, False, G_m, g_lb)
-    L = float((G_m.double() * mm.double()).sum()) + g_lb * lb
+    mm, (lb, e), (gc, gwh, gwv) = _grads(f, 2, False, G_m, g_lb, g_e)
+    L = float((G_m.double() * mm.double()).sum()) + g_lb * lb + g_e * e
     euler = float((f["cost"].double() * gc.double()).sum() + (f["w_h"].double() * gwh.double()).sum()
                   + (f["w_v"].double() * gwv.double()).sum())
     scale = float((f["cost"].double() * gc.double()).abs().sum() + (f["w_h"].double() * gwh.double()).abs().sum()
                   + (f["w_v"].double() * gwv.double()).abs().sum())
-    shift = (gc.double().sum(dim=2) - g_lb).abs().max().item()
-    print(f"[parity] full-size backward: Euler {euler:.6f} vs L {L:.6f} (scale {scale:.1f}); per-pixel sum of "
-          f"dL/dcost - g_lb: max {shift:.2e}", flush=True)
+    shift = (gc.double().sum(dim=2) - (g_lb + g_e)).abs().max().item()
+    print(f"[parity] {name} backward: Euler {euler:.6f} vs L {L:.6f} (scale {scale:.1f}); per-pixel sum of "
+          f"dL/dcost - (g_lb + g_e): max {shift:.2e}", flush=True)
     assert abs(euler - L) <= 1e-5 * scale
     assert shift <= 1e-3
     assert torch.isfinite(gc).all() and torch.isfinite(gwh).all() and torch.isfinite(gwv).all()
+
+
+def test_fullsize_backward_properties(frame):
+    """The identities at the bench frame (1242x375x192, FP16 cost)."""
+    _backward_properties(frame, "full-size")
+
+
+def test_differentiation_frame_backward_properties():
+    """The identities at the differentiation workload's frame size (960x320, K=96, FP32 cost,
+    20 dual iterations, the tapes kept by the forward)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1601_06274_amd import ops
+    W, H, K = 960, 320, 96
+    pair = synth.stereo_pair(W, H, K, seed=5000, slope=0.08, occlusion_bands=2)
+    dev = torch.device("cuda:0")
+    print(f"[case] differentiation frame {W}x{H}x{K} FP32", flush=True)
+    cost, w_h, w_v = ops.build_cost_volume(torch.from_numpy(pair.left).to(dev), torch.from_numpy(pair.right).to(dev),
+                                           K, dtype=torch.float32)
+    f = dict(ops=ops, cost=cost, w_h=w_h, w_v=w_v, kw=dict(T=T, gammas=GAMMAS))
+    _backward_properties(f, "960x320x96", seed=13)
 
 
 def test_fullsize_tape_equals_recompute(frame):
