@@ -13,11 +13,12 @@ itself declares independent (all rows of one half-step, all columns of the
 other); along a chain every step is taken in the paper's order.
 
 Modules
-  chain        messages, min-marginals, iterative / naive / hierarchical minorants (App. A.1, A.3)
+  chain        messages, min-marginals, iterative / naive / hierarchical / uniform minorants (App. A.1, A.3)
   dmm          dual decomposition and the Dual_MM loop (Sec. 2.3, Alg. Dual_MM)
   energy       the discrete energy and brute-force minimisation (Sec. 2.2)
   cost_volume  SAD cost volume and contrast edge weights (Sec. 2.2 "Stereo", Sec. 3.1)
   census       Census + Hamming cost volume and the left-right check (Sec. 3.1)
   refine       continuous refinement by non-linear primal-dual (Sec. 2.4, Sec. 3.1)
+  trws         TRW-S on the same decomposition (App. A.1, eq. TRW-S-update), a quality reference
 """
-from . import chain, dmm, energy, cost_volume, census, refine  # noqa: F401
+from . import chain, dmm, energy, cost_volume, census, refine, trws  # noqa: F401

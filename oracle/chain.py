@@ -28,6 +28,8 @@ __all__ = [
     "naive_minorant",
     "hierarchical_minorant",
     "hierarchical_split",
+    "chain_argmin",
+    "uniform_minorant",
 ]
 
 
@@ -241,3 +243,82 @@ def hierarchical_minorant(a: np.ndarray, w: np.ndarray, T: int) -> np.ndarray:
         process(0, n - 1)
     m = a + L + R
     return m - m.min(axis=2, keepdims=True)
+
+
+def chain_argmin(a: np.ndarray, w: np.ndarray, T: int) -> np.ndarray:
+    """An optimal labeling of each chain (dynamic programming, App. A.1): x_0 minimises
+    a_0 + R_0, then each x_j minimises a_j + R_j + w_{j-1} rho(x_{j-1} - x_j) given x_{j-1};
+    the lowest label wins ties.  Returns (C, n) int64."""
+    a = np.asarray(a, np.float64)
+    w = np.asarray(w, np.float64)
+    C, n, K = a.shape
+    _, R = left_right_messages(a, w, T)
+    x = np.zeros((C, n), np.int64)
+    k = np.arange(K)
+    x[:, 0] = np.argmin(a[:, 0] + R[:, 0], axis=1)
+    for j in range(1, n):
+        pw = w[:, j - 1][:, None] * rho(k[None, :] - x[:, j - 1][:, None], T)
+        x[:, j] = np.argmin(a[:, j] + R[:, j] + pw, axis=1)
+    return x
+
+
+def uniform_minorant(a: np.ndarray, w: np.ndarray, T: int, *, tol: float = 1e-9, max_steps: int | None = None):
+    """Maximal uniform minorant of chains a (App. A.3.1, Alg. Maximal Uniform Minorant).
+
+    Starting from h = 0, repeat: take the normalized min-marginals m of the remainder
+    f - h; stop when they are all 0; otherwise let O mark the label-nodes with m = 0 (the
+    support of the remainder's optimal labelings), find the largest eps with
+    eps * <1 - O, x> <= (f - h)(x) - min(f - h) for every labeling x (Prop. max-epsilon),
+    and add eps to every label-node outside O.
+
+    The largest eps is the minimum over labelings x with <1 - O, x> > 0 of the ratio
+    N(x) / D(x), N(x) = (f - h)(x) - min(f - h), D(x) = <1 - O, x> (a minimum-ratio path,
+    as the text notes).  It is found by Dinkelbach's parametric iteration: for a trial
+    ratio e, an optimal labeling x of the chain with unaries (a - h) - e (1 - O) gives
+    min_x [N(x) - e D(x)]; if that minimum is (numerically) 0, e is the largest eps,
+    otherwise D(x) > 0 and the next trial is N(x) / D(x), strictly smaller.  The first
+    trial is the smallest positive min-marginal, an upper bound of the largest eps (the
+    best labeling through that label-node has N equal to it and D >= 1).
+
+    ``tol`` (relative to the cost range) decides m = 0, the numerically delicate part that
+    the text points out.  ``max_steps`` stops after that many outer steps (1 gives the
+    first step of the worked example).  Arrays: a (C, n, K), w (C, n-1); returns h.
+    """
+    a = np.asarray(a, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    C, n, K = a.shape
+    h = np.zeros_like(a)
+    scale = max(1.0, float(np.abs(a).max()) if a.size else 1.0)
+    eps_tol = tol * scale
+    steps = 0
+    # every step adds at least one label-node to the support O, so n*K steps suffice
+    limit = n * K if max_steps is None else max_steps
+    while steps < limit:
+        rem = a - h
+        m = min_marginals(rem, w, T, normalized=True)
+        O = m <= eps_tol
+        active = ~O.all(axis=(1, 2))
+        if not active.any():
+            break
+        D = (~O).astype(np.float64)
+        fstar = min_marginals(rem, w, T, normalized=False)[:, 0, :].min(axis=1)
+        e = np.where(active, np.where(O, np.inf, m).reshape(C, -1).min(axis=1), 0.0)
+        todo = active.copy()
+        rounds = 0
+        while todo.any():
+            rounds += 1
+            if rounds > 10 * n * K:  # Dinkelbach's ratios strictly decrease over finitely many labelings
+                raise RuntimeError("uniform minorant: the parametric ratio search does not converge")
+            x = chain_argmin(rem - e[:, None, None] * D, w, T)
+            val = chain_energy(rem - e[:, None, None] * D, w, T, x) - fstar
+            Dx = np.take_along_axis(D, x[:, :, None], axis=2)[:, :, 0].sum(axis=1)
+            Nx = chain_energy(rem, w, T, x) - fstar
+            better = todo & (val < -eps_tol) & (Dx > 0)
+            e = np.where(better, Nx / np.where(Dx > 0, Dx, 1.0), e)
+            todo = better
+        h += np.where(active, e, 0.0)[:, None, None] * D
+        steps += 1
+    else:
+        if max_steps is None:
+            raise RuntimeError("uniform minorant: the support did not grow to every label-node")
+    return h

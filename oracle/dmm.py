@@ -55,6 +55,8 @@ def _minorant(a, w, T, minorant, gammas):
         return chain.naive_minorant(a, w, T)
     if minorant == "hierarchical":
         return chain.hierarchical_minorant(a, w, T)
+    if minorant == "uniform":
+        return chain.uniform_minorant(a, w, T)
     raise ValueError(minorant)
 
 
