@@ -1,6 +1,10 @@
 """Builds libdmatch.so for gfx950 in place (hipcc, no torch extension machinery).
 
-Usage: python -m paper_1601_06274_amd.build [--jobs N]
+Usage: python -m paper_1601_06274_amd.build [--jobs N] [--incremental]
+
+By default every unit is compiled.  With --incremental a unit is skipped when its object
+is newer than every file its last compile depended on (hipcc's dependency list, kept
+beside the object).
 """
 from __future__ import annotations
 
@@ -45,24 +49,41 @@ FLAGS = [
 ]
 
 
-def _compile(unit) -> str:
+def _up_to_date(obj: str, dep: str) -> bool:
+    """True when `obj` is newer than every prerequisite listed in the make-style `dep`."""
+    if not (os.path.exists(obj) and os.path.exists(dep)):
+        return False
+    with open(dep) as f:
+        text = f.read().replace("\\\n", " ")
+    _, _, prereqs = text.partition(":")
+    t = os.path.getmtime(obj)
+    for p in prereqs.split():
+        if not os.path.exists(p) or os.path.getmtime(p) > t:
+            return False
+    return True
+
+
+def _compile(unit, incremental=False) -> str:
     src, defs, name = unit
     obj = os.path.join(BUILD, name + ".o")
-    cmd = [HIPCC, *FLAGS, *defs, "-c", os.path.join(CSRC, src), "-o", obj]
+    dep = os.path.join(BUILD, name + ".d")
+    if incremental and _up_to_date(obj, dep):
+        return obj
+    cmd = [HIPCC, *FLAGS, *defs, "-MMD", "-MF", dep, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(UNITS), os.cpu_count() or 1)
     for f in os.listdir(BUILD):  # objects of units that no longer exist
         if f.endswith(".o") and f[:-2] not in {u[2] for u in UNITS}:
             os.remove(os.path.join(BUILD, f))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, UNITS))
+        objs = list(ex.map(lambda u: _compile(u, incremental), UNITS))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -77,6 +98,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--incremental", action="store_true", help="skip units whose object is up to date")
     a = ap.parse_args()
-    build(a.jobs, verbose=True)
+    build(a.jobs, verbose=True, incremental=a.incremental)
     sys.exit(0)
