@@ -196,6 +196,20 @@ int dm_solve_discrete(const void* cost, dm_dtype cost_dtype, const float* w_h, c
                       double* bounds_out, double* lb_trace_out,
                       void* workspace, size_t workspace_bytes, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid allocation): dm_solve_discrete with the same arguments and
+ * results, but without a workspace.  The scratch memory lives in a library-owned device
+ * array of dm_solve_discrete_noalloc_limit() bytes (256 MiB) per GPU, held from the first
+ * call on that GPU until the process ends; this call allocates nothing.  Problems whose
+ * dm_solve_discrete_workspace() exceeds the limit fail with DM_ERR_WORKSPACE (e.g. K = 128
+ * fits up to about 640 x 480 with keep_checkpoints = 0).  All calls on one GPU share the
+ * array: calls that overlap in time on the same GPU race, so the caller serialises them. */
+size_t dm_solve_discrete_noalloc_limit(void);
+int dm_solve_discrete_noalloc(const void* cost, dm_dtype cost_dtype, const float* w_h, const float* w_v,
+                              dm_shape s, const dm_discrete_params* p,
+                              int32_t* labels_out, float* minmarg_out, float* dual_inout,
+                              double* bounds_out, double* lb_trace_out, void* hip_stream);
+
 /* The tile used when p->tile_lanes is 0: the compiled (lanes per chain, labels per lane)
  * tile with the fewest idle label slots for K labels (more lanes on ties).  Host only;
  * returns DM_ERR_SHAPE for K outside [1, 256], DM_ERR_NULL for null outputs. */

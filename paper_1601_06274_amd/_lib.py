@@ -77,6 +77,9 @@ _SIGNATURES = [
     ("dm_solve_discrete", ctypes.c_int,
      [_VP, ctypes.c_int, _VP, _VP, DmShape, ctypes.POINTER(DmDiscreteParams), _VP, _VP, _VP, _VP, _VP, _VP,
       ctypes.c_size_t, _VP]),
+    ("dm_solve_discrete_noalloc_limit", ctypes.c_size_t, []),
+    ("dm_solve_discrete_noalloc", ctypes.c_int,
+     [_VP, ctypes.c_int, _VP, _VP, DmShape, ctypes.POINTER(DmDiscreteParams), _VP, _VP, _VP, _VP, _VP, _VP]),
     ("dm_default_tile", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     ("dm_autotune_tiles", ctypes.c_int, [DmShape, ctypes.c_int, ctypes.POINTER(DmDiscreteParams), _VP]),
     ("dm_solve_discrete_backward_workspace", ctypes.c_size_t, [DmShape, ctypes.POINTER(DmDiscreteParams)]),
