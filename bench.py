@@ -118,6 +118,9 @@ def cpu_baseline(pair, wl, target_s):
     updates = sum(r[0] for r in res)
     reps = sum(r[2] for r in res)
     return {"value": updates / wall, "unit": "label-node updates/s", "cores": n, "kind": "oracle",
+            "host_cpus": os.cpu_count(), "host_cpus_available": len(os.sched_getaffinity(0)),
+            "cores_note": "one worker process per CPU available to this process, capped at 16: the CPU share "
+                          "of one GPU on this host (the host's other CPUs serve its other GPUs)",
             "sample": f"{n} processes, each repeating (horizontal half-step on 16 rows x {wl['W']} + vertical "
                       f"half-step on 32 columns x {wl['H']}) of its own bands of the frame, K={wl['K']}, FP64 "
                       f"numpy, {reps} repetitions in {wall:.1f} s wall",
@@ -180,10 +183,10 @@ def batched_extra(torch, ops, dev, n=64, seed=4000, n_iters=20, T=3, reps=3):
             "speedup_vs_plain_fp32": ms_p / ms_b}
 
 
-def diff_extra(torch, ops, dev, n=8, W=960, H=320, K=96, n_iters=20, T=3, warps=5, iters=10, seed=5000, reps=2,
+def diff_extra(torch, ops, dev, n=8, W=960, H=320, K=96, n_iters=20, T=3, warps=1, iters=50, seed=5000, reps=2,
                n_streams=8):
     """Differentiation workload: a batch of 8 frames 960x320, K=96, FP16 cost; forward
-    (Dual_MM 20 its keeping the selection tapes + refinement 5 x 10 steps) and backward
+    (Dual_MM 20 its keeping the selection tapes + refinement 1 x 50 steps) and backward
     (dL/dcost, dL/dw) per frame.  One frame fills only a few hundred waves, so the batch
     runs on n_streams streams (default priority; frames round-robin, each stream with its
     own workspaces).  Reported against the plain FP32 forward of the same frames, one

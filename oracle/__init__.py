@@ -20,5 +20,6 @@ Modules
   census       Census + Hamming cost volume and the left-right check (Sec. 3.1)
   refine       continuous refinement by non-linear primal-dual (Sec. 2.4, Sec. 3.1)
   trws         TRW-S on the same decomposition (App. A.1, eq. TRW-S-update), a quality reference
+  flow         optical flow: 2-D SAD cost, decoupled layer costs, quadratic-fit refinement (Sec. 2.2, 3.2)
 """
-from . import chain, dmm, energy, cost_volume, census, refine, trws  # noqa: F401
+from . import chain, dmm, energy, cost_volume, census, refine, trws, flow  # noqa: F401

@@ -26,6 +26,8 @@ __all__ = [
     "stereo_pair",
     "BatchSpec",
     "batch_specs",
+    "FlowPair",
+    "flow_pair",
 ]
 
 
@@ -151,3 +153,57 @@ def batch_specs(n: int = 64, seed: int = 4000, *, w_range=(160, 1280), h_range=(
         K = int(k_choices[int(g.integers(0, len(k_choices)))])
         out.append(BatchSpec(W=W, H=H, K=K, seed=seed + 1 + i))
     return out
+
+
+@dataclasses.dataclass
+class FlowPair:
+    first: np.ndarray   # [H][W] float32 in [0,1]
+    second: np.ndarray  # [H][W] float32 in [0,1]
+    flow: np.ndarray    # [H][W][2] float32: true displacement (horizontal, vertical), second-image grid
+
+
+def flow_pair(W: int, H: int, max_disp: float, seed: int, *, segments: int | None = None, slope: float = 0.02,
+              noise_sigma: float = 2.0 / 255.0) -> FlowPair:
+    """Random-texture image pair related by a piecewise-affine flow.
+
+    * first image: U[0,1) noise, 3x3 box blur, rescaled to [0,1];
+    * flow: Voronoi partition into ``segments`` cells, each with an affine field
+      u = u0 + A (p - c), u0 ~ U[-max_disp, max_disp]^2, |A_kl| <= ``slope``, clipped to
+      [-max_disp, max_disp];
+    * second image: I2(p) = I1(p - u(p)) by bilinear interpolation (clamped), plus Gaussian
+      noise of std ``noise_sigma``, clipped to [0,1].
+    """
+    g = rng(seed)
+    if segments is None:
+        segments = max(3, int(round(W * H / 20000.0)))
+    first = _box3(g.random((H, W)))
+    lo, hi = first.min(), first.max()
+    first = (first - lo) / max(hi - lo, 1e-12)
+    cx = g.random(segments) * W
+    cy = g.random(segments) * H
+    u0 = g.uniform(-max_disp, max_disp, (segments, 2))
+    A = g.uniform(-slope, slope, (segments, 2, 2))
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    best = np.full((H, W), np.inf)
+    seg = np.zeros((H, W), dtype=np.int64)
+    for s in range(segments):
+        dist = (xs - cx[s]) ** 2 + (ys - cy[s]) ** 2
+        closer = dist < best
+        best[closer] = dist[closer]
+        seg[closer] = s
+    dx, dy = xs - cx[seg], ys - cy[seg]
+    flow = np.stack([u0[seg, 0] + A[seg, 0, 0] * dx + A[seg, 0, 1] * dy,
+                     u0[seg, 1] + A[seg, 1, 0] * dx + A[seg, 1, 1] * dy], axis=-1)
+    flow = np.clip(flow, -max_disp, max_disp)
+    sx = np.clip(xs - flow[..., 0], 0.0, W - 1.0)
+    sy = np.clip(ys - flow[..., 1], 0.0, H - 1.0)
+    x0 = np.floor(sx).astype(np.int64)
+    y0 = np.floor(sy).astype(np.int64)
+    x1 = np.minimum(x0 + 1, W - 1)
+    y1 = np.minimum(y0 + 1, H - 1)
+    t, s_ = sx - x0, sy - y0
+    second = ((1 - s_) * ((1 - t) * first[y0, x0] + t * first[y0, x1])
+              + s_ * ((1 - t) * first[y1, x0] + t * first[y1, x1]))
+    second = second + g.normal(0.0, noise_sigma, second.shape)
+    return FlowPair(first=first.astype(np.float32), second=np.clip(second, 0.0, 1.0).astype(np.float32),
+                    flow=flow.astype(np.float32))
