@@ -316,6 +316,51 @@ int dm_refine_continuous_backward(const float* grad_u, const void* cost, dm_dtyp
                                   size_t workspace_bytes, void* hip_stream);
 
 /* ---------------------------------------------------------------------------------
+ * Optical flow (paper Sec. 2.2 "Flow" and Sec. 3.2).  u_i in R^2: the horizontal and the
+ * vertical displacement.  Labels: i in [0, K1) is the horizontal displacement i - off1,
+ * j in [0, K2) the vertical displacement j - off2 (pixels).  The discretised data cost of
+ * pixel (x, y) is a K2 x K1 table, stored [H][W][K2][K1]: cost[((y*W + x)*K2 + j)*K1 + i].
+ * 1 <= W, H <= 16384; 1 <= K1, K2 <= 256, K1*K2 <= 4096; 0 <= off1 < K1, 0 <= off2 < K2;
+ * W*H*K1*K2 < 2^32.  Errors as elsewhere (validation before any launch).
+ *
+ * The discrete stage decouples the two components (eq. flow decoupled costs): layer 1 has
+ * the unaries f1(i) = min_j cost(i, j), layer 2 f2(j) = min_i cost(i, j), and each layer is
+ * a stereo-like Dual_MM problem on the same grid and edge weights (two dm_solve_discrete
+ * calls, K = K1 and K = K2).  The refinement (Sec. 3.2) runs the primal-dual iteration of
+ * dm_refine_continuous on each component (the regulariser is separable over the
+ * components, eq. regularizer-form) with the quadratic data model of eq. quadfit:
+ * L = central first differences and Q = the positive part of the central second
+ * differences (diagonal) of the bilinearly interpolated table at the current point, step
+ * h, and the prox of eq. prox_flow read as
+ *     u = clamp(u0 +- h, (u_hat + tau (Q u0 - L)) / (1 + tau Q))   per component,
+ * the box also intersected with the label range.  u is returned in label units (the
+ * displacement is u - off).
+ * ------------------------------------------------------------------------------- */
+typedef struct { int W, H, K1, K2, off1, off2; } dm_flow_shape;
+
+/* Two-dimensional truncated SAD: e(x,y,i,j) = |I1(x,y) - I2(x+i-off1, y+j-off2)| (trunc if
+ * the displaced position is outside I2); cost = min(trunc, mean of e over the window x.+-r,
+ * y.+-r clamped to the image).  w_h / w_v (may be NULL): contrast weights of I1, as in
+ * dm_build_cost_volume.  I1, I2: [H][W] float32; cost_out of out_dtype (FP16 rounded to
+ * nearest even). */
+int dm_build_flow_cost_volume(const float* I1, const float* I2, dm_flow_shape s, const dm_cost_params* p,
+                              dm_dtype out_dtype, void* cost_out, float* w_h, float* w_v, void* hip_stream);
+
+/* eq. flow decoupled costs: f1_out [H][W][K1], f2_out [H][W][K2], both in cost_dtype (the
+ * minima are exact). */
+int dm_flow_project(const void* cost, dm_dtype cost_dtype, dm_flow_shape s, void* f1_out, void* f2_out,
+                    void* hip_stream);
+
+/* Quadratic-fit refinement of both components from the two layers' labels.  p: as for
+ * dm_refine_continuous (C, eps, delta, h, tau, sigma, n_warps, n_iters); keep_tape must be 0
+ * (no backward: DM_ERR_UNSUPPORTED).  u1_out, u2_out: [H][W] float32 in label units.
+ * State FP64 in a caller workspace of dm_refine_flow_workspace() bytes. */
+size_t dm_refine_flow_workspace(dm_flow_shape s, const dm_refine_params* p);
+int dm_refine_flow(const void* cost, dm_dtype cost_dtype, const int32_t* labels1, const int32_t* labels2,
+                   const float* w_h, const float* w_v, dm_flow_shape s, const dm_refine_params* p,
+                   float* u1_out, float* u2_out, void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* ---------------------------------------------------------------------------------
  * Batched form: many instances of uneven size (each with its own W, H, K) solved by
  * one hipGraph launch.  dm_plan_batched picks a chain tile per labels count and chain
  * family (dm_autotune_tiles unless p fixes tile_lanes), builds the work tables and
@@ -372,7 +417,9 @@ typedef enum {
     DM_PROF_RECORD_V = 13,        /* record-mode vertical half-step (likewise)          */
     DM_PROF_CENSUS = 14,          /* Census + Hamming cost volume (without the weights) */
     DM_PROF_LR_CHECK = 15,        /* left-right consistency check                       */
-    DM_PROF_KINDS = 16
+    DM_PROF_FLOW_COST = 16,       /* two-dimensional SAD flow cost (without the weights) */
+    DM_PROF_FLOW_PROJECT = 17,    /* decoupled layer costs of the flow                  */
+    DM_PROF_KINDS = 18
 } dm_prof_kind;
 
 /* kind_mask != 0: clear all records and record launches of the kinds whose bit

@@ -51,26 +51,31 @@ __all__ = ["flow_cost_volume", "project", "interp2", "linearize_quadfit", "prox_
            "solve_flow", "FlowResult"]
 
 
-def flow_cost_volume(I1, I2, K1: int, K2: int, off1: int, off2: int, window: int = 3, trunc: float = 0.3):
+def flow_cost_volume(I1, I2, K1: int, K2: int, off1: int, off2: int, window: int = 3, trunc: float = 0.3,
+                     rows=None):
     """[H][W][K2][K1] truncated windowed SAD between I1 at (x, y) and I2 at the displaced
-    position (x + i - off1, y + j - off2); a displaced position outside I2 costs trunc."""
+    position (x + i - off1, y + j - off2); a displaced position outside I2 costs trunc.
+    ``rows`` = (lo, hi) returns only the output rows lo..hi-1 (the same values)."""
     A = np.asarray(I1, np.float64)
     B = np.asarray(I2, np.float64)
     H, W = A.shape
     r = window // 2
-    ys, xs = np.arange(H), np.arange(W)
-    out = np.zeros((H, W, K2, K1))
+    lo, hi = (0, H) if rows is None else rows
+    ys_out = np.arange(lo, hi)
+    e_rows = np.arange(max(lo - r, 0), min(hi + r, H))  # the rows of e the windows reach
+    xs = np.arange(W)
+    out = np.zeros((hi - lo, W, K2, K1))
     for j in range(K2):
         for i in range(K1):
             d1, d2 = i - off1, j - off2
-            e = np.full((H, W), trunc)
+            e = np.full((len(e_rows), W), trunc)
             vx = (xs + d1 >= 0) & (xs + d1 < W)
-            vy = (ys + d2 >= 0) & (ys + d2 < H)
+            vy = (e_rows + d2 >= 0) & (e_rows + d2 < H)
             yy, xx = np.nonzero(vy[:, None] & vx[None, :])
-            e[yy, xx] = np.abs(A[yy, xx] - B[yy + d2, xx + d1])
-            acc = np.zeros((H, W))
+            e[yy, xx] = np.abs(A[e_rows[yy], xx] - B[e_rows[yy] + d2, xx + d1])
+            acc = np.zeros((hi - lo, W))
             for dy in range(-r, r + 1):
-                cy = np.clip(ys + dy, 0, H - 1)
+                cy = np.clip(ys_out + dy, 0, H - 1) - e_rows[0]
                 for dx in range(-r, r + 1):
                     cx = np.clip(xs + dx, 0, W - 1)
                     acc += e[cy][:, cx]

@@ -20,7 +20,8 @@ DM_MINORANT_HIERARCHICAL = 2
 
 PROF_KINDS = {"sweep_h": 0, "sweep_v": 1, "sweep_final": 2, "sweep_opt": 3, "bounds": 4, "cost_volume": 5,
               "refine_linearize": 6, "refine_iter": 7, "other": 8, "adjoint_h": 9, "adjoint_v": 10,
-              "adjoint_final": 11, "record_h": 12, "record_v": 13, "census": 14, "lr_check": 15}
+              "adjoint_final": 11, "record_h": 12, "record_v": 13, "census": 14, "lr_check": 15, "flow_cost": 16,
+              "flow_project": 17}
 
 STATUS_NAMES = {
     0: "DM_OK", -1: "DM_ERR_NULL", -2: "DM_ERR_SHAPE", -3: "DM_ERR_PARAM", -4: "DM_ERR_DTYPE",
@@ -49,6 +50,11 @@ class DmRefineParams(ctypes.Structure):
     _fields_ = [("C", ctypes.c_float), ("eps", ctypes.c_float), ("delta", ctypes.c_float), ("h", ctypes.c_float),
                 ("tau", ctypes.c_float), ("sigma", ctypes.c_float), ("n_warps", ctypes.c_int), ("n_iters", ctypes.c_int),
                 ("keep_tape", ctypes.c_int)]
+
+
+class DmFlowShape(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_int), ("H", ctypes.c_int), ("K1", ctypes.c_int), ("K2", ctypes.c_int),
+                ("off1", ctypes.c_int), ("off2", ctypes.c_int)]
 
 
 class DmInstance(ctypes.Structure):
@@ -89,6 +95,13 @@ _SIGNATURES = [
     ("dm_refine_continuous_workspace", ctypes.c_size_t, [DmShape, ctypes.POINTER(DmRefineParams)]),
     ("dm_refine_continuous", ctypes.c_int,
      [_VP, ctypes.c_int, _VP, _VP, _VP, DmShape, ctypes.POINTER(DmRefineParams), _VP, _VP, ctypes.c_size_t, _VP]),
+    ("dm_build_flow_cost_volume", ctypes.c_int,
+     [_VP, _VP, DmFlowShape, ctypes.POINTER(DmCostParams), ctypes.c_int, _VP, _VP, _VP, _VP]),
+    ("dm_flow_project", ctypes.c_int, [_VP, ctypes.c_int, DmFlowShape, _VP, _VP, _VP]),
+    ("dm_refine_flow_workspace", ctypes.c_size_t, [DmFlowShape, ctypes.POINTER(DmRefineParams)]),
+    ("dm_refine_flow", ctypes.c_int,
+     [_VP, ctypes.c_int, _VP, _VP, _VP, _VP, DmFlowShape, ctypes.POINTER(DmRefineParams), _VP, _VP, _VP,
+      ctypes.c_size_t, _VP]),
     ("dm_profiler_enable", ctypes.c_int, [ctypes.c_uint]),
     ("dm_profiler_query", ctypes.c_int,
      [ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),

@@ -30,7 +30,8 @@ def _tiles():
 
 TILES = _tiles()
 UNITS = [("api.hip", [], "api"), ("dmm.hip", [], "dmm"), ("cost_volume.hip", [], "cost_volume"),
-         ("refine.hip", [], "refine"), ("batched.hip", [], "batched"), ("noalloc.hip", [], "noalloc")]
+         ("refine.hip", [], "refine"), ("batched.hip", [], "batched"), ("noalloc.hip", [], "noalloc"),
+         ("flow.hip", [], "flow")]
 # largest units first so the parallel build's critical path starts early
 UNITS = [("dmm_tile.hip", [f"-DDM_TILE_G={g}", f"-DDM_TILE_L={l}", f"-DDM_TILE_PART={k}"], f"dmm_tile_{g}x{l}_{v}")
          for k, v in [(2, "adj"), (4, "tape"), (1, "fwd"), (3, "batch")] for g, l in sorted(TILES, key=lambda t: -t[0] * t[1])] + UNITS

@@ -34,6 +34,11 @@ int check_hip(const char* where);
     } while (0)
 
 int validate_shape(const dm_shape& s);
+
+// Contrast edge weights w = lambda_pw * exp(-|I(neighbour) - I| / contrast_sigma) of one
+// image (cost_volume.hip); w_h / w_v may be null.
+hipError_t launch_contrast_weights(const float* I, int W, int H, float lambda_pw, float contrast_sigma, float* w_h,
+                                   float* w_v, hipStream_t stream);
 int validate_discrete(const dm_shape& s, const dm_discrete_params* p);
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }

@@ -104,6 +104,15 @@ __global__ __launch_bounds__(256) void contrast_kernel(const float* __restrict__
     }
 }
 
+hipError_t launch_contrast_weights(const float* I, int W, int H, float lambda_pw, float contrast_sigma, float* w_h,
+                                   float* w_v, hipStream_t stream) {
+    const long long npx = (long long)W * H;
+    const unsigned b2 = (unsigned)std::min<long long>((npx + 255) / 256, 65535LL);
+    hipLaunchKernelGGL(contrast_kernel, dim3(b2), dim3(256), 0, stream, I, W, H, lambda_pw, 1.0f / contrast_sigma, w_h,
+                       w_v);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ Census + Hamming
 // The paper's data term (Sec. 3.1): each image's Census transform over a small patch,
 // compared by the Hamming distance.  Readings: bit b of a pixel's code is

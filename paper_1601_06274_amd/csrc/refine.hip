@@ -35,6 +35,7 @@
 // (exact ties of a branch test) the derivative of the branch that the forward took is
 // used; on the interpolated data term at integer arguments the segment [k, k+1].
 #include "common.h"
+#include "pdhg.h"
 #include "refine.h"
 
 namespace dm {
@@ -92,34 +93,6 @@ __global__ __launch_bounds__(256) void linearize_kernel(const TT* __restrict__ t
         linearize_px(th, u, p, K, h, u0, sL, sR);
 }
 
-// Branch codes of the conjugate prox (3 bits): 0 = identity slope in t, 1 / 2 = flat at
-// +alpha*w / -alpha*w, 3 / 4 = clamped at +w / -w.
-__device__ __forceinline__ rfloat prox_conj(rfloat t, rfloat w, rfloat alpha, rfloat beta, rfloat step, int& code) {
-    const rfloat a = fabs(t);
-    const rfloat aw = alpha * w;
-    rfloat r;
-    code = 0;
-    if (a <= aw) {
-        r = t;
-    } else {
-        const rfloat sh = a - beta * step;
-        if (sh < aw) {
-            r = copysign(aw, t);
-            code = t > 0.0 ? 1 : 2;
-        } else {
-            r = copysign(sh, t);
-        }
-    }
-    if (r < -w) {
-        r = -w;
-        code = 4;
-    } else if (r > w) {
-        r = w;
-        code = 3;
-    }
-    return r;
-}
-
 // prox of tau * D~ (two-slope soft threshold) and the box [u0 - h, u0 + h] n [0, K-1].
 // code: bits 0-1 zone (0 middle, 1 right slope, 2 left slope), bits 2-3 clamp (0, 1 low, 2 high).
 __device__ __forceinline__ rfloat prox_data(rfloat uh, rfloat u0, rfloat l, rfloat r, rfloat tau, rfloat h, rfloat kmax,
@@ -150,79 +123,22 @@ __device__ __forceinline__ rfloat prox_data(rfloat uh, rfloat u0, rfloat l, rflo
     return v;
 }
 
-constexpr int kTX = 64, kTY = 4;
-
-// Mask layout (uint16 per pixel and iteration): [0,4) u-prox, [4,7) qh, [7,10) qv,
-// [10,13) ph, [13,16) pv.
-__device__ __forceinline__ int mfield(uint32_t m, int shift, int bits) { return (int)((m >> shift) & ((1u << bits) - 1u)); }
-
-// Edge arrays are stored per pixel: ph/qh at (x, y) belong to the edge (x, y)-(x+1, y)
-// (unused in the last column), pv/qv to (x, y)-(x, y+1) (unused in the last row).
-__device__ __forceinline__ void pdhg_tile(const RefineState& in, const RefineState& out, const rfloat* __restrict__ u0,
-                                          const rfloat* __restrict__ sL, const rfloat* __restrict__ sR,
-                                          const float* __restrict__ w_h, const float* __restrict__ w_v, int W, int H,
-                                          int K, const RefineScalars& sc, uint16_t* __restrict__ mask, int x0, int y0) {
-    __shared__ rfloat s_uo[kTY + 1][kTX + 1];
-    __shared__ rfloat s_un[kTY + 1][kTX + 1];
-    __shared__ int s_code[kTY][kTX];
-    const rfloat kmax = (rfloat)(K - 1);
-    // Phase A: u+ on the tile and its right / lower halo.
-    for (int idx = threadIdx.x; idx < (kTX + 1) * (kTY + 1); idx += blockDim.x) {
-        const int i = idx % (kTX + 1), j = idx / (kTX + 1);
-        const int x = x0 + i, y = y0 + j;
-        rfloat uo = 0.0, un = 0.0;
-        int code = 0;
-        if (x < W && y < H) {
-            const long long p = (long long)y * W + x;
-            // (A^T z)_i = z_h(i) + z_v(i) - z_h(left) - z_v(up), z = p - q
-            rfloat at = 0.0;
-            if (x + 1 < W) at += in.ph[p] - in.qh[p];
-            if (y + 1 < H) at += in.pv[p] - in.qv[p];
-            if (x > 0) at -= in.ph[p - 1] - in.qh[p - 1];
-            if (y > 0) at -= in.pv[p - W] - in.qv[p - W];
-            uo = in.u[p];
-            un = prox_data(uo - sc.tau * at, u0[p], sL[p], sR[p], sc.tau, sc.h, kmax, code);
-        }
-        s_uo[j][i] = uo;
-        s_un[j][i] = un;
-        if (i < kTX && j < kTY) s_code[j][i] = code;
+struct TwoSlopeProx {
+    const rfloat* u0;
+    const rfloat* sL;
+    const rfloat* sR;
+    rfloat tau, h;
+    __device__ __forceinline__ rfloat operator()(rfloat uh, long long p, rfloat kmax, int& code) const {
+        return prox_data(uh, u0[p], sL[p], sR[p], tau, h, kmax, code);
     }
-    __syncthreads();
-    // Phase B: q+ (old u) and p+ (extrapolated 2u+ - u) on the tile's edges.
-    const int i = threadIdx.x % kTX, j = threadIdx.x / kTX;
-    const int x = x0 + i, y = y0 + j;
-    if (x >= W || y >= H) return;
-    const long long p = (long long)y * W + x;
-    const rfloat uo = s_uo[j][i], un = s_un[j][i];
-    out.u[p] = un;
-    uint32_t m = (uint32_t)s_code[j][i];
-    int c;
-    if (x + 1 < W) {
-        const rfloat w = (rfloat)w_h[(long long)y * (W - 1) + x];
-        const rfloat gq = uo - s_uo[j][i + 1];
-        out.qh[p] = prox_conj(in.qh[p] + sc.tau * gq, w, 0.0, sc.beta_minus, sc.tau, c);
-        m |= (uint32_t)c << 4;
-        const rfloat gp = (2.0 * un - uo) - (2.0 * s_un[j][i + 1] - s_uo[j][i + 1]);
-        out.ph[p] = prox_conj(in.ph[p] + sc.sigma * gp, w, sc.eps, sc.delta, sc.sigma, c);
-        m |= (uint32_t)c << 10;
-    }
-    if (y + 1 < H) {
-        const rfloat w = (rfloat)w_v[p];
-        const rfloat gq = uo - s_uo[j + 1][i];
-        out.qv[p] = prox_conj(in.qv[p] + sc.tau * gq, w, 0.0, sc.beta_minus, sc.tau, c);
-        m |= (uint32_t)c << 7;
-        const rfloat gp = (2.0 * un - uo) - (2.0 * s_un[j + 1][i] - s_uo[j + 1][i]);
-        out.pv[p] = prox_conj(in.pv[p] + sc.sigma * gp, w, sc.eps, sc.delta, sc.sigma, c);
-        m |= (uint32_t)c << 13;
-    }
-    if (mask != nullptr) mask[p] = (uint16_t)m;
-}
+};
 
 __global__ __launch_bounds__(256) void pdhg_kernel(const RefineState in, RefineState out, const rfloat* __restrict__ u0,
                                                    const rfloat* __restrict__ sL, const rfloat* __restrict__ sR,
                                                    const float* __restrict__ w_h, const float* __restrict__ w_v, int W,
                                                    int H, int K, RefineScalars sc, uint16_t* __restrict__ mask) {
-    pdhg_tile(in, out, u0, sL, sR, w_h, w_v, W, H, K, sc, mask, blockIdx.x * kTX, blockIdx.y * kTY);
+    pdhg_tile(in, out, TwoSlopeProx{u0, sL, sR, sc.tau, sc.h}, w_h, w_v, W, H, K, sc, mask, blockIdx.x * kTX,
+              blockIdx.y * kTY);
 }
 
 // ------------------------------------------------------------------ batched forms
@@ -259,8 +175,8 @@ __global__ __launch_bounds__(256) void batched_pdhg_kernel(const RefBatchInst* _
                                                            RefineScalars sc) {
     const RefTile t = tiles[blockIdx.x];
     const RefBatchInst& in = insts[t.inst];
-    pdhg_tile(in.S[cur], in.S[cur ^ 1], in.u0, in.sL, in.sR, in.w_h, in.w_v, in.W, in.H, in.K, sc, nullptr,
-              t.bx * kTX, t.by * kTY);
+    pdhg_tile(in.S[cur], in.S[cur ^ 1], TwoSlopeProx{in.u0, in.sL, in.sR, sc.tau, sc.h}, in.w_h, in.w_v, in.W, in.H,
+              in.K, sc, nullptr, t.bx * kTX, t.by * kTY);
 }
 
 __global__ __launch_bounds__(256) void batched_narrow_kernel(const RefBatchInst* __restrict__ insts,

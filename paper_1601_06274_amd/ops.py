@@ -14,7 +14,8 @@ import torch
 from . import _lib as L
 
 __all__ = ["DiscreteResult", "solve_discrete", "discrete_params", "tile_for", "refine_params", "refine_continuous",
-           "build_cost_volume", "build_cost_volume_census", "lr_check"]
+           "build_cost_volume", "build_cost_volume_census", "lr_check", "build_flow_cost_volume", "flow_project",
+           "refine_flow", "solve_flow", "FlowResult"]
 
 
 def _ptr(t):
@@ -264,6 +265,101 @@ def lr_check(u_left, u_right, *, max_diff=1.0, invalid=-1.0, stream=None, out=No
                              _stream(stream))
     L.check("dm_lr_check", st)
     return out
+
+
+def _flow_shape(H, W, K1, K2, off1, off2):
+    return L.DmFlowShape(int(W), int(H), int(K1), int(K2), int(off1), int(off2))
+
+
+def build_flow_cost_volume(I1, I2, K1, K2, off1, off2, *, window=3, trunc=0.3, lambda_pw=0.1, contrast_sigma=0.1,
+                           dtype=torch.float32, stream=None, cost_out=None, w_h=None, w_v=None):
+    """Two-dimensional truncated SAD flow cost [H][W][K2][K1] and the contrast weights of I1
+    (dm_build_flow_cost_volume).  Label (i, j) is the displacement (i - off1, j - off2)."""
+    H, W = I1.shape
+    _check_dev("I1", I1, torch.float32, (H, W))
+    _check_dev("I2", I2, torch.float32, (H, W))
+    dev = I1.device
+    if cost_out is None:
+        cost_out = torch.empty((H, W, K2, K1), dtype=dtype, device=dev)
+    _check_dev("cost_out", cost_out, None, (H, W, K2, K1))
+    if w_h is None:
+        w_h = torch.empty((H, W - 1), dtype=torch.float32, device=dev)
+    if w_v is None:
+        w_v = torch.empty((H - 1, W), dtype=torch.float32, device=dev)
+    cp = L.DmCostParams(int(window), float(trunc), float(lambda_pw), float(contrast_sigma))
+    st = L.lib().dm_build_flow_cost_volume(_ptr(I1), _ptr(I2), _flow_shape(H, W, K1, K2, off1, off2), ctypes.byref(cp),
+                                           _cost_dtype(cost_out), _ptr(cost_out), _ptr(w_h), _ptr(w_v), _stream(stream))
+    L.check("dm_build_flow_cost_volume", st)
+    return cost_out, w_h, w_v
+
+
+def flow_project(cost, *, stream=None, f1=None, f2=None):
+    """Decoupled layer costs (dm_flow_project): f1 [H][W][K1] = min over the vertical label,
+    f2 [H][W][K2] = min over the horizontal label, in the cost dtype."""
+    H, W, K2, K1 = cost.shape
+    _check_dev("cost", cost)
+    if f1 is None:
+        f1 = torch.empty((H, W, K1), dtype=cost.dtype, device=cost.device)
+    if f2 is None:
+        f2 = torch.empty((H, W, K2), dtype=cost.dtype, device=cost.device)
+    _check_dev("f1", f1, cost.dtype, (H, W, K1))
+    _check_dev("f2", f2, cost.dtype, (H, W, K2))
+    st = L.lib().dm_flow_project(_ptr(cost), _cost_dtype(cost), _flow_shape(H, W, K1, K2, 0, 0), _ptr(f1), _ptr(f2),
+                                 _stream(stream))
+    L.check("dm_flow_project", st)
+    return f1, f2
+
+
+def refine_flow(cost, labels1, labels2, w_h, w_v, *, off1=0, off2=0, C=3.0, eps=1.0, delta=0.0, h=1.0, tau=0.3,
+                sigma=0.3, n_warps=5, n_iters=40, stream=None, workspace=None, u1_out=None, u2_out=None):
+    """Quadratic-fit refinement of both flow components (dm_refine_flow); returns (u1, u2)
+    in label units."""
+    H, W, K2, K1 = cost.shape
+    _check_dev("cost", cost)
+    _check_dev("labels1", labels1, torch.int32, (H, W))
+    _check_dev("labels2", labels2, torch.int32, (H, W))
+    _check_dev("w_h", w_h, torch.float32, (H, W - 1))
+    _check_dev("w_v", w_v, torch.float32, (H - 1, W))
+    p = refine_params(C, eps, delta, h, tau, sigma, n_warps, n_iters, False)
+    shape = _flow_shape(H, W, K1, K2, off1, off2)
+    lib = L.lib()
+    ws_bytes = max(int(lib.dm_refine_flow_workspace(shape, ctypes.byref(p))), 256)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=cost.device)
+    if u1_out is None:
+        u1_out = torch.empty((H, W), dtype=torch.float32, device=cost.device)
+    if u2_out is None:
+        u2_out = torch.empty((H, W), dtype=torch.float32, device=cost.device)
+    st = lib.dm_refine_flow(_ptr(cost), _cost_dtype(cost), _ptr(labels1), _ptr(labels2), _ptr(w_h), _ptr(w_v), shape,
+                            ctypes.byref(p), _ptr(u1_out), _ptr(u2_out), _ptr(workspace),
+                            ctypes.c_size_t(workspace.numel()), _stream(stream))
+    L.check("dm_refine_flow", st)
+    return u1_out, u2_out
+
+
+@dataclass
+class FlowResult:
+    f1: torch.Tensor
+    f2: torch.Tensor
+    layer1: DiscreteResult
+    layer2: DiscreteResult
+    u1: torch.Tensor           # [H][W] horizontal component, label units (displacement u1 - off1)
+    u2: torch.Tensor           # [H][W] vertical component, label units (displacement u2 - off2)
+
+
+def solve_flow(cost, w_h, w_v, *, off1=0, off2=0, T=3, n_iters=20, refine=None, stream=None, **discrete_kw):
+    """The flow pipeline on a [H][W][K2][K1] cost: decoupled layer costs, one Dual_MM solve per
+    layer, then the quadratic-fit refinement (dict of refine_flow parameters; None = the
+    defaults, False = none).  Composes the C calls only."""
+    f1, f2 = flow_project(cost, stream=stream)
+    r1 = solve_discrete(f1, w_h, w_v, T=T, n_iters=n_iters, stream=stream, **discrete_kw)
+    r2 = solve_discrete(f2, w_h, w_v, T=T, n_iters=n_iters, stream=stream, **discrete_kw)
+    if refine is False:
+        u1, u2 = r1.labels.float(), r2.labels.float()
+    else:
+        u1, u2 = refine_flow(cost, r1.labels, r2.labels, w_h, w_v, off1=off1, off2=off2, stream=stream,
+                             **(refine or {}))
+    return FlowResult(f1=f1, f2=f2, layer1=r1, layer2=r2, u1=u1, u2=u2)
 
 
 def profiler_enable(kinds=None):

@@ -41,6 +41,15 @@ def test_flow_cost_volume_true_shift():
     assert D.max() <= 0.3 + 1e-15 and D.min() >= 0.0
 
 
+def test_flow_cost_volume_row_band():
+    """A band of output rows equals the same rows of the whole volume."""
+    pair = synth.flow_pair(17, 9, 2.0, seed=8)
+    full = flow.flow_cost_volume(pair.first, pair.second, 5, 4, 2, 1)
+    for lo, hi in [(0, 1), (3, 6), (8, 9), (0, 9)]:
+        np.testing.assert_array_equal(flow.flow_cost_volume(pair.first, pair.second, 5, 4, 2, 1, rows=(lo, hi)),
+                                      full[lo:hi])
+
+
 def test_flow_cost_volume_hand_example():
     """2 x 3 images, one label pair, 3 x 3 clamped window, by hand."""
     A = np.array([[0.1, 0.2, 0.4], [0.3, 0.3, 0.0]])
