@@ -23,8 +23,8 @@
 //   flow_linearize_kernel: per pixel, L and the positive part of diag Q of the data term at
 //                         the current (u1, u2) by central differences of the bilinearly
 //                         interpolated table (FP64, like the stereo refinement).
-//   flow_pdhg_kernel    : the stereo refinement's iteration (pdhg.h) with the quadratic
-//                         prox, one component per blockIdx.z.
+//   flow_pdhg_kernel    : the stereo refinement's iteration (pdhg.h, several iterations per
+//                         launch) with the quadratic prox, one component per blockIdx.z.
 #include <algorithm>
 
 #include "common.h"
@@ -176,9 +176,16 @@ struct QuadProx {
     const rfloat* L;
     const rfloat* Q;
     rfloat tau, h;
+    struct Px {
+        rfloat u0, L, Q;
+    };
+    __device__ __forceinline__ Px load(long long p) const { return Px{u0[p], L[p], Q[p]}; }
     __device__ __forceinline__ rfloat operator()(rfloat uh, long long p, rfloat kmax, int& code) const {
-        const rfloat c = u0[p], q = Q[p];
-        rfloat v = (uh + tau * (q * c - L[p])) / (1.0 + tau * q);
+        return apply(uh, load(p), kmax, code);
+    }
+    __device__ __forceinline__ rfloat apply(rfloat uh, const Px& d, rfloat kmax, int& code) const {
+        const rfloat c = d.u0, q = d.Q;
+        rfloat v = (uh + tau * (q * c - d.L)) / (1.0 + tau * q);
         const rfloat lo = fmax(c - h, 0.0);
         const rfloat hi = fmin(c + h, kmax);
         int cl = 0;
@@ -195,10 +202,11 @@ struct QuadProx {
 };
 
 __global__ __launch_bounds__(256) void flow_pdhg_kernel(FlowComps fc, int cur, const float* __restrict__ w_h,
-                                                        const float* __restrict__ w_v, int W, int H, RefineScalars sc) {
+                                                        const float* __restrict__ w_v, int W, int H, RefineScalars sc,
+                                                        int n_iter) {
     const FlowComp& c = fc.c[blockIdx.z];
-    pdhg_tile(c.S[cur], c.S[cur ^ 1], QuadProx{c.u0, c.L, c.Q, sc.tau, sc.h}, w_h, w_v, W, H, c.K, sc, nullptr,
-              blockIdx.x * kTX, blockIdx.y * kTY);
+    pdhg_fused_tile<kFTX, kFTY, kFS>(c.S[cur], c.S[cur ^ 1], QuadProx{c.u0, c.L, c.Q, sc.tau, sc.h}, w_h, w_v, W, H,
+                                     c.K, sc, nullptr, 0, n_iter, blockIdx.x * kFTX, blockIdx.y * kFTY);
 }
 
 __global__ __launch_bounds__(256) void flow_init_kernel(const int* __restrict__ l1, const int* __restrict__ l2,
@@ -377,7 +385,7 @@ extern "C" int dm_refine_flow(const void* cost, dm_dtype cost_dtype, const int32
     hipLaunchKernelGGL(flow_init_kernel, dim3(eb), dim3(256), 0, stream, labels1, labels2, npx, fc);
     DM_HIP_TRY(hipGetLastError(), "flow refine init");
     const RefineScalars sc = refine_scalars(*p);
-    const dim3 grid((s.W + kTX - 1) / kTX, (s.H + kTY - 1) / kTY, 2);
+    const dim3 grid((s.W + kFTX - 1) / kFTX, (s.H + kFTY - 1) / kFTY, 2);
     int cur = 0;
     for (int wp = 0; wp < p->n_warps; ++wp) {
         ProfScope ps1(DM_PROF_REFINE_LINEARIZE, (double)npx * (16.0 + 20.0 * (cost_dtype == DM_F16 ? 2 : 4) + 48.0),
@@ -390,9 +398,10 @@ extern "C" int dm_refine_flow(const void* cost, dm_dtype cost_dtype, const int32
                                static_cast<const float*>(cost), npx, s.K1, s.K2, (rfloat)p->h, fc, cur);
         ps1.stop();
         DM_HIP_TRY(hipGetLastError(), "flow linearize");
-        for (int it = 0; it < p->n_iters; ++it) {
-            ProfScope ps2(DM_PROF_REFINE_ITER, 2.0 * npx * (8.0 * 13.0 + 8.0), stream);
-            hipLaunchKernelGGL(flow_pdhg_kernel, grid, dim3(256), 0, stream, fc, cur, w_h, w_v, s.W, s.H, sc);
+        for (int it0 = 0; it0 < p->n_iters; it0 += kFS) {
+            const int nit = std::min(kFS, p->n_iters - it0);
+            ProfScope ps2(DM_PROF_REFINE_ITER, 2.0 * nit * npx * (8.0 * 13.0 + 8.0), stream);
+            hipLaunchKernelGGL(flow_pdhg_kernel, grid, dim3(256), 0, stream, fc, cur, w_h, w_v, s.W, s.H, sc, nit);
             cur ^= 1;
         }
         DM_HIP_TRY(hipGetLastError(), "flow pdhg");

@@ -16,6 +16,9 @@
 // Kernels
 //   linearize_kernel : u0 := u, slopes (s_L, s_R) of the data term at u0 by linear
 //                      interpolation of the cost volume along the label axis (once per warp)
+//   pdhg_fused_kernel: kFS iterations per launch on a tile extended by kFS pixels, the state
+//                      in LDS between iterations (temporal tiling, pdhg.h); the single
+//                      instance's refinement.
 //   pdhg_kernel      : one full iteration.  A block owns a TX x TY tile; it first computes
 //                      u+ on the tile plus a one-pixel halo to the right and below (the
 //                      halo values are recomputed, not exchanged), keeps u and u+ in LDS,
@@ -34,6 +37,8 @@
 // linearisation into the cost volume and into u (linearize_adjoint_kernel).  At kinks
 // (exact ties of a branch test) the derivative of the branch that the forward took is
 // used; on the interpolated data term at integer arguments the segment [k, k+1].
+#include <algorithm>
+
 #include "common.h"
 #include "pdhg.h"
 #include "refine.h"
@@ -128,8 +133,15 @@ struct TwoSlopeProx {
     const rfloat* sL;
     const rfloat* sR;
     rfloat tau, h;
+    struct Px {
+        rfloat u0, sL, sR;
+    };
     __device__ __forceinline__ rfloat operator()(rfloat uh, long long p, rfloat kmax, int& code) const {
         return prox_data(uh, u0[p], sL[p], sR[p], tau, h, kmax, code);
+    }
+    __device__ __forceinline__ Px load(long long p) const { return Px{u0[p], sL[p], sR[p]}; }
+    __device__ __forceinline__ rfloat apply(rfloat uh, const Px& d, rfloat kmax, int& code) const {
+        return prox_data(uh, d.u0, d.sL, d.sR, tau, h, kmax, code);
     }
 };
 
@@ -139,6 +151,16 @@ __global__ __launch_bounds__(256) void pdhg_kernel(const RefineState in, RefineS
                                                    int H, int K, RefineScalars sc, uint16_t* __restrict__ mask) {
     pdhg_tile(in, out, TwoSlopeProx{u0, sL, sR, sc.tau, sc.h}, w_h, w_v, W, H, K, sc, mask, blockIdx.x * kTX,
               blockIdx.y * kTY);
+}
+
+__global__ __launch_bounds__(256) void pdhg_fused_kernel(const RefineState in, RefineState out,
+                                                         const rfloat* __restrict__ u0, const rfloat* __restrict__ sL,
+                                                         const rfloat* __restrict__ sR, const float* __restrict__ w_h,
+                                                         const float* __restrict__ w_v, int W, int H, int K,
+                                                         RefineScalars sc, uint16_t* __restrict__ mask0,
+                                                         size_t mask_stride, int n_iter) {
+    pdhg_fused_tile<kFTX, kFTY, kFS>(in, out, TwoSlopeProx{u0, sL, sR, sc.tau, sc.h}, w_h, w_v, W, H, K, sc, mask0,
+                                     mask_stride, n_iter, blockIdx.x * kFTX, blockIdx.y * kFTY);
 }
 
 // ------------------------------------------------------------------ batched forms
@@ -536,7 +558,7 @@ extern "C" int dm_refine_continuous(const void* cost, dm_dtype cost_dtype, const
     ps0.stop();
     DM_HIP_TRY(hipGetLastError(), "refine init");
     const RefineScalars sc = refine_scalars(*p);
-    const dim3 grid((s.W + kTX - 1) / kTX, (s.H + kTY - 1) / kTY);
+    const dim3 fgrid((s.W + kFTX - 1) / kFTX, (s.H + kFTY - 1) / kFTY);
     int cur = 0;
     for (int wp = 0; wp < p->n_warps; ++wp) {
         // with a tape, every warp keeps its own u0 (the adjoint needs it)
@@ -551,14 +573,16 @@ extern "C" int dm_refine_continuous(const void* cost, dm_dtype cost_dtype, const
                                S[cur].u, s.W, s.H, s.K, (rfloat)p->h, u0, sL, sR);
         ps1.stop();
         DM_HIP_TRY(hipGetLastError(), "linearize");
-        for (int it = 0; it < p->n_iters; ++it) {
-            uint16_t* mask = p->keep_tape ? reinterpret_cast<uint16_t*>(
-                                                ws + L.tape_mask + ((size_t)wp * p->n_iters + it) * L.mask_plane)
-                                          : nullptr;
-            // per pixel: reads u, u0, sL, sR, 4 duals, 2 weights; writes u and 4 duals
-            ProfScope ps2(DM_PROF_REFINE_ITER, npx * (8.0 * 13.0 + 8.0), stream);
-            hipLaunchKernelGGL(pdhg_kernel, grid, dim3(256), 0, stream, S[cur], S[cur ^ 1], u0, sL, sR, w_h, w_v, s.W,
-                               s.H, s.K, sc, mask);
+        // kFS iterations per launch, the state on chip in between
+        for (int it0 = 0; it0 < p->n_iters; it0 += kFS) {
+            const int nit = std::min(kFS, p->n_iters - it0);
+            uint16_t* mask0 = p->keep_tape ? reinterpret_cast<uint16_t*>(
+                                                 ws + L.tape_mask + ((size_t)wp * p->n_iters + it0) * L.mask_plane)
+                                           : nullptr;
+            // per pixel and iteration: reads u, u0, sL, sR, 4 duals, 2 weights; writes u and 4 duals
+            ProfScope ps2(DM_PROF_REFINE_ITER, nit * npx * (8.0 * 13.0 + 8.0), stream);
+            hipLaunchKernelGGL(pdhg_fused_kernel, fgrid, dim3(256), 0, stream, S[cur], S[cur ^ 1], u0, sL, sR, w_h,
+                               w_v, s.W, s.H, s.K, sc, mask0, L.mask_plane / sizeof(uint16_t), nit);
             cur ^= 1;
         }
         DM_HIP_TRY(hipGetLastError(), "pdhg");
