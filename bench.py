@@ -139,10 +139,11 @@ def _timed(fn, reps, torch):
     return (time.perf_counter() - t0) * 1e3 / reps
 
 
-def batched_extra(torch, ops, dev, n=64, seed=4000, n_iters=20, T=3, reps=3):
+def batched_extra(torch, ops, dev, n=64, seed=4000, n_iters=20, T=3, warps=5, iters=40, reps=3):
     """64 uneven instances (W in [160, 1280], H in [120, 720], K in {32, 64, 128, 192}) of
-    the stereo generator: the batched plan (FP16 cost, one hipGraph launch) against the
-    plain single-instance FP32 forward on the same GPU, Dual_MM 20 iterations each."""
+    the stereo generator: the batched plan (FP16 cost, one hipGraph launch: Dual_MM 20
+    iterations, labels and bounds of every instance, refinement 5 x 40) against the plain
+    single-instance FP32 forward of the same work on the same GPU."""
     import synth
     specs = synth.batch_specs(n, seed=seed)
     inst16, inst32 = [], []
@@ -156,27 +157,37 @@ def batched_extra(torch, ops, dev, n=64, seed=4000, n_iters=20, T=3, reps=3):
         inst32.append(dict(cost=c32, w_h=wh, w_v=wv))
     nodes = sum(sp.W * sp.H * sp.K for sp in specs)
     updates = nodes * (8 * n_iters + 2)
+    rkw = dict(C=3.0, n_warps=warps, n_iters=iters)
     t0 = time.perf_counter()
-    plan = ops.BatchedPlan(inst16, T=T, n_iters=n_iters)
+    plan = ops.BatchedPlan(inst16, T=T, n_iters=n_iters, refine=rkw)
     plan_s = time.perf_counter() - t0
     try:
         ms_b = _timed(plan.run, reps, torch)
         dev_gb = plan.device_bytes / 1e9
+        lb_le_e = bool(all(float(d["bounds"][0]) <= float(d["bounds"][1]) + 1e-6 * abs(float(d["bounds"][1]))
+                           for d in plan.instances))
     finally:
         plan.close()
-    ws = None
+    ws, rws = None, None
     duals = [torch.empty(d["cost"].shape, dtype=torch.float32, device=dev) for d in inst32]
+    bounds = [torch.empty(2, dtype=torch.float64, device=dev) for _ in inst32]
 
     def plain():
-        nonlocal ws
-        for d, lam in zip(inst32, duals):
+        nonlocal ws, rws
+        for d, lam, b in zip(inst32, duals, bounds):
             r = ops.solve_discrete(d["cost"], d["w_h"], d["w_v"], T=T, n_iters=n_iters, dual=lam, workspace=ws,
-                                   want_bounds=False, want_minmarg=False)
+                                   want_bounds=True, want_minmarg=False)
             if ws is None or r.workspace.numel() > ws.numel():
                 ws = r.workspace
+            b.copy_(r.bounds)
+            need = ops.refine_workspace_bytes(tuple(d["cost"].shape), **rkw)
+            if rws is None or rws.numel() < need:
+                rws = torch.empty(need, dtype=torch.uint8, device=dev)
+            ops.refine_continuous(d["cost"], r.labels, d["w_h"], d["w_v"], workspace=rws, **rkw)
     ms_p = _timed(plain, reps, torch)
     return {"workload": f"{n} uneven stereo instances, W in [160,1280], H in [120,720], K in {{32,64,128,192}}, "
-                        f"seed {seed}; Dual_MM {n_iters} its, T={T}",
+                        f"seed {seed}; Dual_MM {n_iters} its, T={T}, labels and bounds; refinement {warps}x{iters}",
+            "bounds_lb_le_e_all": lb_le_e,
             "label_nodes": nodes, "plan_build_s": plan_s, "plan_device_GB": dev_gb,
             "batched_fp16_ms": ms_b, "batched_fp16_updates_per_s": updates / (ms_b * 1e-3),
             "plain_fp32_ms": ms_p, "plain_fp32_updates_per_s": updates / (ms_p * 1e-3),

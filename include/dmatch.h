@@ -373,7 +373,10 @@ int dm_refine_flow(const void* cost, dm_dtype cost_dtype, const int32_t* labels1
  * instance buffer, which must stay valid and at the same addresses.
  * dm_run_batched replays the graph on hip_stream.  Instances with warm_start = 0 get
  * dual := 0 at the start of every run.  All instances share the cost dtype and the
- * parameters.  No bounds / min-marginals are produced in this form.
+ * parameters.  An instance with a bounds buffer gets, per run, its lower bound (the
+ * row optima of the final pass plus the column optima at the final dual, eq. DD-dual)
+ * and the energy of its labels, FP64, the same quantities as dm_solve_discrete's
+ * bounds_out (sums in another fixed order).  No min-marginals in this form.
  * ------------------------------------------------------------------------------- */
 typedef struct {
     dm_shape s;
@@ -383,6 +386,7 @@ typedef struct {
     int32_t* labels;       /* [H][W] output                                         */
     float* dual;           /* [H][W][K] dual state                                  */
     float* u;              /* [H][W] refined disparities (required with refinement) */
+    double* bounds;        /* device [2] = {LB, E(labels)} per run, or NULL          */
 } dm_instance;
 
 int dm_plan_batched(const dm_instance* inst, int n, dm_dtype cost_dtype, const dm_discrete_params* p,

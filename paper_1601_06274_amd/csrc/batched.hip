@@ -48,6 +48,74 @@ __global__ void zero_dual_kernel(const InstDesc* __restrict__ insts, int n) {
     }
 }
 
+// Energy of every instance's labels (one with a bounds buffer): FP64 partial sums per
+// (instance, block) in a fixed order, as energy_partial_kernel for one instance.
+template <typename TT>
+__global__ __launch_bounds__(256) void batch_energy_kernel(const InstDesc* __restrict__ insts, int T,
+                                                           double* __restrict__ partial) {
+    __shared__ double sh[256];
+    const InstDesc in = insts[blockIdx.y];
+    double acc = 0.0;
+    if (in.bounds != nullptr) {
+        const TT* theta = static_cast<const TT*>(in.theta);
+        const int W = in.W, H = in.H, K = in.K;
+        const long long npx = (long long)W * H;
+        for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npx;
+             p += (long long)gridDim.x * blockDim.x) {
+            const int y = (int)(p / W), x = (int)(p % W);
+            const int l = min(max(in.labels[p], 0), K - 1);
+            acc += (double)to_f<TT>(theta[p * K + l]);
+            if (x + 1 < W) {
+                const int d = abs(l - min(max(in.labels[p + 1], 0), K - 1));
+                acc += (double)in.w_h[(long long)y * (W - 1) + x] * (double)(d < T ? d : T);
+            }
+            if (y + 1 < H) {
+                const int d = abs(l - min(max(in.labels[p + W], 0), K - 1));
+                acc += (double)in.w_v[p] * (double)(d < T ? d : T);
+            }
+        }
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = sh[0];
+}
+
+__device__ double batch_block_sum(const double* __restrict__ v, int n, double* sh) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += v[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// bounds = {sum of row optima + sum of column optima, sum of the energy partials}, one
+// block per instance (the lower bound of eq. DD-dual at the final dual).
+__global__ __launch_bounds__(256) void batch_bounds_kernel(const InstDesc* __restrict__ insts,
+                                                           const double* __restrict__ partial, int n_part) {
+    __shared__ double sh[256];
+    const InstDesc in = insts[blockIdx.x];
+    if (in.bounds == nullptr) return;  // uniform over the block
+    const double a = batch_block_sum(in.opt_rows, in.H, sh);
+    const double b = batch_block_sum(in.opt_cols, in.W, sh);
+    const double e = batch_block_sum(partial + (long long)blockIdx.x * n_part, n_part, sh);
+    if (threadIdx.x == 0) {
+        in.bounds[0] = a + b;
+        in.bounds[1] = e;
+    }
+}
+
+constexpr int kBatchEnergyBlocks = 32;  // energy partial sums per instance
+
 struct Class {
     int family, G, LPL;
     bool full;
@@ -168,11 +236,21 @@ extern "C" int dm_plan_batched(const dm_instance* inst, int n, dm_dtype cost_dty
 
     // 2. device instance table and message scratch
     std::vector<InstDesc> hd(n);
-    size_t msg_total = 0;
-    for (int i = 0; i < n; ++i) msg_total += align_up((size_t)inst[i].s.W * inst[i].s.H * inst[i].s.K * 4, 256);
+    size_t msg_total = 0, opt_total = 0;
+    bool any_bounds = false;
+    for (int i = 0; i < n; ++i) {
+        msg_total += align_up((size_t)inst[i].s.W * inst[i].s.H * inst[i].s.K * 4, 256);
+        if (inst[i].bounds != nullptr) {
+            any_bounds = true;
+            opt_total += (size_t)inst[i].s.W + inst[i].s.H;
+        }
+    }
     char* msg_pool = plan->alloc<char>(msg_total);
     InstDesc* d_insts = plan->alloc<InstDesc>(n);
-    if (!msg_pool || !d_insts) return fail("allocation", hipErrorOutOfMemory);
+    double* opt_pool = any_bounds ? plan->alloc<double>(opt_total) : nullptr;
+    double* partial = any_bounds ? plan->alloc<double>((size_t)n * kBatchEnergyBlocks) : nullptr;
+    if (!msg_pool || !d_insts || (any_bounds && (!opt_pool || !partial))) return fail("allocation", hipErrorOutOfMemory);
+    size_t opt_off = 0;
     size_t off = 0;
     for (int i = 0; i < n; ++i) {
         const dm_instance& I = inst[i];
@@ -185,6 +263,13 @@ extern "C" int dm_plan_batched(const dm_instance* inst, int n, dm_dtype cost_dty
         d.w_h = I.w_h;
         d.w_v = I.w_v;
         d.labels = I.labels;
+        d.bounds = I.bounds;
+        d.opt_rows = d.opt_cols = nullptr;
+        if (I.bounds != nullptr) {
+            d.opt_rows = opt_pool + opt_off;
+            d.opt_cols = opt_pool + opt_off + I.s.H;
+            opt_off += (size_t)I.s.W + I.s.H;
+        }
         d.W = I.s.W;
         d.H = I.s.H;
         d.K = I.s.K;
@@ -232,7 +317,7 @@ extern "C" int dm_plan_batched(const dm_instance* inst, int n, dm_dtype cost_dty
     }
     const int S = p->n_half_steps > 0 ? p->n_half_steps : 2 * p->n_iters;
     const int n_cls = (int)plan->classes.size();
-    const long long n_counters = (long long)(S + 1) * n_cls;
+    const long long n_counters = (long long)(S + 2) * n_cls;
     int* counters = plan->alloc<int>(n_counters);
     if (!counters) return fail("allocation", hipErrorOutOfMemory);
 
@@ -332,7 +417,7 @@ extern "C" int dm_plan_batched(const dm_instance* inst, int n, dm_dtype cost_dty
         hipLaunchKernelGGL(zero_dual_kernel, dim3(256, std::min(n, 64)), dim3(256), 0, main_s, d_insts, n);
         note(hipGetLastError());
     }
-    auto launch_step = [&](int slot, int family, int mode) {
+    auto launch_step = [&](int slot, int family, int mode, bool want_opt) {
         // fork: every class of this family on its own side stream
         note(hipEventRecord(ev_fork, main_s));
         int used = 0;
@@ -348,6 +433,7 @@ extern "C" int dm_plan_batched(const dm_instance* inst, int n, dm_dtype cost_dty
             bl.counter = counters + (long long)slot * n_cls + ci;
             bl.family = family;
             bl.mode = mode;
+            bl.want_opt = want_opt ? 1 : 0;
             bl.T = p->trunc_T;
             bl.n_pass = p->max_pass;
             for (int g = 0; g < 8; ++g) bl.gamma[g] = p->gamma[g];
@@ -361,8 +447,23 @@ extern "C" int dm_plan_batched(const dm_instance* inst, int n, dm_dtype cost_dty
         }
     };
     const int mode = p->minorant == DM_MINORANT_NAIVE ? kModeNaive : kModeIterative;
-    for (int k = 0; k < S; ++k) launch_step(k, k % 2, mode);
-    launch_step(S, 0, kModeFinal);
+    // with bounds: the column optima at the final dual come from the last vertical
+    // half-step when it is the last half-step (its family's optimum is unchanged by it),
+    // else from a column optimum pass; the row optima from the final pass
+    for (int k = 0; k < S; ++k) launch_step(k, k % 2, mode, any_bounds && k == S - 1 && k % 2 == 1);
+    launch_step(S, 0, kModeFinal, any_bounds);
+    if (any_bounds) {
+        if (S == 0 || S % 2 == 1) launch_step(S + 1, 1, kModeOptimum, true);
+        if (cost_dtype == DM_F16)
+            hipLaunchKernelGGL(batch_energy_kernel<_Float16>, dim3(kBatchEnergyBlocks, n), dim3(256), 0, main_s,
+                               d_insts, p->trunc_T, partial);
+        else
+            hipLaunchKernelGGL(batch_energy_kernel<float>, dim3(kBatchEnergyBlocks, n), dim3(256), 0, main_s,
+                               d_insts, p->trunc_T, partial);
+        note(hipGetLastError());
+        hipLaunchKernelGGL(batch_bounds_kernel, dim3(n), dim3(256), 0, main_s, d_insts, partial, kBatchEnergyBlocks);
+        note(hipGetLastError());
+    }
     if (rp != nullptr) note(launch_batched_refine(d_rinst, d_chunks, n_chunks, d_tiles, n_tiles, cost_dtype, *rp, main_s));
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(main_s, &graph);

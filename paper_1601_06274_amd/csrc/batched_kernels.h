@@ -20,6 +20,9 @@ struct InstDesc {
     const float* w_h;       // [H][W-1]
     const float* w_v;       // [H-1][W]
     int* labels;            // [H][W]
+    double* opt_rows;       // [H] row chain optima (plan scratch; null without bounds)
+    double* opt_cols;       // [W] column chain optima
+    double* bounds;         // [2] = {LB, E(labels)} or null
     int W, H, K;
     unsigned vol_bytes_f32, vol_bytes_theta, wh_bytes, wv_bytes;
 };
@@ -36,6 +39,7 @@ struct BatchLaunch {
     int* counter;           // zeroed before the launch
     int family;             // 0: rows (horizontal), 1: columns (vertical)
     int mode, T, n_pass;
+    int want_opt;           // store each chain's optimum into opt_rows / opt_cols
     float gamma[8];
 };
 
@@ -49,7 +53,7 @@ __device__ __forceinline__ SweepArgs batch_args(const InstDesc& in, const BatchL
     a.w = rows ? in.w_h : in.w_v;
     a.minmarg = nullptr;
     a.labels = in.labels;
-    a.opt = nullptr;
+    a.opt = bl.want_opt ? (rows ? in.opt_rows : in.opt_cols) : nullptr;
     a.chain_px = rows ? in.W : 1;
     a.node_px = rows ? 1 : in.W;
     a.w_chain = rows ? in.W - 1 : 1;
@@ -91,8 +95,9 @@ __global__ __launch_bounds__(64) void batched_sweep_kernel(BatchLaunch bl) {
 
 template <int G, int LPL>
 hipError_t launch_batched_tile(const BatchLaunch& bl, bool full, dm_dtype dt, int workers, hipStream_t st) {
-    // family 0 reads the cost; the final pass is a row pass
+    // family 0 reads the cost; the final pass is a row pass, the optimum pass a column pass
     const bool final_pass = bl.mode == kModeFinal;
+    const bool opt_pass = bl.mode == kModeOptimum;
 #define DM_BATCH_LAUNCH(TT, FULLV, HT, MGV)                                                                      \
     hipLaunchKernelGGL((batched_sweep_kernel<G, LPL, kPF, TT, FULLV, HT, MGV>), dim3(workers), dim3(64), 0, st, bl)
     if (bl.family == 0) {
@@ -114,8 +119,13 @@ hipError_t launch_batched_tile(const BatchLaunch& bl, bool full, dm_dtype dt, in
             }
         }
     } else {
-        if (full) DM_BATCH_LAUNCH(float, true, false, kGroupHalfStep);
-        else DM_BATCH_LAUNCH(float, false, false, kGroupHalfStep);
+        if (full) {
+            if (opt_pass) DM_BATCH_LAUNCH(float, true, false, kGroupOptimum);
+            else DM_BATCH_LAUNCH(float, true, false, kGroupHalfStep);
+        } else {
+            if (opt_pass) DM_BATCH_LAUNCH(float, false, false, kGroupOptimum);
+            else DM_BATCH_LAUNCH(float, false, false, kGroupHalfStep);
+        }
     }
 #undef DM_BATCH_LAUNCH
     return hipGetLastError();

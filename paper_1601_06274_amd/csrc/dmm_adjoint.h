@@ -964,19 +964,10 @@ __device__ __forceinline__ void adjoint_pass(AW& wk, const unsigned* tape, unsig
     }
 }
 
-template <int G, int LPL, int PF, typename TT, bool FULL, bool HAS_THETA, bool TAPE>
-__global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
-    using AW = AdjWalker<G, LPL, PF, TT, FULL, HAS_THETA>;
-    // LDS for the recomputing form's long-reach message adjoint (unused with a tape)
-    __shared__ float s_v[TAPE ? 1 : 64 * LPL];
-    __shared__ float s_cb[TAPE ? 1 : 64 * LPL];
-    __shared__ int s_src[TAPE ? 1 : 64 * LPL];
-    constexpr int CPW = 64 / G;
-    const int lane = threadIdx.x;
-    const int sub = lane % G;
-    const int grp = lane / G;
-    const int chain = blockIdx.x * CPW + grp;
-    AW wk(a, chain, sub, grp, s_v, s_cb, s_src);
+// The adjoint passes of one launch (a half-step's, or the final row pass's) for the chain
+// walked by `wk` (an AdjWalker, or a walker of the same interface).
+template <bool TAPE, class AW>
+__device__ __forceinline__ void run_adjoint_walker(const AdjArgs& a, AW& wk) {
     const unsigned vb = a.vol_bytes_f32;
     const unsigned tb = a.tape_bytes;
     if (a.mode == kModeFinal) {
@@ -1037,6 +1028,22 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
     wk.r_bin = make_rsrc(a.bbar[0], vb);
     wk.r_bout = make_rsrc(nullptr, 0u);
     adjoint_pass<TAPE, false, kAdjR0, false>(wk, a.tape[0], tb, 0.0f);
+}
+
+template <int G, int LPL, int PF, typename TT, bool FULL, bool HAS_THETA, bool TAPE>
+__global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs a) {
+    using AW = AdjWalker<G, LPL, PF, TT, FULL, HAS_THETA>;
+    // LDS for the recomputing form's long-reach message adjoint (unused with a tape)
+    __shared__ float s_v[TAPE ? 1 : 64 * LPL];
+    __shared__ float s_cb[TAPE ? 1 : 64 * LPL];
+    __shared__ int s_src[TAPE ? 1 : 64 * LPL];
+    constexpr int CPW = 64 / G;
+    const int lane = threadIdx.x;
+    const int sub = lane % G;
+    const int grp = lane / G;
+    const int chain = blockIdx.x * CPW + grp;
+    AW wk(a, chain, sub, grp, s_v, s_cb, s_src);
+    run_adjoint_walker<TAPE>(a, wk);
 }
 
 constexpr int kAdjPF = 4;      // recomputing form: a node's ring slot holds cost, dual and two messages

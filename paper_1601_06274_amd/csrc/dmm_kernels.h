@@ -810,10 +810,10 @@ struct Walker {
 // plain half-step).
 enum ModeGroup : int { kGroupHalfStep = 0, kGroupFinal = 1, kGroupOptimum = 2, kGroupRecord = 3, kGroupTape = 4 };
 
-// All passes of one mode group for the chain owned by this lane group.
-template <int G, int LPL, int PF, typename TT, bool FULL, bool HAS_THETA, int MG>
-__device__ __forceinline__ void run_chain(const SweepArgs& a, int chain, int sub) {
-    Walker<G, LPL, PF, TT, FULL, HAS_THETA> wk(a, chain, sub);
+// All passes of one mode group for the chain walked by `wk` (a Walker, or a walker of
+// the same interface); `writer`: this lane stores the chain optimum.
+template <int MG, class WK>
+__device__ __forceinline__ void run_walker(const SweepArgs& a, WK& wk, int chain, bool writer) {
     double opt = 0.0;
     if constexpr (MG == kGroupHalfStep) {
         // R0 and the first update pass read lam_in; update passes write lam
@@ -894,7 +894,14 @@ __device__ __forceinline__ void run_chain(const SweepArgs& a, int chain, int sub
                 wk.template run_pass<false, 1, TP>(g, keep_msg, opt);
         }
     }
-    if (a.opt != nullptr && wk.ok && sub == 0) a.opt[chain] = opt;
+    if (a.opt != nullptr && wk.ok && writer) a.opt[chain] = opt;
+}
+
+// All passes of one mode group for the chain owned by this lane group.
+template <int G, int LPL, int PF, typename TT, bool FULL, bool HAS_THETA, int MG>
+__device__ __forceinline__ void run_chain(const SweepArgs& a, int chain, int sub) {
+    Walker<G, LPL, PF, TT, FULL, HAS_THETA> wk(a, chain, sub);
+    run_walker<MG>(a, wk, chain, sub == 0);
 }
 
 template <int G, int LPL, int PF, typename TT, bool FULL, bool HAS_THETA, int MG>

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import dmm as odmm, refine as oref
+from oracle import dmm as odmm, energy as oenergy, refine as oref
 from tests.parity import MM_RTOL, check_labels
 
 torch = pytest.importorskip("torch")
@@ -38,24 +38,29 @@ def _instances(specs, dtype=torch.float32):
 SPECS = [(7, 11, 8, 1), (12, 5, 32, 2), (3, 30, 20, 3), (16, 16, 64, 4), (9, 23, 8, 5), (1, 17, 5, 6), (13, 1, 4, 7)]
 
 
-@pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
-def test_batched_equals_single_instance_bitwise(dtype):
+@pytest.mark.parametrize("dtype,half", [(torch.float32, 0), (torch.float16, 0), (torch.float16, 5)])
+def test_batched_equals_single_instance_bitwise(dtype, half):
+    """Labels, duals and the lower bound bit for bit (the same chain optima summed in the
+    same order); the energy of the labels to FP64 rounding (partial sums in another
+    order).  half = 5: the last half-step is a row one, so the column optima come from
+    the plan's column optimum pass."""
     ops = _need()
     insts = _instances(SPECS, dtype)
-    print(f"[case] batched {len(insts)} instances {dtype}", flush=True)
+    print(f"[case] batched {len(insts)} instances {dtype} half-steps {half}", flush=True)
     tiles = {}
     for d in insts:
         K = d["cost"].shape[2]
         tiles[K] = ops.tile_for(K)
     # one fixed tile per K: give the plan the per-K default through single-K batches
     plan = ops.BatchedPlan([{k: d[k] for k in ("cost", "w_h", "w_v")} for d in insts], T=3, n_iters=3,
-                           tile=None)
+                           n_half_steps=half, tile=None)
     try:
         singles = []
         for d in insts:
             K = d["cost"].shape[2]
             tr, tc = ops.autotune_tiles(tuple(d["cost"].shape), dtype, T=3)
-            singles.append(ops.solve_discrete(d["cost"], d["w_h"], d["w_v"], T=3, n_iters=3, tile=(tr, tc)))
+            singles.append(ops.solve_discrete(d["cost"], d["w_h"], d["w_v"], T=3, n_iters=3, n_half_steps=half,
+                                              tile=(tr, tc)))
         torch.cuda.synchronize()
         for rep in range(3):
             plan.run()
@@ -64,6 +69,9 @@ def test_batched_equals_single_instance_bitwise(dtype):
             for i, (pi, s) in enumerate(zip(plan.instances, singles)):
                 assert torch.equal(pi["labels"], s.labels), f"replay {rep} instance {i} labels"
                 assert torch.equal(pi["dual"], s.dual), f"replay {rep} instance {i} dual"
+                b, bs = pi["bounds"].cpu().numpy(), s.bounds.cpu().numpy()
+                assert b[0] == bs[0], f"replay {rep} instance {i} lower bound {b[0]} vs {bs[0]}"
+                assert b[1] == pytest.approx(bs[1], rel=1e-12, abs=1e-12), f"replay {rep} instance {i} energy"
     finally:
         plan.close()
 
@@ -84,6 +92,12 @@ def test_batched_oracle_parity_and_refinement():
             ndiff, nbad = check_labels(lab, ref.labels, ref.minmarg, th)
             assert nbad == 0
             np.testing.assert_allclose(pi["dual"].cpu().numpy(), ref.lam, atol=1e-4)
+            # bounds against the oracle's lower bound and the FP64 energy of the GPU labels
+            b = pi["bounds"].cpu().numpy()
+            scale = max(abs(ref.lower_bound), 1.0)
+            assert abs(b[0] - ref.lower_bound) <= 1e-5 * scale
+            assert b[1] == pytest.approx(oenergy.grid_energy(th, d["wh"], d["wv"], 2, lab), rel=1e-9, abs=1e-9)
+            assert b[0] <= b[1] + 1e-6 * scale
             P32 = oref.RefineParams(C=2.0, tau=float(np.float32(0.3)), sigma=float(np.float32(0.3)), n_warps=2,
                                     n_iters=10)
             u_ref = oref.refine_continuous(th, d["wh"], d["wv"], lab, P32)

@@ -49,7 +49,7 @@ def _dev(a, dtype=torch.float32):
 
 
 def _discrete_case(H, W, K, T, n_iters, seed, *, minorant="iterative", gammas=(0.25, 0.25, 1.0), g_lb=0.7,
-                   g_e=0.3, n_half=0, tile=None, dirs=4, cost_dtype=torch.float32):
+                   g_e=0.3, n_half=0, tile=None, dirs=4, cost_dtype=torch.float32, keep=True):
     ops = _need()
     theta, w_h, w_v = synth.tiny_instance(H, W, K, seed=seed, w_max=0.5)
     th = _dev(theta, cost_dtype)
@@ -59,9 +59,10 @@ def _discrete_case(H, W, K, T, n_iters, seed, *, minorant="iterative", gammas=(0
     print(f"[case] discrete grad {H}x{W}x{K} T={T} iters={n_iters} half={n_half} {minorant} tile={tile} "
           f"{cost_dtype}", flush=True)
     kw = dict(T=T, n_iters=n_iters, n_half_steps=n_half, minorant=minorant, gammas=gammas, tile=tile)
-    res = ops.solve_discrete(th, _dev(w_h), _dev(w_v), keep_checkpoints=True, **kw)
+    res = ops.solve_discrete(th, _dev(w_h), _dev(w_v), keep_checkpoints=keep, **kw)
     gc, gwh, gwv = ops.solve_discrete_backward(th, _dev(w_h), _dev(w_v), res.dual, res.workspace,
-                                               grad_minmarg=_dev(Gm), grad_lb=g_lb, grad_energy=g_e, **kw)
+                                               grad_minmarg=_dev(Gm), grad_lb=g_lb, grad_energy=g_e,
+                                               keep_checkpoints=keep, **kw)
     torch.cuda.synchronize()
     gc, gwh, gwv = gc.cpu().numpy().astype(np.float64), gwh.cpu().numpy().astype(np.float64), \
         gwv.cpu().numpy().astype(np.float64)
