@@ -198,10 +198,11 @@ def diff_extra(torch, ops, dev, n=8, W=960, H=320, K=96, n_iters=20, T=3, warps=
                n_streams=8):
     """Differentiation workload: a batch of 8 frames 960x320, K=96, FP16 cost; forward
     (Dual_MM 20 its keeping the selection tapes + refinement 1 x 50 steps) and backward
-    (dL/dcost, dL/dw) per frame.  One frame fills only a few hundred waves, so the batch
-    runs on n_streams streams (default priority; frames round-robin, each stream with its
-    own workspaces).  Reported against the plain FP32 forward of the same frames, one
-    frame after another and on the same streams."""
+    (dL/dcost, dL/dw) of every frame as one batched plan (dm_plan_batched_grad: one
+    hipGraph, frames on n_streams forked streams, each frame advancing on its own).
+    Reported against the plain FP32 forward of the same frames (Dual_MM + refinement),
+    one frame after another and on the same number of streams, and against the same
+    forward + backward calls made eagerly one frame after another."""
     import ctypes
     import synth
     import paper_1601_06274_amd as P
@@ -215,87 +216,104 @@ def diff_extra(torch, ops, dev, n=8, W=960, H=320, K=96, n_iters=20, T=3, warps=
         frames.append((c16, c32, wh, wv))
     dkw = dict(T=T, n_iters=n_iters)
     rkw = dict(C=3.0, n_warps=warps, n_iters=iters)
+    gen = torch.Generator(device=dev).manual_seed(seed)
+    G_m = torch.randn((H, W, K), generator=gen, device=dev)
+    G_u = torch.randn((H, W), generator=gen, device=dev)
+    G_b = torch.tensor([1.0, 0.0], dtype=torch.float64, device=dev)
+
+    t0 = time.perf_counter()
+    plan = ops.BatchedGradPlan([dict(cost=c16, w_h=wh, w_v=wv, grad_minmarg=G_m, grad_bounds=G_b, grad_u=G_u)
+                                for c16, _, wh, wv in frames], keep_checkpoints=2, refine=rkw, n_streams=n_streams,
+                               **dkw)
+    plan_s = time.perf_counter() - t0
+    try:
+        ms_fb = _timed(plan.run, reps, torch)
+        plan_gb = plan.device_bytes / 1e9
+        # dL/dlambda_pw: the weights are lambda_pw * exp(...), so sum(dL/dw * w) / lambda_pw
+        grad_lpw = [(d["grad_w_h"] * d["w_h"]).sum() + (d["grad_w_v"] * d["w_v"]).sum() for d in plan.instances]
+        finite = bool(all(torch.isfinite(g).item() for g in grad_lpw) and
+                      all(bool(torch.isfinite(d["grad_cost"]).all()) for d in plan.instances))
+    finally:
+        plan.close()
+
+    # the same calls made eagerly, one frame after another on one stream
     lib = P.lib()
     shp = P._lib.DmShape(W, H, K)
     dp = ops.discrete_params(keep_checkpoints=2, **dkw)
     rp = ops.refine_params(keep_tape=True, **rkw)
-    gen = torch.Generator(device=dev).manual_seed(seed)
-    G_m = torch.randn((H, W, K), generator=gen, device=dev)
-    G_u = torch.randn((H, W), generator=gen, device=dev)
+    b = dict(ws_d=torch.empty(lib.dm_solve_discrete_workspace(shp, P._lib.DM_F16, ctypes.byref(dp)), dtype=torch.uint8,
+                              device=dev),
+             ws_db=torch.empty(lib.dm_solve_discrete_backward_workspace(shp, ctypes.byref(dp)), dtype=torch.uint8,
+                               device=dev),
+             ws_r=torch.empty(lib.dm_refine_continuous_workspace(shp, ctypes.byref(rp)), dtype=torch.uint8, device=dev),
+             ws_rb=torch.empty(lib.dm_refine_continuous_backward_workspace(shp, ctypes.byref(rp)), dtype=torch.uint8,
+                               device=dev),
+             dual=torch.empty((H, W, K), dtype=torch.float32, device=dev),
+             mm=torch.empty((H, W, K), dtype=torch.float32, device=dev),
+             gc=torch.empty((H, W, K), dtype=torch.float32, device=dev),
+             lab=torch.empty((H, W), dtype=torch.int32, device=dev), u=torch.empty((H, W), dtype=torch.float32,
+                                                                                  device=dev),
+             gwh=torch.empty((H, W - 1), dtype=torch.float32, device=dev),
+             gwv=torch.empty((H - 1, W), dtype=torch.float32, device=dev))
 
-    def buffers():
-        b = dict(ws_d=torch.empty(lib.dm_solve_discrete_workspace(shp, P._lib.DM_F16, ctypes.byref(dp)),
-                                  dtype=torch.uint8, device=dev),
-                 ws_db=torch.empty(lib.dm_solve_discrete_backward_workspace(shp, ctypes.byref(dp)), dtype=torch.uint8,
-                                   device=dev),
-                 ws_r=torch.empty(lib.dm_refine_continuous_workspace(shp, ctypes.byref(rp)), dtype=torch.uint8,
-                                  device=dev),
-                 ws_rb=torch.empty(lib.dm_refine_continuous_backward_workspace(shp, ctypes.byref(rp)),
-                                   dtype=torch.uint8, device=dev))
-        b["dual"] = torch.empty((H, W, K), dtype=torch.float32, device=dev)
-        b["mm"] = torch.empty_like(b["dual"])
-        b["gc"] = torch.empty_like(b["dual"])
-        b["lab"] = torch.empty((H, W), dtype=torch.int32, device=dev)
-        b["u"] = torch.empty((H, W), dtype=torch.float32, device=dev)
-        b["gwh"] = torch.empty((H, W - 1), dtype=torch.float32, device=dev)
-        b["gwv"] = torch.empty((H - 1, W), dtype=torch.float32, device=dev)
-        b["ws32"] = None
-        return b
+    def eager_fwd_bwd():
+        for c16, _, wh, wv in frames:
+            ops.solve_discrete(c16, wh, wv, dual=b["dual"], workspace=b["ws_d"], labels=b["lab"], minmarg=b["mm"],
+                               want_bounds=True, keep_checkpoints=2, **dkw)
+            ops.refine_continuous(c16, b["lab"], wh, wv, workspace=b["ws_r"], u_out=b["u"], keep_tape=True, **rkw)
+            ops.refine_continuous_backward(G_u, c16, wh, wv, b["ws_r"], grad_cost=b["gc"], grad_w_h=b["gwh"],
+                                           grad_w_v=b["gwv"], accumulate=False, workspace=b["ws_rb"], **rkw)
+            ops.solve_discrete_backward(c16, wh, wv, b["dual"], b["ws_d"], grad_minmarg=G_m, grad_bounds=G_b,
+                                        grad_cost=b["gc"], grad_w_h=b["gwh"], grad_w_v=b["gwv"], accumulate=True,
+                                        workspace=b["ws_db"], keep_checkpoints=2, **dkw)
 
-    bufs = [buffers() for _ in range(n_streams)]
+    ms_fb_seq = _timed(eager_fwd_bwd, reps, torch)
+    ckpt_gb = b["ws_d"].numel() / 1e9
+    del b
+
+    # the plain FP32 forward (no checkpoints), one frame after another and on n_streams streams
+    fb = [dict(dual=torch.empty((H, W, K), dtype=torch.float32, device=dev),
+               lab=torch.empty((H, W), dtype=torch.int32, device=dev),
+               u=torch.empty((H, W), dtype=torch.float32, device=dev), ws32=None, ws_r=None)
+          for _ in range(n_streams)]
     streams = [torch.cuda.Stream(device=dev) for _ in range(n_streams)]
-    grad_lpw = [None] * n
 
-    def one_fwd_bwd(f, b):
-        c16, _, wh, wv = frames[f]
-        ops.solve_discrete(c16, wh, wv, dual=b["dual"], workspace=b["ws_d"], labels=b["lab"], minmarg=b["mm"],
-                           want_bounds=True, keep_checkpoints=2, **dkw)
-        ops.refine_continuous(c16, b["lab"], wh, wv, workspace=b["ws_r"], u_out=b["u"], keep_tape=True, **rkw)
-        ops.refine_continuous_backward(G_u, c16, wh, wv, b["ws_r"], grad_cost=b["gc"], grad_w_h=b["gwh"],
-                                       grad_w_v=b["gwv"], accumulate=False, workspace=b["ws_rb"], **rkw)
-        ops.solve_discrete_backward(c16, wh, wv, b["dual"], b["ws_d"], grad_minmarg=G_m, grad_lb=1.0,
-                                    grad_cost=b["gc"], grad_w_h=b["gwh"], grad_w_v=b["gwv"], accumulate=True,
-                                    workspace=b["ws_db"], keep_checkpoints=2, **dkw)
-        # dL/dlambda_pw: the weights are lambda_pw * exp(...), so sum(dL/dw * w) / lambda_pw
-        grad_lpw[f] = (b["gwh"] * wh).sum() + (b["gwv"] * wv).sum()
-
-    def one_plain32(f, b):
+    def one_plain32(f, bb):
         _, c32, wh, wv = frames[f]
-        r = ops.solve_discrete(c32, wh, wv, dual=b["dual"], workspace=b["ws32"], labels=b["lab"], want_bounds=False,
-                               want_minmarg=False, **dkw)
-        b["ws32"] = r.workspace
-        ops.refine_continuous(c32, b["lab"], wh, wv, u_out=b["u"], workspace=b["ws_r"], **rkw)
+        r = ops.solve_discrete(c32, wh, wv, dual=bb["dual"], workspace=bb["ws32"], labels=bb["lab"],
+                               want_bounds=False, want_minmarg=False, **dkw)
+        bb["ws32"] = r.workspace
+        if bb["ws_r"] is None:
+            bb["ws_r"] = torch.empty(ops.refine_workspace_bytes((H, W, K), **rkw), dtype=torch.uint8, device=dev)
+        ops.refine_continuous(c32, bb["lab"], wh, wv, u_out=bb["u"], workspace=bb["ws_r"], **rkw)
 
-    def concurrent(fn):
+    def concurrent():
         main = torch.cuda.current_stream(dev)
         for st in streams:
             st.wait_stream(main)
         for f in range(n):
             k = f % n_streams
             with torch.cuda.stream(streams[k]):
-                fn(f, bufs[k])
+                one_plain32(f, fb[k])
         for st in streams:
             main.wait_stream(st)
 
-    def sequential(fn):
+    def sequential():
         for f in range(n):
-            fn(f, bufs[0])
+            one_plain32(f, fb[0])
 
-    ms_fb = _timed(lambda: concurrent(one_fwd_bwd), reps, torch)
-    ms_fb_seq = _timed(lambda: sequential(one_fwd_bwd), reps, torch)
-    ms_32 = _timed(lambda: sequential(one_plain32), reps, torch)
-    ms_32_conc = _timed(lambda: concurrent(one_plain32), reps, torch)
-    finite = bool(all(torch.isfinite(g).item() for g in grad_lpw))
+    ms_32 = _timed(sequential, reps, torch)
+    ms_32_conc = _timed(concurrent, reps, torch)
     return {"workload": f"batch of {n} frames {W}x{H}, K={K}, FP16 cost; Dual_MM {n_iters} its (tapes kept by the "
-                        f"forward) + refinement {warps}x{iters}; backward dL/dcost, dL/dw (and dL/dlambda_pw); "
-                        f"{n_streams} streams",
+                        f"forward) + refinement {warps}x{iters}; backward dL/dcost, dL/dw (and dL/dlambda_pw); one "
+                        f"batched plan (hipGraph, {n_streams} forked streams)",
             "fwd_bwd_fp16_ms_per_batch": ms_fb, "fwd_bwd_fp16_ms_per_frame": ms_fb / n,
-            "fwd_bwd_fp16_one_stream_ms_per_batch": ms_fb_seq,
+            "fwd_bwd_fp16_eager_one_stream_ms_per_batch": ms_fb_seq,
             "plain_fp32_forward_ms_per_batch": ms_32, "plain_fp32_forward_streams_ms_per_batch": ms_32_conc,
             "ratio_fwd_bwd_to_plain_fwd": ms_fb / ms_32,
             "ratio_fwd_bwd_to_plain_fwd_same_streams": ms_fb / ms_32_conc,
-            "checkpoint_GB_per_stream": bufs[0]["ws_d"].numel() / 1e9,
-            "backward_workspace_GB_per_stream": bufs[0]["ws_db"].numel() / 1e9,
+            "plan_build_s": plan_s, "plan_device_GB": plan_gb,
+            "checkpoint_GB_per_frame": ckpt_gb,
             "grad_finite": finite}
 
 

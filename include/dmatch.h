@@ -391,6 +391,43 @@ typedef struct {
 
 int dm_plan_batched(const dm_instance* inst, int n, dm_dtype cost_dtype, const dm_discrete_params* p,
                     const dm_refine_params* rp, void** plan_out);
+
+/* Batched forward + backward (the differentiation workload): per instance Dual_MM
+ * keeping what its backward needs (p->keep_checkpoints 1 or 2), the refinement if
+ * rp != NULL (its keep_tape is taken as 1), then the refinement adjoint (if grad_u is
+ * given) and the Dual_MM adjoint, added into grad_cost / grad_w_h / grad_w_v - the calls
+ * dm_solve_discrete, dm_refine_continuous, dm_refine_continuous_backward and
+ * dm_solve_discrete_backward of this header, with their meaning, captured once into
+ * one hipGraph.  Instance i runs on forked stream i % n_streams (1..16): instances
+ * advance through their half-steps independently, those of one stream one after
+ * another, sharing that stream's workspaces, which the plan owns.  Outputs per run:
+ * labels, dual, minmarg and bounds (each may be NULL but labels and dual), u; the
+ * gradients overwritten.  Loss inputs per instance (device, read at run time):
+ * grad_minmarg [H][W][K], grad_bounds [2] = {dL/dLB, dL/dE}, grad_u [H][W] (each may be
+ * NULL).  The caller owns every instance buffer (same addresses for every run).
+ * dm_run_batched replays the graph, dm_plan_destroy frees the plan.  Each run starts
+ * from dual 0 (warm_start must be 0). */
+typedef struct {
+    dm_shape s;
+    const void* cost;            /* [H][W][K] of the plan's cost dtype                */
+    const float* w_h;            /* [H][W-1]                                          */
+    const float* w_v;            /* [H-1][W]                                          */
+    int32_t* labels;             /* [H][W] output                                     */
+    float* dual;                 /* [H][W][K] output (the final dual)                 */
+    float* minmarg;              /* [H][W][K] output or NULL                          */
+    double* bounds;              /* [2] output {LB, E(labels)} or NULL                */
+    float* u;                    /* [H][W] refined disparities (with refinement)      */
+    const float* grad_minmarg;   /* [H][W][K] dL/dminmarg or NULL                     */
+    const double* grad_bounds;   /* [2] {dL/dLB, dL/dE} or NULL                       */
+    const float* grad_u;         /* [H][W] dL/du or NULL                              */
+    float* grad_cost;            /* [H][W][K] float32 output                          */
+    float* grad_w_h;             /* [H][W-1] output or NULL                           */
+    float* grad_w_v;             /* [H-1][W] output or NULL                           */
+} dm_grad_instance;
+
+int dm_plan_batched_grad(const dm_grad_instance* inst, int n, dm_dtype cost_dtype, const dm_discrete_params* p,
+                         const dm_refine_params* rp, int n_streams, void** plan_out);
+
 int dm_run_batched(void* plan, void* hip_stream);
 size_t dm_plan_device_bytes(const void* plan);
 void dm_plan_destroy(void* plan);

@@ -63,6 +63,12 @@ class DmInstance(ctypes.Structure):
                 ("bounds", ctypes.c_void_p)]
 
 
+class DmGradInstance(ctypes.Structure):
+    _fields_ = [("s", DmShape)] + [(k, ctypes.c_void_p) for k in (
+        "cost", "w_h", "w_v", "labels", "dual", "minmarg", "bounds", "u", "grad_minmarg", "grad_bounds", "grad_u",
+        "grad_cost", "grad_w_h", "grad_w_v")]
+
+
 class DmError(RuntimeError):
     def __init__(self, fn: str, status: int, detail: str):
         super().__init__(f"{fn} failed: {STATUS_NAMES.get(status, status)}: {detail}")
@@ -113,6 +119,9 @@ _SIGNATURES = [
     ("dm_plan_batched", ctypes.c_int,
      [ctypes.POINTER(DmInstance), ctypes.c_int, ctypes.c_int, ctypes.POINTER(DmDiscreteParams),
       ctypes.POINTER(DmRefineParams), ctypes.POINTER(ctypes.c_void_p)]),
+    ("dm_plan_batched_grad", ctypes.c_int,
+     [ctypes.POINTER(DmGradInstance), ctypes.c_int, ctypes.c_int, ctypes.POINTER(DmDiscreteParams),
+      ctypes.POINTER(DmRefineParams), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
     ("dm_run_batched", ctypes.c_int, [_VP, _VP]),
     ("dm_plan_device_bytes", ctypes.c_size_t, [_VP]),
     ("dm_plan_destroy", None, [_VP]),

@@ -30,7 +30,7 @@ def _tiles():
 
 TILES = _tiles()
 UNITS = [("api.hip", [], "api"), ("dmm.hip", [], "dmm"), ("cost_volume.hip", [], "cost_volume"),
-         ("refine.hip", [], "refine"), ("batched.hip", [], "batched"), ("noalloc.hip", [], "noalloc"),
+         ("refine.hip", [], "refine"), ("batched.hip", [], "batched"), ("noalloc.hip", [], "noalloc"), ("batched_grad.hip", [], "batched_grad"),
          ("flow.hip", [], "flow")]
 # largest units first so the parallel build's critical path starts early
 UNITS = [("dmm_tile.hip", [f"-DDM_TILE_G={g}", f"-DDM_TILE_L={l}", f"-DDM_TILE_PART={k}"], f"dmm_tile_{g}x{l}_{v}")

@@ -13,6 +13,7 @@
 
 #include "batched_kernels.h"
 #include "common.h"
+#include "plan.h"
 #include "refine.h"
 #include "tiles.h"
 
@@ -125,31 +126,13 @@ struct Class {
 
 }  // namespace
 
-struct BatchPlan {
+struct BatchPlan : PlanBase {
     int n = 0;
     dm_dtype dt = DM_F32;
     dm_discrete_params dp{};
     bool has_refine = false;
     dm_refine_params rp{};
-    std::vector<void*> allocs;
     std::vector<Class> classes;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    size_t device_bytes = 0;
-    ~BatchPlan() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        for (void* p : allocs) (void)hipFree(p);
-    }
-    template <typename T>
-    T* alloc(size_t count) {
-        void* p = nullptr;
-        const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
-        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
-        allocs.push_back(p);
-        device_bytes += bytes;
-        return static_cast<T*>(p);
-    }
 };
 
 }  // namespace dm
@@ -475,20 +458,20 @@ extern "C" int dm_plan_batched(const dm_instance* inst, int n, dm_dtype cost_dty
     if (e != hipSuccess) return fail("end capture", e);
     plan->graph = graph;
     if ((e = hipGraphInstantiate(&plan->exec, graph, nullptr, nullptr, 0)) != hipSuccess) return fail("instantiate", e);
-    *plan_out = plan;
+    *plan_out = static_cast<PlanBase*>(plan);
     return DM_OK;
 }
 
 extern "C" int dm_run_batched(void* plan, void* hip_stream) {
     clear_error();
     DM_REQUIRE(plan != nullptr, DM_ERR_NULL, "plan is NULL");
-    BatchPlan* bp = static_cast<BatchPlan*>(plan);
+    PlanBase* bp = static_cast<PlanBase*>(plan);
     DM_HIP_TRY(hipGraphLaunch(bp->exec, static_cast<hipStream_t>(hip_stream)), "graph launch");
     return DM_OK;
 }
 
 extern "C" size_t dm_plan_device_bytes(const void* plan) {
-    return plan == nullptr ? 0 : static_cast<const BatchPlan*>(plan)->device_bytes;
+    return plan == nullptr ? 0 : static_cast<const PlanBase*>(plan)->device_bytes;
 }
 
-extern "C" void dm_plan_destroy(void* plan) { delete static_cast<BatchPlan*>(plan); }
+extern "C" void dm_plan_destroy(void* plan) { delete static_cast<PlanBase*>(plan); }

@@ -21,7 +21,10 @@
 // lane shifts), else in-lane scans and a 64-lane min-plus scan with the linear
 // distance; then the cap min v + wT.  Passes prefetch the next nodes' unaries kHierPF
 // nodes ahead (with the weights of their edges); a Handshake issues its four loads
-// together.
+// together.  Every HBM access is a raw buffer instruction at a 32-bit byte offset (node
+// offset = first node's + node * per-node step): vector loads and stores of a lane's
+// labels when K fills the tile (FULL), else one access per label with the labels that
+// do not exist at an out-of-range offset (reads 0, writes dropped) - no predicates.
 #include "dmm_hier.h"
 
 namespace dm {
@@ -39,17 +42,16 @@ __device__ __forceinline__ int hsplit(int s, int e) { return s + (e - s + 1) / 2
 // spans at most the neighbouring lanes: the message is the window minimum, no scans);
 // -1: any T, by scans.
 // NW: waves per chain (a workgroup of NW waves).
-template <int LPL, typename TT, bool HAS_THETA, int TW, int NW>
+template <int LPL, typename TT, bool HAS_THETA, int TW, int NW, bool FULL>
 struct HierChain {
     static constexpr int kHierChunk = hier_chunk(NW);
     static constexpr int kLdsFloats = 3 * kHierChunk * 64 * LPL + kHierChunk;  // per wave
-    const TT* th;
-    const float* lin;
-    float* lout;
-    float* msgL;  // message into a node from the left (within its current part)
-    float* msgR;  // message into a node from the right
-    const float* w;
-    long long px0, npx, w0, wn;
+    static constexpr int ES = (int)sizeof(TT);
+    // buffers: cost, dual read, dual written, messages from the left / right, weights
+    __amdgpu_buffer_rsrc_t r_th, r_lin, r_lout, r_mL, r_mR, r_w;
+    // byte offsets of this lane's first label at node 0 (FP32 volumes, cost volume) and of
+    // edge 0, and their per-node / per-edge steps; lanes without labels sit at kOOB
+    unsigned f0, f_step, c0, c_step, w0, w_step;
     int K, n, lane, wv;
     float Tf, sign;
     bool lv[LPL];
@@ -57,16 +59,6 @@ struct HierChain {
     int* stk_small;  // this wave's part stack inside a small part
 
     __device__ HierChain(const SweepArgs& a, float* msg_right, int chain) {
-        th = static_cast<const TT*>(a.theta);
-        lin = a.lam_in != nullptr ? a.lam_in : a.lam;
-        lout = a.lam;
-        msgL = a.msg;
-        msgR = msg_right;
-        w = a.w;
-        px0 = (long long)chain * a.chain_px;
-        npx = a.node_px;
-        w0 = (long long)chain * a.w_chain;
-        wn = a.w_node;
         K = a.K;
         n = a.n;
         lane = (int)threadIdx.x & 63;
@@ -74,36 +66,85 @@ struct HierChain {
         Tf = (float)a.T;
         sign = a.sign;
 #pragma unroll
-        for (int i = 0; i < LPL; ++i) lv[i] = lane * LPL + i < K;
+        for (int i = 0; i < LPL; ++i) lv[i] = FULL || lane * LPL + i < K;
+        const bool any = FULL || lane * LPL < K;
+        const unsigned long long e0 =
+            (unsigned long long)chain * (unsigned long long)a.chain_px * (unsigned long long)K + (unsigned)(lane * LPL);
+        const unsigned long long nk = (unsigned long long)a.node_px * (unsigned long long)K;
+        f0 = any ? (unsigned)(e0 * 4ull) : kOOB;
+        f_step = any ? (unsigned)(nk * 4ull) : 0u;
+        c0 = any ? (unsigned)(e0 * (unsigned long long)ES) : kOOB;
+        c_step = any ? (unsigned)(nk * (unsigned long long)ES) : 0u;
+        w0 = (unsigned)((unsigned long long)chain * (unsigned long long)a.w_chain * 4ull);
+        w_step = (unsigned)(a.w_node * 4);
+        const unsigned vb = a.vol_bytes_f32;
+        r_th = make_rsrc(a.theta, HAS_THETA ? a.vol_bytes_theta : 0u);
+        r_lin = make_rsrc(a.lam_in != nullptr ? a.lam_in : a.lam, vb);
+        r_lout = make_rsrc(a.lam, vb);
+        r_mL = make_rsrc(a.msg, vb);
+        r_mR = make_rsrc(msg_right, vb);
+        r_w = make_rsrc(a.w, a.w_bytes);
     }
 
-    __device__ __forceinline__ long long el(int node, int i) const {
-        return (px0 + (long long)node * npx) * K + lane * LPL + i;
+    // Per-label byte offsets of the access at `off` (element size E): labels that do not
+    // exist are out of range.
+    template <int E>
+    __device__ __forceinline__ void offs(unsigned off, unsigned (&o)[LPL]) const {
+#pragma unroll
+        for (int i = 0; i < LPL; ++i) o[i] = lv[i] ? off + (unsigned)(i * E) : kOOB;
     }
     // unaries of the family at a node: cost - dual (rows) or dual (columns); kBig for
     // labels that do not exist
     __device__ __forceinline__ void load_r(int node, float (&r)[LPL]) const {
-#pragma unroll
-        for (int i = 0; i < LPL; ++i) {
-            float x = kBig;
-            if (lv[i]) {
-                const long long e = el(node, i);
-                const float l = lin[e];
-                x = HAS_THETA ? (float)th[e] - l : l;
-            }
-            r[i] = x;
+        unsigned o[LPL];
+        const unsigned fo = f0 + (unsigned)node * f_step;
+        offs<4>(fo, o);
+        RawVec<float, LPL, FULL> l;
+        l.load(r_lin, fo, o);
+        RawVec<TT, LPL, FULL> c;
+        if constexpr (HAS_THETA) {
+            const unsigned co = c0 + (unsigned)node * c_step;
+            offs<ES>(co, o);
+            c.load(r_th, co, o);
         }
-    }
-    __device__ __forceinline__ void load_msg(const float* buf, int node, float (&m)[LPL]) const {
 #pragma unroll
-        for (int i = 0; i < LPL; ++i) m[i] = lv[i] ? buf[el(node, i)] : 0.0f;
+        for (int i = 0; i < LPL; ++i) r[i] = lv[i] ? (HAS_THETA ? c.get(i) - l.get(i) : l.get(i)) : kBig;
     }
-    __device__ __forceinline__ void store_msg(float* buf, int node, const float (&m)[LPL]) const {
+    // the dual at a node (0 for labels that do not exist)
+    __device__ __forceinline__ void load_lam(int node, float (&x)[LPL]) const {
+        unsigned o[LPL];
+        const unsigned fo = f0 + (unsigned)node * f_step;
+        offs<4>(fo, o);
+        RawVec<float, LPL, FULL> l;
+        l.load(r_lin, fo, o);
 #pragma unroll
-        for (int i = 0; i < LPL; ++i)
-            if (lv[i]) buf[el(node, i)] = m[i];
+        for (int i = 0; i < LPL; ++i) x[i] = l.get(i);
     }
-    __device__ __forceinline__ float weight(int edge) const { return w[w0 + (long long)edge * wn]; }
+    __device__ __forceinline__ void store_lam(int node, const float (&x)[LPL]) const {
+        unsigned o[LPL];
+        const unsigned fo = f0 + (unsigned)node * f_step;
+        offs<4>(fo, o);
+        store_f32<LPL, FULL>(r_lout, fo, o, x);
+    }
+    __device__ __forceinline__ void load_msg(bool left, int node, float (&m)[LPL]) const {
+        unsigned o[LPL];
+        const unsigned fo = f0 + (unsigned)node * f_step;
+        offs<4>(fo, o);
+        RawVec<float, LPL, FULL> v;
+        v.load(left ? r_mL : r_mR, fo, o);
+#pragma unroll
+        for (int i = 0; i < LPL; ++i) m[i] = v.get(i);
+    }
+    __device__ __forceinline__ void store_msg(bool left, int node, const float (&m)[LPL]) const {
+        unsigned o[LPL];
+        const unsigned fo = f0 + (unsigned)node * f_step;
+        offs<4>(fo, o);
+        store_f32<LPL, FULL>(left ? r_mL : r_mR, fo, o, m);
+    }
+    __device__ __forceinline__ float weight(int edge) const {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r_w, (int)(w0 + (unsigned)edge * w_step),
+                                                                              0, 0));
+    }
 
     __device__ __forceinline__ float wave_min(const float (&x)[LPL]) const {
         float m = x[0];
@@ -175,11 +216,9 @@ struct HierChain {
     struct Glob {
         const HierChain* h;
         __device__ __forceinline__ void load_r(int k, float (&r)[LPL]) const { h->load_r(k, r); }
-        __device__ __forceinline__ void load_m(bool left, int k, float (&m)[LPL]) const {
-            h->load_msg(left ? h->msgL : h->msgR, k, m);
-        }
+        __device__ __forceinline__ void load_m(bool left, int k, float (&m)[LPL]) const { h->load_msg(left, k, m); }
         __device__ __forceinline__ void store_m(bool left, int k, const float (&m)[LPL]) const {
-            h->store_msg(left ? h->msgL : h->msgR, k, m);
+            h->store_msg(left, k, m);
         }
         __device__ __forceinline__ float w(int edge) const { return h->weight(edge); }
     };
@@ -353,15 +392,11 @@ struct HierChain {
             if (j < m - 1) ew[j] = weight(s + j);
 #pragma unroll
         for (int j = 0; j < kHierChunk; ++j)
-            if (j < m) load_msg(s + j <= cut ? msgL : msgR, s + j, mg[j]);
+            if (j < m) load_msg(s + j <= cut, s + j, mg[j]);
         if constexpr (HAS_THETA) {
 #pragma unroll
-            for (int j = 0; j < kHierChunk; ++j) {
-                if (j < m) {
-#pragma unroll
-                    for (int i = 0; i < LPL; ++i) lam[j][i] = lv[i] ? lin[el(s + j, i)] : 0.0f;
-                }
-            }
+            for (int j = 0; j < kHierChunk; ++j)
+                if (j < m) load_lam(s + j, lam[j]);
         }
 #pragma unroll
         for (int j = 0; j < kHierChunk; ++j) {
@@ -392,13 +427,13 @@ struct HierChain {
 #pragma unroll
                 for (int i = 0; i < LPL; ++i) mm[i] = lv[i] ? r[i] + a[i] + b[i] : kBig;
                 const float mn = wave_min(mm);
+                float out[LPL];
 #pragma unroll
                 for (int i = 0; i < LPL; ++i) {
-                    if (lv[i]) {
-                        const float l0 = HAS_THETA ? lam[j][i] : r[i];
-                        lout[el(s + j, i)] = l0 + sign * (mm[i] - mn);
-                    }
+                    const float l0 = HAS_THETA ? lam[j][i] : r[i];
+                    out[i] = l0 + sign * (mm[i] - mn);
                 }
+                store_lam(s + j, out);
             }
         }
         wave_lds_sync();  // the next part reuses the LDS
@@ -435,13 +470,13 @@ struct HierChain {
             if (wv == 0) {
 #pragma unroll
                 for (int q = 0; q < LPL; ++q) c[q] = 0.0f;
-                store_msg(msgL, 0, c);
+                store_msg(true, 0, c);
                 pass(G, 0, i0, +1, c, opt);
             }
             if (wv == (NW > 1 ? 1 : 0)) {
 #pragma unroll
                 for (int q = 0; q < LPL; ++q) c[q] = 0.0f;
-                store_msg(msgR, n - 1, c);
+                store_msg(false, n - 1, c);
                 pass(G, n - 1, n - 2 - i0, -1, c, opt);
             }
             __syncthreads();
@@ -488,11 +523,11 @@ struct HierChain {
                     double unused = 0.0;  // the parts' normalisation constants are not the optimum's
                     if ((q & 1) == 0) {
                         if (i > s0) {
-                            load_msg(msgR, i, c);
+                            load_msg(false, i, c);
                             pass(G, i, i - hsplit(s0, i) - 1, -1, c, unused);
                         }
                     } else if (e0 > i + 1) {
-                        load_msg(msgL, i + 1, c);
+                        load_msg(true, i + 1, c);
                         pass(G, i + 1, hsplit(i + 1, e0) - i - 1, +1, c, unused);
                     }
                 }
@@ -501,17 +536,14 @@ struct HierChain {
             }
         } else if (wv == 0) {
             // one node: its minorant is its unary
-            float r[LPL];
+            float r[LPL], l0[LPL], out[LPL];
             load_r(0, r);
+            load_lam(0, l0);
             const float mn = wave_min(r);
             opt = (double)mn;
 #pragma unroll
-            for (int i = 0; i < LPL; ++i) {
-                if (lv[i]) {
-                    const long long e = el(0, i);
-                    lout[e] = lin[e] + sign * (r[i] - mn);
-                }
-            }
+            for (int i = 0; i < LPL; ++i) out[i] = l0[i] + sign * (r[i] - mn);
+            store_lam(0, out);
         }
         if constexpr (NW > 1) {
             if (wv == 1 && lane == 0) *opt_share = opt;
@@ -522,9 +554,9 @@ struct HierChain {
     }
 };
 
-template <int LPL, typename TT, bool HAS_THETA, int TW, int NW>
+template <int LPL, typename TT, bool HAS_THETA, int TW, int NW, bool FULL>
 __global__ __launch_bounds__(64 * NW) void hier_chain_kernel(SweepArgs a, float* msg_right) {
-    using HC = HierChain<LPL, TT, HAS_THETA, TW, NW>;
+    using HC = HierChain<LPL, TT, HAS_THETA, TW, NW, FULL>;
     __shared__ int stk[NW][2 * 64];  // each wave's part stack (depth <= 32)
     __shared__ double opt_share[1];
     extern __shared__ float part[];  // per wave: [3][chunk][64 * LPL], then chunk weights
@@ -535,17 +567,23 @@ __global__ __launch_bounds__(64 * NW) void hier_chain_kernel(SweepArgs a, float*
     hc.run(a.opt != nullptr ? a.opt + chain : nullptr, opt_share);
 }
 
+template <int LPL, int TW, int NW, bool FULL>
+hipError_t launch_full(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st) {
+    const dim3 grid((unsigned)a.n_chains), block(64 * NW);
+    const size_t lds = (size_t)NW * HierChain<LPL, float, false, TW, NW, FULL>::kLdsFloats * sizeof(float);
+    if (a.theta == nullptr)
+        hipLaunchKernelGGL((hier_chain_kernel<LPL, float, false, TW, NW, FULL>), grid, block, lds, st, a, msg_right);
+    else if (dt == DM_F16)
+        hipLaunchKernelGGL((hier_chain_kernel<LPL, _Float16, true, TW, NW, FULL>), grid, block, lds, st, a, msg_right);
+    else
+        hipLaunchKernelGGL((hier_chain_kernel<LPL, float, true, TW, NW, FULL>), grid, block, lds, st, a, msg_right);
+    return hipGetLastError();
+}
+
 template <int LPL, int TW, int NW>
 hipError_t launch_nw(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st) {
-    const dim3 grid((unsigned)a.n_chains), block(64 * NW);
-    const size_t lds = (size_t)NW * HierChain<LPL, float, false, TW, NW>::kLdsFloats * sizeof(float);
-    if (a.theta == nullptr)
-        hipLaunchKernelGGL((hier_chain_kernel<LPL, float, false, TW, NW>), grid, block, lds, st, a, msg_right);
-    else if (dt == DM_F16)
-        hipLaunchKernelGGL((hier_chain_kernel<LPL, _Float16, true, TW, NW>), grid, block, lds, st, a, msg_right);
-    else
-        hipLaunchKernelGGL((hier_chain_kernel<LPL, float, true, TW, NW>), grid, block, lds, st, a, msg_right);
-    return hipGetLastError();
+    if (a.K == 64 * LPL) return launch_full<LPL, TW, NW, true>(a, msg_right, dt, st);
+    return launch_full<LPL, TW, NW, false>(a, msg_right, dt, st);
 }
 
 // Several waves per chain when the chains alone leave most SIMDs idle (1024 SIMDs).
@@ -578,14 +616,18 @@ hipError_t launch_hier_half_step(const SweepArgs& a, float* msg_right, dm_dtype 
 }
 
 double hier_half_step_bytes(const SweepArgs& a, dm_dtype dt) {
-    // per label-node: the level-0 passes read the unaries of every node and write a
-    // message; each further level does so for half of the nodes (about log2(n) - 1
-    // levels); the final pass reads the unaries and both messages and writes the dual
+    // per label-node, HBM only: the two level-0 passes read every node's unaries (cost
+    // and dual for rows, the dual for columns) and write its message; at every depth whose
+    // parts are longer than the LDS part, the passes after the cuts do so for half of the
+    // nodes; a part of at most that length is read once (unaries, one message) into LDS
+    // and its nodes' duals written.  The Handshakes' own loads and stores (two nodes per
+    // cut, about one cut per LDS part) are left out.
     const double b = a.theta != nullptr ? (dt == DM_F16 ? 2.0 : 4.0) : 0.0;
-    int levels = 0;
-    for (int m = a.n; m > 1; m = (m + 1) / 2) ++levels;
-    const double step = b + 4.0 + 4.0;  // cost, dual read; message written
-    const double per = step * (1.0 + 0.5 * (levels > 1 ? levels - 1 : 0)) + (b + 4.0 + 8.0 + 4.0);
+    const int chunk = hier_chunk(1);
+    int deep = 0;  // depths whose parts are longer than the LDS part
+    for (int m = a.n; m > chunk; m = (m + 1) / 2) ++deep;
+    const double step = b + 4.0 + 4.0;                 // unaries read, message written
+    const double per = step * (1.0 + 0.5 * deep) + (b + 4.0 + 4.0) + 4.0;  // + LDS part in, dual out
     return per * (double)a.n * a.n_chains * a.K;
 }
 

@@ -489,3 +489,78 @@ class BatchedPlan:
             self.close()
         except Exception:
             pass
+
+
+class BatchedGradPlan:
+    """Forward and backward of many instances as one hipGraph launch (dm_plan_batched_grad).
+
+    ``instances``: list of dicts with GPU tensors ``cost`` [H][W][K] (all float32 or all
+    float16), ``w_h``, ``w_v`` and the loss inputs ``grad_minmarg`` [H][W][K], ``grad_bounds``
+    (float64 [2]), ``grad_u`` [H][W] (each optional).  The plan allocates, unless given,
+    ``labels``, ``dual``, ``minmarg`` (when grad_minmarg is given), ``bounds``, ``u`` (with
+    refinement) and the gradients ``grad_cost``, ``grad_w_h``, ``grad_w_v``; every run
+    overwrites them.  Instance i runs on forked stream i % n_streams of the graph.
+    """
+
+    def __init__(self, instances, *, T=3, n_iters=20, n_half_steps=0, minorant="iterative",
+                 gammas=(0.25, 0.25, 1.0), tile=None, keep_checkpoints=2, refine=None, n_streams=8):
+        self.instances = []
+        arr = (L.DmGradInstance * len(instances))()
+        dtype = instances[0]["cost"].dtype
+        for i, inst in enumerate(instances):
+            cost = inst["cost"]
+            if cost.dtype != dtype:
+                raise ValueError("all instances must share the cost dtype")
+            H, W, K = cost.shape
+            d = dict(inst)
+            dev = cost.device
+            d.setdefault("labels", torch.empty((H, W), dtype=torch.int32, device=dev))
+            d.setdefault("dual", torch.empty((H, W, K), dtype=torch.float32, device=dev))
+            if d.get("grad_minmarg") is not None:
+                d.setdefault("minmarg", torch.empty((H, W, K), dtype=torch.float32, device=dev))
+            d.setdefault("bounds", torch.empty(2, dtype=torch.float64, device=dev))
+            if refine is not None:
+                d.setdefault("u", torch.empty((H, W), dtype=torch.float32, device=dev))
+            d.setdefault("grad_cost", torch.empty((H, W, K), dtype=torch.float32, device=dev))
+            d.setdefault("grad_w_h", torch.empty((H, W - 1), dtype=torch.float32, device=dev))
+            d.setdefault("grad_w_v", torch.empty((H - 1, W), dtype=torch.float32, device=dev))
+            _check_dev("cost", cost)
+            for k, dt_, shp in (("w_h", torch.float32, (H, W - 1)), ("w_v", torch.float32, (H - 1, W)),
+                                ("labels", torch.int32, (H, W)), ("dual", torch.float32, (H, W, K)),
+                                ("minmarg", torch.float32, (H, W, K)), ("bounds", torch.float64, (2,)),
+                                ("u", torch.float32, (H, W)), ("grad_minmarg", torch.float32, (H, W, K)),
+                                ("grad_bounds", torch.float64, (2,)), ("grad_u", torch.float32, (H, W)),
+                                ("grad_cost", torch.float32, (H, W, K)), ("grad_w_h", torch.float32, (H, W - 1)),
+                                ("grad_w_v", torch.float32, (H - 1, W))):
+                _check_dev(k, d.get(k), dt_, shp)
+            arr[i] = L.DmGradInstance(L.DmShape(W, H, K), *[_ptr(d.get(k)) for k in (
+                "cost", "w_h", "w_v", "labels", "dual", "minmarg", "bounds", "u", "grad_minmarg", "grad_bounds",
+                "grad_u", "grad_cost", "grad_w_h", "grad_w_v")])
+            self.instances.append(d)
+        p = discrete_params(T, n_iters, n_half_steps, minorant, gammas, False, tile, keep_checkpoints)
+        rp = None if refine is None else refine_params(keep_tape=True, **refine)
+        handle = ctypes.c_void_p()
+        self._lib = L.lib()
+        st = self._lib.dm_plan_batched_grad(arr, len(instances), _cost_dtype(instances[0]["cost"]), ctypes.byref(p),
+                                            None if rp is None else ctypes.byref(rp), int(n_streams),
+                                            ctypes.byref(handle))
+        L.check("dm_plan_batched_grad", st)
+        self.handle = handle
+
+    @property
+    def device_bytes(self):
+        return int(self._lib.dm_plan_device_bytes(self.handle))
+
+    def run(self, stream=None):
+        L.check("dm_run_batched", self._lib.dm_run_batched(self.handle, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.dm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -176,3 +176,50 @@ def test_batched_full_64_instances_sampled():
         assert checked >= 4
     finally:
         plan.close()
+
+
+def _eager_fwd_bwd(ops, d, kw, rkw):
+    """One instance's forward and backward through the single-instance calls."""
+    r = ops.solve_discrete(d["cost"], d["w_h"], d["w_v"], keep_checkpoints=2, **kw)
+    rws = torch.empty(ops.refine_workspace_bytes(tuple(d["cost"].shape), keep_tape=True, **rkw), dtype=torch.uint8,
+                      device="cuda")
+    u = ops.refine_continuous(d["cost"], r.labels, d["w_h"], d["w_v"], keep_tape=True, workspace=rws, **rkw)
+    gc, gwh, gwv = ops.refine_continuous_backward(d["grad_u"], d["cost"], d["w_h"], d["w_v"], rws, **rkw)
+    ops.solve_discrete_backward(d["cost"], d["w_h"], d["w_v"], r.dual, r.workspace, grad_minmarg=d["grad_minmarg"],
+                                grad_bounds=d["grad_bounds"], grad_cost=gc, grad_w_h=gwh, grad_w_v=gwv,
+                                accumulate=True, keep_checkpoints=2, **kw)
+    torch.cuda.synchronize()
+    return dict(labels=r.labels, dual=r.dual, minmarg=r.minmarg, bounds=r.bounds, u=u, grad_cost=gc, grad_w_h=gwh,
+                grad_w_v=gwv)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
+def test_batched_grad_plan_equals_eager(dtype):
+    """dm_plan_batched_grad: uneven instances on 2 forked streams of one graph (two
+    instances share a stream and its workspaces); every output and gradient equals the
+    same single-instance calls made eagerly, bit for bit, on every replay."""
+    ops = _need()
+    specs = [(6, 9, 8, 21), (10, 7, 16, 22), (5, 14, 12, 23), (4, 6, 5, 24), (8, 8, 24, 25)]
+    insts = _instances(specs, dtype)
+    g = torch.Generator(device="cuda").manual_seed(7)
+    for d in insts:
+        H, W, K = d["cost"].shape
+        d["grad_minmarg"] = torch.randn((H, W, K), generator=g, device="cuda")
+        d["grad_u"] = torch.randn((H, W), generator=g, device="cuda")
+        d["grad_bounds"] = torch.tensor([0.7, 0.3], dtype=torch.float64, device="cuda")
+    kw = dict(T=3, n_iters=2)
+    rkw = dict(C=3.0, n_warps=2, n_iters=9)
+    keys = ("cost", "w_h", "w_v", "grad_minmarg", "grad_bounds", "grad_u")
+    print(f"[case] batched grad plan {len(insts)} instances {dtype}", flush=True)
+    plan = ops.BatchedGradPlan([{k: d[k] for k in keys} for d in insts], refine=rkw, n_streams=2, **kw)
+    try:
+        refs = [_eager_fwd_bwd(ops, d, kw, rkw) for d in insts]
+        for rep in range(2):
+            plan.run()
+            torch.cuda.synchronize()
+            _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+            for i, (pi, ref) in enumerate(zip(plan.instances, refs)):
+                for k, v in ref.items():
+                    assert torch.equal(pi[k], v), f"replay {rep} instance {i}: {k} differs"
+    finally:
+        plan.close()
