@@ -35,8 +35,10 @@ UNITS = [("api.hip", [], "api"), ("dmm.hip", [], "dmm"), ("cost_volume.hip", [],
 # largest units first so the parallel build's critical path starts early
 UNITS = [("dmm_tile.hip", [f"-DDM_TILE_G={g}", f"-DDM_TILE_L={l}", f"-DDM_TILE_PART={k}"], f"dmm_tile_{g}x{l}_{v}")
          for k, v in [(2, "adj"), (4, "tape"), (1, "fwd"), (3, "batch")] for g, l in sorted(TILES, key=lambda t: -t[0] * t[1])] + UNITS
-# the hierarchical-minorant unit is the slowest single compile: first
-UNITS = [("dmm_hier.hip", [], "dmm_hier")] + UNITS
+# the hierarchical-minorant kernels, one unit per labels-per-lane count (the slowest
+# compiles: first), and their dispatch
+UNITS = ([("dmm_hier.hip", [f"-DDM_HIER_LPL={l}"], f"dmm_hier_{l}") for l in (3, 4, 2, 1)] + UNITS +
+         [("dmm_hier.hip", ["-DDM_HIER_LPL=0"], "dmm_hier_0")])
 
 FLAGS = [
     "--offload-arch=gfx950",

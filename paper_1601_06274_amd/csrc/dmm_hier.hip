@@ -25,16 +25,36 @@
 // offset = first node's + node * per-node step): vector loads and stores of a lane's
 // labels when K fills the tile (FULL), else one access per label with the labels that
 // do not exist at an out-of-range offset (reads 0, writes dropped) - no predicates.
+// Built once per labels-per-lane count (-DDM_HIER_LPL=1..4: that count's kernels) and
+// once with -DDM_HIER_LPL=0 (the dispatch and the byte count), so the many kernel
+// instantiations compile in parallel.
 #include "dmm_hier.h"
 
-namespace dm {
-namespace {
+#ifndef DM_HIER_LPL
+#error "DM_HIER_LPL must be defined (0: dispatch, 1..4: the kernels of that labels-per-lane count)"
+#endif
 
-constexpr int kHierPF = 8;
+namespace dm {
+
 // Parts of at most this many nodes are finished in LDS by one wave (App. A.3.3's
 // iteration count assumes that short parts sit in fast memory); 8 keeps a wave's
 // staging at 18.4 KB for K = 192, so every column chain of a frame stays resident.
 constexpr int hier_chunk(int) { return 8; }
+
+hipError_t launch_hier_lpl1(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st);
+hipError_t launch_hier_lpl2(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st);
+hipError_t launch_hier_lpl3(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st);
+hipError_t launch_hier_lpl4(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st);
+
+#if DM_HIER_LPL > 0
+namespace {
+
+// LDS pointers typed in the local address space (a generic pointer would make every
+// access a flat instruction, which also waits on the vector-memory counter)
+using lds_f32 = __attribute__((address_space(3))) float;
+using lds_i32 = __attribute__((address_space(3))) int;
+
+constexpr int kHierPF = 8;
 
 __device__ __forceinline__ int hsplit(int s, int e) { return s + (e - s + 1) / 2 - 1; }
 
@@ -55,8 +75,8 @@ struct HierChain {
     int K, n, lane, wv;
     float Tf, sign;
     bool lv[LPL];
-    float* lds;      // this wave's staging of one small part
-    int* stk_small;  // this wave's part stack inside a small part
+    lds_f32* lds;        // this wave's staging of one small part
+    lds_i32* stk_small;  // this wave's part stack inside a small part
 
     __device__ HierChain(const SweepArgs& a, float* msg_right, int chain) {
         K = a.K;
@@ -224,23 +244,23 @@ struct HierChain {
     };
     struct Lds {
         const HierChain* h;
-        float* base;  // [3][kHierChunk][64 * LPL] then the part's kHierChunk - 1 edge weights
+        lds_f32* base;  // [3][kHierChunk][64 * LPL] then the part's kHierChunk - 1 edge weights
         int s;
-        __device__ __forceinline__ float* at(int arr, int k) const {
+        __device__ __forceinline__ lds_f32* at(int arr, int k) const {
             return base + ((size_t)arr * kHierChunk + (k - s)) * (64 * LPL) + h->lane * LPL;
         }
         __device__ __forceinline__ void load_r(int k, float (&r)[LPL]) const {
-            const float* p = at(0, k);
+            const lds_f32* p = at(0, k);
 #pragma unroll
             for (int i = 0; i < LPL; ++i) r[i] = h->lv[i] ? p[i] : kBig;
         }
         __device__ __forceinline__ void load_m(bool left, int k, float (&m)[LPL]) const {
-            const float* p = at(left ? 1 : 2, k);
+            const lds_f32* p = at(left ? 1 : 2, k);
 #pragma unroll
             for (int i = 0; i < LPL; ++i) m[i] = p[i];
         }
         __device__ __forceinline__ void store_m(bool left, int k, const float (&m)[LPL]) const {
-            float* p = at(left ? 1 : 2, k);
+            lds_f32* p = at(left ? 1 : 2, k);
 #pragma unroll
             for (int i = 0; i < LPL; ++i) p[i] = m[i];
         }
@@ -345,7 +365,8 @@ struct HierChain {
     // s..cut and those from the right on cut+1..e) and its parts depth first, down to
     // single nodes.
     template <class M>
-    __device__ __forceinline__ void split_parts(const M& mem, int* stk, int s0, int e0, bool& first, double& opt) const {
+    __device__ __forceinline__ void split_parts(const M& mem, lds_i32* stk, int s0, int e0, bool& first,
+                                                double& opt) const {
         double unused = 0.0;  // the parts' normalisation constants are not the optimum's
         float pji[LPL], pij[LPL];
         int sp = 1;
@@ -401,13 +422,13 @@ struct HierChain {
 #pragma unroll
         for (int j = 0; j < kHierChunk; ++j) {
             if (j < m) {
-                float* p = L.at(0, s + j);
+                lds_f32* p = L.at(0, s + j);
 #pragma unroll
                 for (int i = 0; i < LPL; ++i) p[i] = rr[j][i];
                 L.store_m(s + j <= cut, s + j, mg[j]);
             }
         }
-        float* wl = lds + (size_t)3 * kHierChunk * (64 * LPL);
+        lds_f32* wl = lds + (size_t)3 * kHierChunk * (64 * LPL);
         if (lane == 0) {
 #pragma unroll
             for (int j = 0; j < kHierChunk - 1; ++j)
@@ -562,8 +583,8 @@ __global__ __launch_bounds__(64 * NW) void hier_chain_kernel(SweepArgs a, float*
     extern __shared__ float part[];  // per wave: [3][chunk][64 * LPL], then chunk weights
     const int chain = blockIdx.x;
     HC hc(a, msg_right, chain);
-    hc.lds = part + (size_t)hc.wv * HC::kLdsFloats;
-    hc.stk_small = stk[hc.wv];
+    hc.lds = (lds_f32*)(part + (size_t)hc.wv * HC::kLdsFloats);
+    hc.stk_small = (lds_i32*)stk[hc.wv];
     hc.run(a.opt != nullptr ? a.opt + chain : nullptr, opt_share);
 }
 
@@ -607,11 +628,19 @@ hipError_t launch_lpl(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStre
 
 }  // namespace
 
+#define DM_HIER_FN2(n) launch_hier_lpl##n
+#define DM_HIER_FN(n) DM_HIER_FN2(n)
+hipError_t DM_HIER_FN(DM_HIER_LPL)(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st) {
+    return launch_lpl<DM_HIER_LPL>(a, msg_right, dt, st);
+}
+
+#else  // DM_HIER_LPL == 0
+
 hipError_t launch_hier_half_step(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st) {
-    if (a.K <= 64) return launch_lpl<1>(a, msg_right, dt, st);
-    if (a.K <= 128) return launch_lpl<2>(a, msg_right, dt, st);
-    if (a.K <= 192) return launch_lpl<3>(a, msg_right, dt, st);
-    if (a.K <= 256) return launch_lpl<4>(a, msg_right, dt, st);
+    if (a.K <= 64) return launch_hier_lpl1(a, msg_right, dt, st);
+    if (a.K <= 128) return launch_hier_lpl2(a, msg_right, dt, st);
+    if (a.K <= 192) return launch_hier_lpl3(a, msg_right, dt, st);
+    if (a.K <= 256) return launch_hier_lpl4(a, msg_right, dt, st);
     return hipErrorInvalidValue;
 }
 
@@ -630,5 +659,7 @@ double hier_half_step_bytes(const SweepArgs& a, dm_dtype dt) {
     const double per = step * (1.0 + 0.5 * deep) + (b + 4.0 + 4.0) + 4.0;  // + LDS part in, dual out
     return per * (double)a.n * a.n_chains * a.K;
 }
+
+#endif  // DM_HIER_LPL
 
 }  // namespace dm
