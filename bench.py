@@ -168,6 +168,13 @@ def batched_extra(torch, ops, dev, n=64, seed=4000, n_iters=20, T=3, warps=5, it
                            for d in plan.instances))
     finally:
         plan.close()
+    # the same work as one graph of per-instance kernel chains on forked streams
+    # (instances advance through their half-steps independently)
+    splan = ops.BatchedGradPlan(inst16, T=T, n_iters=n_iters, refine=rkw, n_streams=8, want_grad=False)
+    try:
+        ms_s = _timed(splan.run, reps, torch)
+    finally:
+        splan.close()
     ws, rws = None, None
     duals = [torch.empty(d["cost"].shape, dtype=torch.float32, device=dev) for d in inst32]
     bounds = [torch.empty(2, dtype=torch.float64, device=dev) for _ in inst32]
@@ -190,6 +197,8 @@ def batched_extra(torch, ops, dev, n=64, seed=4000, n_iters=20, T=3, warps=5, it
             "bounds_lb_le_e_all": lb_le_e,
             "label_nodes": nodes, "plan_build_s": plan_s, "plan_device_GB": dev_gb,
             "batched_fp16_ms": ms_b, "batched_fp16_updates_per_s": updates / (ms_b * 1e-3),
+            "streams_plan_fp16_ms": ms_s, "streams_plan_note": "per-instance kernel chains on 8 forked streams of "
+                                                              "one graph (dm_plan_batched_grad, forward only)",
             "plain_fp32_ms": ms_p, "plain_fp32_updates_per_s": updates / (ms_p * 1e-3),
             "speedup_vs_plain_fp32": ms_p / ms_b}
 

@@ -398,9 +398,11 @@ int dm_plan_batched(const dm_instance* inst, int n, dm_dtype cost_dtype, const d
  * given) and the Dual_MM adjoint, added into grad_cost / grad_w_h / grad_w_v - the calls
  * dm_solve_discrete, dm_refine_continuous, dm_refine_continuous_backward and
  * dm_solve_discrete_backward of this header, with their meaning, captured once into
- * one hipGraph.  Instance i runs on forked stream i % n_streams (1..16): instances
- * advance through their half-steps independently, those of one stream one after
- * another, sharing that stream's workspaces, which the plan owns.  Outputs per run:
+ * one hipGraph.  With grad_cost NULL for every instance the plan is the forward only
+ * (Dual_MM and the refinement; any keep_checkpoints).  The instances run on n_streams
+ * (1..16) forked streams, largest (W*H*K) first to the stream with the least work so
+ * far: instances advance through their half-steps independently, those of one stream
+ * one after another, sharing that stream's workspaces, which the plan owns.  Outputs per run:
  * labels, dual, minmarg and bounds (each may be NULL but labels and dual), u; the
  * gradients overwritten.  Loss inputs per instance (device, read at run time):
  * grad_minmarg [H][W][K], grad_bounds [2] = {dL/dLB, dL/dE}, grad_u [H][W] (each may be
@@ -420,7 +422,7 @@ typedef struct {
     const float* grad_minmarg;   /* [H][W][K] dL/dminmarg or NULL                     */
     const double* grad_bounds;   /* [2] {dL/dLB, dL/dE} or NULL                       */
     const float* grad_u;         /* [H][W] dL/du or NULL                              */
-    float* grad_cost;            /* [H][W][K] float32 output                          */
+    float* grad_cost;            /* [H][W][K] float32 output (NULL: forward only)     */
     float* grad_w_h;             /* [H][W-1] output or NULL                           */
     float* grad_w_v;             /* [H-1][W] output or NULL                           */
 } dm_grad_instance;

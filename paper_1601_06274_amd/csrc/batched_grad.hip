@@ -1,12 +1,14 @@
-// batched_grad.hip - forward and backward of many instances as one captured graph.
+// batched_grad.hip - many instances, each its own chain of kernels, as one captured graph.
 //
 // The differentiation workload: every instance runs Dual_MM keeping what its backward
 // needs (Sec. 2.3, Alg. Dual_MM), the refinement keeping its prox branches (Sec. 2.4,
-// Sec. 3.1), then the refinement adjoint and the Dual_MM adjoint.  One instance's chain
-// families fill only part of the chip, so the instances run on forked streams of one
-// graph: each instance's kernels form a chain of their own, and instances advance
-// through their half-steps independently (no barrier common to all instances).
-// Instances of one stream run one after another and share that stream's workspaces.
+// Sec. 3.1), then the refinement adjoint and the Dual_MM adjoint; without gradient
+// buffers, the forward only (Dual_MM and refinement).  One instance's chain families fill
+// only part of the chip, so the instances run on forked streams of one graph: each
+// instance's kernels form a chain of their own, and instances advance through their
+// half-steps independently (no barrier common to all instances).  Instances go to the
+// streams largest first, each to the stream with the least work so far (work ~ W*H*K);
+// those of one stream run one after another and share that stream's workspaces.
 #include <algorithm>
 #include <string>
 #include <vector>
@@ -38,20 +40,35 @@ extern "C" int dm_plan_batched_grad(const dm_grad_instance* inst, int n, dm_dtyp
     DM_REQUIRE(n >= 1 && n <= 4096, DM_ERR_PARAM, "n=%d instances out of range [1, 4096]", n);
     DM_REQUIRE(n_streams >= 1 && n_streams <= 16, DM_ERR_PARAM, "n_streams=%d out of range [1, 16]", n_streams);
     DM_REQUIRE(cost_dtype == DM_F32 || cost_dtype == DM_F16, DM_ERR_DTYPE, "unknown cost dtype");
-    DM_REQUIRE(p->keep_checkpoints == 1 || p->keep_checkpoints == 2, DM_ERR_PARAM,
-               "the forward must keep checkpoints for the backward (keep_checkpoints 1 or 2)");
     DM_REQUIRE(p->warm_start == 0, DM_ERR_UNSUPPORTED, "batched gradient plans start every run from dual 0");
+    // with gradients every instance has grad_cost; forward only: none has
+    const bool grad = inst[0].grad_cost != nullptr;
+    DM_REQUIRE(!grad || p->keep_checkpoints == 1 || p->keep_checkpoints == 2, DM_ERR_PARAM,
+               "the forward must keep checkpoints for the backward (keep_checkpoints 1 or 2)");
     dm_refine_params rq{};
     if (rp != nullptr) {
         rq = *rp;
-        rq.keep_tape = 1;  // the refinement adjoint reads the forward's branch tape
+        rq.keep_tape = grad ? 1 : 0;  // the refinement adjoint reads the forward's branch tape
     }
     const int S = n_streams < n ? n_streams : n;
+    // streams by work, largest instance first to the least loaded stream
+    std::vector<int> order(n), stream_of(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    auto work = [&](int i) { return (double)inst[i].s.W * inst[i].s.H * inst[i].s.K; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+    std::vector<double> load(S, 0.0);
+    for (int i : order) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        stream_of[i] = k;
+        load[k] += work(i);
+    }
     std::vector<StreamWs> ws(S);
     for (int i = 0; i < n; ++i) {
         const dm_grad_instance& I = inst[i];
-        DM_REQUIRE(I.cost != nullptr && I.dual != nullptr && I.labels != nullptr && I.grad_cost != nullptr,
-                   DM_ERR_NULL, "instance %d: cost, dual, labels and grad_cost are required", i);
+        DM_REQUIRE(I.cost != nullptr && I.dual != nullptr && I.labels != nullptr, DM_ERR_NULL,
+                   "instance %d: cost, dual and labels are required", i);
+        DM_REQUIRE((I.grad_cost != nullptr) == grad, DM_ERR_NULL,
+                   "instance %d: grad_cost must be given for every instance or for none", i);
         DM_REQUIRE(rp == nullptr || I.u != nullptr, DM_ERR_NULL, "instance %d: u required with refinement", i);
         const size_t f = dm_solve_discrete_workspace(I.s, cost_dtype, p);
         if (f == 0) {
@@ -59,13 +76,12 @@ extern "C" int dm_plan_batched_grad(const dm_grad_instance* inst, int n, dm_dtyp
             set_error("instance %d: %s", i, why.c_str());
             return DM_ERR_PARAM;
         }
-        const size_t b = dm_solve_discrete_backward_workspace(I.s, p);
-        StreamWs& w = ws[i % S];
+        StreamWs& w = ws[stream_of[i]];
         w.fwd_b = std::max(w.fwd_b, f);
-        w.bwd_b = std::max(w.bwd_b, b);
+        if (grad) w.bwd_b = std::max(w.bwd_b, dm_solve_discrete_backward_workspace(I.s, p));
         if (rp != nullptr) {
             w.ref_b = std::max(w.ref_b, dm_refine_continuous_workspace(I.s, &rq));
-            w.refb_b = std::max(w.refb_b, dm_refine_continuous_backward_workspace(I.s, &rq));
+            if (grad) w.refb_b = std::max(w.refb_b, dm_refine_continuous_backward_workspace(I.s, &rq));
         }
     }
     hipError_t e0 = hipGetLastError();
@@ -81,12 +97,13 @@ extern "C" int dm_plan_batched_grad(const dm_grad_instance* inst, int n, dm_dtyp
     };
     for (StreamWs& w : ws) {
         w.fwd = plan->alloc<char>(w.fwd_b);
-        w.bwd = plan->alloc<char>(w.bwd_b);
-        if (!w.fwd || !w.bwd) return fail_hip("workspace allocation", hipErrorOutOfMemory);
+        if (!w.fwd) return fail_hip("workspace allocation", hipErrorOutOfMemory);
+        if (grad && !(w.bwd = plan->alloc<char>(w.bwd_b))) return fail_hip("workspace allocation", hipErrorOutOfMemory);
         if (rp != nullptr) {
             w.ref = plan->alloc<char>(w.ref_b);
-            w.refb = plan->alloc<char>(w.refb_b);
-            if (!w.ref || !w.refb) return fail_hip("workspace allocation", hipErrorOutOfMemory);
+            if (!w.ref) return fail_hip("workspace allocation", hipErrorOutOfMemory);
+            if (grad && !(w.refb = plan->alloc<char>(w.refb_b)))
+                return fail_hip("workspace allocation", hipErrorOutOfMemory);
         }
     }
 
@@ -117,18 +134,18 @@ extern "C" int dm_plan_batched_grad(const dm_grad_instance* inst, int n, dm_dtyp
     for (int k = 0; k < S && ce == hipSuccess; ++k) ce = hipStreamWaitEvent(side[k], ev_fork, 0);
     for (int i = 0; i < n && st == DM_OK && ce == hipSuccess; ++i) {
         const dm_grad_instance& I = inst[i];
-        const StreamWs& w = ws[i % S];
-        void* s2 = side[i % S];
+        const StreamWs& w = ws[stream_of[i]];
+        void* s2 = side[stream_of[i]];
         st = dm_solve_discrete(I.cost, cost_dtype, I.w_h, I.w_v, I.s, p, I.labels, I.minmarg, I.dual, I.bounds,
                                nullptr, w.fwd, w.fwd_b, s2);
         if (st == DM_OK && rp != nullptr) {
             st = dm_refine_continuous(I.cost, cost_dtype, I.labels, I.w_h, I.w_v, I.s, &rq, I.u, w.ref, w.ref_b, s2);
-            if (st == DM_OK && I.grad_u != nullptr)
+            if (st == DM_OK && grad && I.grad_u != nullptr)
                 st = dm_refine_continuous_backward(I.grad_u, I.cost, cost_dtype, I.w_h, I.w_v, I.s, &rq, w.ref, w.ref_b,
                                                    I.grad_cost, I.grad_w_h, I.grad_w_v, 0, w.refb, w.refb_b, s2);
         }
         const int acc = (rp != nullptr && I.grad_u != nullptr) ? 1 : 0;
-        if (st == DM_OK)
+        if (st == DM_OK && grad)
             st = dm_solve_discrete_backward(I.grad_minmarg, I.grad_bounds, I.cost, cost_dtype, I.w_h, I.w_v, I.s, p,
                                             I.dual, w.fwd, w.fwd_b, I.grad_cost, I.grad_w_h, I.grad_w_v, acc, w.bwd,
                                             w.bwd_b, s2);

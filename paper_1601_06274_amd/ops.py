@@ -499,11 +499,14 @@ class BatchedGradPlan:
     (float64 [2]), ``grad_u`` [H][W] (each optional).  The plan allocates, unless given,
     ``labels``, ``dual``, ``minmarg`` (when grad_minmarg is given), ``bounds``, ``u`` (with
     refinement) and the gradients ``grad_cost``, ``grad_w_h``, ``grad_w_v``; every run
-    overwrites them.  Instance i runs on forked stream i % n_streams of the graph.
+    overwrites them.  With want_grad=False the plan is the forward only (no gradient
+    buffers, no loss inputs).  The instances are spread over n_streams forked streams
+    of the graph by size.
     """
 
     def __init__(self, instances, *, T=3, n_iters=20, n_half_steps=0, minorant="iterative",
-                 gammas=(0.25, 0.25, 1.0), tile=None, keep_checkpoints=2, refine=None, n_streams=8):
+                 gammas=(0.25, 0.25, 1.0), tile=None, keep_checkpoints=2, refine=None, n_streams=8,
+                 want_grad=True):
         self.instances = []
         arr = (L.DmGradInstance * len(instances))()
         dtype = instances[0]["cost"].dtype
@@ -521,9 +524,12 @@ class BatchedGradPlan:
             d.setdefault("bounds", torch.empty(2, dtype=torch.float64, device=dev))
             if refine is not None:
                 d.setdefault("u", torch.empty((H, W), dtype=torch.float32, device=dev))
-            d.setdefault("grad_cost", torch.empty((H, W, K), dtype=torch.float32, device=dev))
-            d.setdefault("grad_w_h", torch.empty((H, W - 1), dtype=torch.float32, device=dev))
-            d.setdefault("grad_w_v", torch.empty((H - 1, W), dtype=torch.float32, device=dev))
+            if want_grad:
+                d.setdefault("grad_cost", torch.empty((H, W, K), dtype=torch.float32, device=dev))
+                d.setdefault("grad_w_h", torch.empty((H, W - 1), dtype=torch.float32, device=dev))
+                d.setdefault("grad_w_v", torch.empty((H - 1, W), dtype=torch.float32, device=dev))
+            else:
+                keep_checkpoints = False
             _check_dev("cost", cost)
             for k, dt_, shp in (("w_h", torch.float32, (H, W - 1)), ("w_v", torch.float32, (H - 1, W)),
                                 ("labels", torch.int32, (H, W)), ("dual", torch.float32, (H, W, K)),

@@ -223,3 +223,32 @@ def test_batched_grad_plan_equals_eager(dtype):
                     assert torch.equal(pi[k], v), f"replay {rep} instance {i}: {k} differs"
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("n_streams", [1, 3])
+def test_batched_forward_plan_on_streams_equals_eager(n_streams):
+    """dm_plan_batched_grad without gradients: each instance's Dual_MM and refinement on
+    forked streams of one graph (instances spread by size); labels, duals, min-marginals,
+    bounds and refined disparities equal the single-instance calls bit for bit."""
+    ops = _need()
+    specs = [(6, 9, 8, 31), (10, 7, 16, 32), (5, 14, 12, 33), (4, 6, 5, 34), (8, 8, 24, 35), (3, 11, 9, 36)]
+    insts = _instances(specs, torch.float16)
+    kw = dict(T=3, n_iters=3)
+    rkw = dict(C=3.0, n_warps=2, n_iters=9)
+    plan = ops.BatchedGradPlan([{k: d[k] for k in ("cost", "w_h", "w_v")} for d in insts], refine=rkw,
+                               n_streams=n_streams, want_grad=False, **kw)
+    try:
+        refs = []
+        for d in insts:
+            r = ops.solve_discrete(d["cost"], d["w_h"], d["w_v"], want_minmarg=False, **kw)
+            u = ops.refine_continuous(d["cost"], r.labels, d["w_h"], d["w_v"], **rkw)
+            refs.append(dict(labels=r.labels, dual=r.dual, bounds=r.bounds, u=u))
+        torch.cuda.synchronize()
+        for rep in range(2):
+            plan.run()
+            torch.cuda.synchronize()
+            for i, (pi, ref) in enumerate(zip(plan.instances, refs)):
+                for k, v in ref.items():
+                    assert torch.equal(pi[k], v), f"replay {rep} instance {i}: {k} differs"
+    finally:
+        plan.close()
