@@ -19,29 +19,18 @@ namespace dm {
 
 // Branch codes of the conjugate prox (3 bits): 0 = identity slope in t, 1 / 2 = flat at
 // +alpha*w / -alpha*w, 3 / 4 = clamped at +w / -w.
+// Written with selects (every candidate computed, no divergent branches).
 __device__ __forceinline__ rfloat prox_conj(rfloat t, rfloat w, rfloat alpha, rfloat beta, rfloat step, int& code) {
     const rfloat a = fabs(t);
     const rfloat aw = alpha * w;
-    rfloat r;
-    code = 0;
-    if (a <= aw) {
-        r = t;
-    } else {
-        const rfloat sh = a - beta * step;
-        if (sh < aw) {
-            r = copysign(aw, t);
-            code = t > 0.0 ? 1 : 2;
-        } else {
-            r = copysign(sh, t);
-        }
-    }
-    if (r < -w) {
-        r = -w;
-        code = 4;
-    } else if (r > w) {
-        r = w;
-        code = 3;
-    }
+    const rfloat sh = a - beta * step;
+    const bool inner = a <= aw;
+    const bool flat = !inner && sh < aw;
+    rfloat r = inner ? t : copysign(flat ? aw : sh, t);
+    const int c = flat ? (t > 0.0 ? 1 : 2) : 0;
+    const bool lo = r < -w, hi = r > w;
+    r = lo ? -w : (hi ? w : r);
+    code = lo ? 4 : (hi ? 3 : c);
     return r;
 }
 
@@ -138,13 +127,14 @@ __device__ __forceinline__ void pdhg_fused_tile(const RefineState& in, const Ref
     const int ox = x0 - S, oy = y0 - S;
     const rfloat kmax = (rfloat)(K - 1);
     // per-pixel constants of the launch stay in registers: the data model and the weights
+    // (in their storage type, widened where used)
     typename DataProx::Px dm[PPT];
-    rfloat wh[PPT], wv[PPT];
+    float wh[PPT], wv[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int idx = (int)threadIdx.x + k * NT;
-        wh[k] = 0.0;
-        wv[k] = 0.0;
+        wh[k] = 0.0f;
+        wv[k] = 0.0f;
         dm[k] = typename DataProx::Px{};
         if (idx >= NP) break;
         const int x = ox + idx % RX, y = oy + idx / RX;
@@ -157,8 +147,8 @@ __device__ __forceinline__ void pdhg_fused_tile(const RefineState& in, const Ref
             qh = in.qh[p];
             qv = in.qv[p];
             dm[k] = prox.load(p);
-            if (x + 1 < W) wh[k] = (rfloat)w_h[(long long)y * (W - 1) + x];
-            if (y + 1 < H) wv[k] = (rfloat)w_v[p];
+            if (x + 1 < W) wh[k] = w_h[(long long)y * (W - 1) + x];
+            if (y + 1 < H) wv[k] = w_v[p];
         }
         s_u[0][idx] = u;
         s_ph[idx] = ph;
@@ -206,19 +196,21 @@ __device__ __forceinline__ void pdhg_fused_tile(const RefineState& in, const Ref
             if (x + 1 < W) {
                 const int r = rx + 1 < RX ? idx + 1 : idx;  // beyond the region: a value that is never used
                 const rfloat gq = uo - s_u[cur][r];
-                s_qh[idx] = prox_conj(s_qh[idx] + sc.tau * gq, wh[k], 0.0, sc.beta_minus, sc.tau, c);
+                const rfloat w = (rfloat)wh[k];
+                s_qh[idx] = prox_conj(s_qh[idx] + sc.tau * gq, w, 0.0, sc.beta_minus, sc.tau, c);
                 m |= (uint32_t)c << 4;
                 const rfloat gp = (2.0 * un - uo) - (2.0 * s_u[cur ^ 1][r] - s_u[cur][r]);
-                s_ph[idx] = prox_conj(s_ph[idx] + sc.sigma * gp, wh[k], sc.eps, sc.delta, sc.sigma, c);
+                s_ph[idx] = prox_conj(s_ph[idx] + sc.sigma * gp, w, sc.eps, sc.delta, sc.sigma, c);
                 m |= (uint32_t)c << 10;
             }
             if (y + 1 < H) {
                 const int d = ry + 1 < RY ? idx + RX : idx;
                 const rfloat gq = uo - s_u[cur][d];
-                s_qv[idx] = prox_conj(s_qv[idx] + sc.tau * gq, wv[k], 0.0, sc.beta_minus, sc.tau, c);
+                const rfloat w = (rfloat)wv[k];
+                s_qv[idx] = prox_conj(s_qv[idx] + sc.tau * gq, w, 0.0, sc.beta_minus, sc.tau, c);
                 m |= (uint32_t)c << 7;
                 const rfloat gp = (2.0 * un - uo) - (2.0 * s_u[cur ^ 1][d] - s_u[cur][d]);
-                s_pv[idx] = prox_conj(s_pv[idx] + sc.sigma * gp, wv[k], sc.eps, sc.delta, sc.sigma, c);
+                s_pv[idx] = prox_conj(s_pv[idx] + sc.sigma * gp, w, sc.eps, sc.delta, sc.sigma, c);
                 m |= (uint32_t)c << 13;
             }
             const bool central = rx >= S && rx < S + TX && ry >= S && ry < S + TY;
@@ -243,8 +235,10 @@ __device__ __forceinline__ void pdhg_fused_tile(const RefineState& in, const Ref
     }
 }
 
-// Fused tile shape: 32 x 16 outputs, 4 iterations per launch (a 40 x 24 region, 46 KB of LDS).
-constexpr int kFTX = 32, kFTY = 16, kFS = 4;
+// Fused tile shape: 32 x 20 outputs, 3 iterations per launch: a 38 x 26 region (47.4 KB of
+// LDS in the forward), so three blocks share a CU (with at most 168 VGPRs per thread) and
+// the 741 blocks of a 1242 x 375 frame are all resident at once.
+constexpr int kFTX = 32, kFTY = 20, kFS = 3;
 
 
 }  // namespace dm

@@ -31,10 +31,11 @@
 // launch latency, not HBM.
 //
 // Adjoint (reverse mode).  Every map of the iteration is piecewise linear; given the
-// recorded branches, the adjoint of one iteration is a linear stencil with the same
-// tile / halo structure (pdhg_adjoint_kernel).  At the start of each warp (processed in
-// reverse) the accumulated adjoints of the slopes and of u0 are pushed through the
-// linearisation into the cost volume and into u (linearize_adjoint_kernel).  At kinks
+// recorded branches, the adjoint of one iteration is a linear stencil reaching one pixel,
+// run kFS reverse iterations per launch by temporal tiling (pdhg_adjoint_fused_kernel).
+// At the start of each warp (processed in reverse) the accumulated adjoints of the
+// slopes and of u0 are pushed through the linearisation into the cost volume and into u
+// (linearize_adjoint_kernel).  At kinks
 // (exact ties of a branch test) the derivative of the branch that the forward took is
 // used; on the interpolated data term at integer arguments the segment [k, k+1].
 #include <algorithm>
@@ -100,30 +101,18 @@ __global__ __launch_bounds__(256) void linearize_kernel(const TT* __restrict__ t
 
 // prox of tau * D~ (two-slope soft threshold) and the box [u0 - h, u0 + h] n [0, K-1].
 // code: bits 0-1 zone (0 middle, 1 right slope, 2 left slope), bits 2-3 clamp (0, 1 low, 2 high).
+// (with selects: every candidate computed, no divergent branches)
 __device__ __forceinline__ rfloat prox_data(rfloat uh, rfloat u0, rfloat l, rfloat r, rfloat tau, rfloat h, rfloat kmax,
                                             int& code) {
-    rfloat v;
-    int zone;
-    if (uh > u0 + tau * r) {
-        v = uh - tau * r;
-        zone = 1;
-    } else if (uh < u0 + tau * l) {
-        v = uh - tau * l;
-        zone = 2;
-    } else {
-        v = u0;
-        zone = 0;
-    }
+    const bool zr = uh > u0 + tau * r;
+    const bool zl = !zr && uh < u0 + tau * l;
+    rfloat v = zr ? uh - tau * r : (zl ? uh - tau * l : u0);
+    const int zone = zr ? 1 : (zl ? 2 : 0);
     const rfloat lo = fmax(u0 - h, 0.0);
     const rfloat hi = fmin(u0 + h, kmax);
-    int cl = 0;
-    if (v < lo) {
-        v = lo;
-        cl = 1;
-    } else if (v > hi) {
-        v = hi;
-        cl = 2;
-    }
+    const bool below = v < lo, above = !below && v > hi;
+    v = below ? lo : (above ? hi : v);
+    const int cl = below ? 1 : (above ? 2 : 0);
     code = zone | (cl << 2);
     return v;
 }
@@ -153,7 +142,7 @@ __global__ __launch_bounds__(256) void pdhg_kernel(const RefineState in, RefineS
               blockIdx.y * kTY);
 }
 
-__global__ __launch_bounds__(256) void pdhg_fused_kernel(const RefineState in, RefineState out,
+__global__ __launch_bounds__(256, 3) void pdhg_fused_kernel(const RefineState in, RefineState out,
                                                          const rfloat* __restrict__ u0, const rfloat* __restrict__ sL,
                                                          const rfloat* __restrict__ sR, const float* __restrict__ w_h,
                                                          const float* __restrict__ w_v, int W, int H, int K,
@@ -234,103 +223,183 @@ hipError_t launch_batched_refine(const RefBatchInst* insts, const RefChunk* chun
     return hipGetLastError();
 }
 
-// d(prox)/dt for a conjugate-prox branch code, and d(prox)/dw.
+// d(prox)/dt for a conjugate-prox branch code, and d(prox)/dw (alpha, -alpha, 1, -1 for
+// codes 1-4, else 0), as selects.
 __device__ __forceinline__ rfloat conj_dt(int code) { return code == 0 ? 1.0 : 0.0; }
 __device__ __forceinline__ rfloat conj_dw(int code, rfloat alpha) {
-    switch (code) {
-        case 1: return alpha;
-        case 2: return -alpha;
-        case 3: return 1.0;
-        case 4: return -1.0;
-        default: return 0.0;
-    }
+    const rfloat s = (code == 1 || code == 3) ? 1.0 : ((code == 2 || code == 4) ? -1.0 : 0.0);
+    return code >= 3 ? s : s * alpha;
 }
 
-// Adjoint of one iteration.  nxt: adjoints of the iteration's outputs (u+, p+, q+);
-// prv: adjoints of its inputs (u, p, q).  Accumulates the adjoints of u0, s_L, s_R
-// (per pixel) and of the edge weights (per edge).
-__global__ __launch_bounds__(256) void pdhg_adjoint_kernel(const RefineState nxt, RefineState prv,
-                                                           const uint16_t* __restrict__ mask,
-                                                           const rfloat* __restrict__ u0, int W, int H, int K,
-                                                           RefineScalars sc, rfloat* __restrict__ acc_u0,
-                                                           rfloat* __restrict__ acc_sL, rfloat* __restrict__ acc_sR,
-                                                           rfloat* __restrict__ acc_wh, rfloat* __restrict__ acc_wv) {
-    __shared__ rfloat s_uhb[kTY + 1][kTX + 1];
-    __shared__ rfloat s_ubt[kTY][kTX];
-    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY;
+// n_iter <= kFS reverse iterations per launch (temporal tiling, as pdhg_fused_tile): the
+// adjoint of iteration it reaches one pixel (diagonals included), so a TX x TY output
+// tile is exact after n_iter iterations on the tile extended by kFS pixels on every side.
+// The adjoint state sits in LDS between iterations; the accumulators of the tile's pixels
+// (u0, slopes, edge weights) are loaded once, carried in registers in the order of the
+// single-iteration kernel's additions and stored once, so the results equal that
+// kernel's bit for bit.  Per iteration: the branch masks of the region into LDS; phase A
+// the adjoint of u-hat and the new u adjoint (from the own and the left / upper edges);
+// phase B the edge adjoints in place and the accumulators.  mask_hi: the mask plane of
+// the launch's first (latest) iteration; earlier iterations lie mask_stride elements
+// below, one plane each.
+__global__ __launch_bounds__(256) void pdhg_adjoint_fused_kernel(const RefineState nxt, RefineState prv,
+                                                                 const uint16_t* __restrict__ mask_hi,
+                                                                 size_t mask_stride, int n_iter,
+                                                                 const rfloat* __restrict__ u0, int W, int H, int K,
+                                                                 RefineScalars sc, rfloat* __restrict__ acc_u0,
+                                                                 rfloat* __restrict__ acc_sL, rfloat* __restrict__ acc_sR,
+                                                                 rfloat* __restrict__ acc_wh,
+                                                                 rfloat* __restrict__ acc_wv) {
+    constexpr int TX = kFTX, TY = kFTY, S = kFS;
+    constexpr int RX = TX + 2 * S, RY = TY + 2 * S, NP = RX * RY;
+    constexpr int NT = 256, PPT = (NP + NT - 1) / NT;
+    // the u adjoint of a pixel is read and written by that pixel only: in registers
+    __shared__ rfloat s_ph[NP], s_pv[NP], s_qh[NP], s_qv[NP], s_uhb[NP];
+    __shared__ uint16_t s_m[NP];
+    const int ox = (int)blockIdx.x * TX - S, oy = (int)blockIdx.y * TY - S;
     const rfloat kmax = (rfloat)(K - 1);
-    // Phase A: adjoint of uh (before the u-prox) on the tile and its right / lower halo.
-    for (int idx = threadIdx.x; idx < (kTX + 1) * (kTY + 1); idx += blockDim.x) {
-        const int i = idx % (kTX + 1), j = idx / (kTX + 1);
-        const int x = x0 + i, y = y0 + j;
-        rfloat uhb = 0.0;
-        if (x < W && y < H) {
+    // per slot: the pixel's u0, and for the tile's own pixels the accumulators
+    rfloat su[PPT], c0[PPT], a_u0[PPT], a_sL[PPT], a_sR[PPT], a_wh[PPT], a_wv[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int idx = (int)threadIdx.x + k * NT;
+        su[k] = c0[k] = a_u0[k] = a_sL[k] = a_sR[k] = a_wh[k] = a_wv[k] = 0.0;
+        if (idx >= NP) break;
+        const int rx = idx % RX, ry = idx / RX;
+        const int x = ox + rx, y = oy + ry;
+        rfloat u = 0.0, ph = 0.0, pv = 0.0, qh = 0.0, qv = 0.0;
+        if (x >= 0 && x < W && y >= 0 && y < H) {
             const long long p = (long long)y * W + x;
-            const uint32_t m = mask[p];
-            rfloat atp = 0.0;  // (A^T pbar_hat)_i
-            if (x + 1 < W) atp += nxt.ph[p] * conj_dt(mfield(m, 10, 3));
-            if (y + 1 < H) atp += nxt.pv[p] * conj_dt(mfield(m, 13, 3));
-            if (x > 0) atp -= nxt.ph[p - 1] * conj_dt(mfield(mask[p - 1], 10, 3));
-            if (y > 0) atp -= nxt.pv[p - W] * conj_dt(mfield(mask[p - W], 13, 3));
-            const rfloat ubt = nxt.u[p] + 2.0 * sc.sigma * atp;
-            const int zone = mfield(m, 0, 2), cl = mfield(m, 2, 2);
-            uhb = (cl == 0 && zone != 0) ? ubt : 0.0;
-            if (i < kTX && j < kTY) s_ubt[j][i] = ubt;
+            u = nxt.u[p];
+            ph = nxt.ph[p];
+            pv = nxt.pv[p];
+            qh = nxt.qh[p];
+            qv = nxt.qv[p];
+            c0[k] = u0[p];
+            if (rx >= S && rx < S + TX && ry >= S && ry < S + TY) {
+                a_u0[k] = acc_u0[p];
+                a_sL[k] = acc_sL[p];
+                a_sR[k] = acc_sR[p];
+                a_wh[k] = acc_wh[p];
+                a_wv[k] = acc_wv[p];
+            }
         }
-        s_uhb[j][i] = uhb;
+        su[k] = u;
+        s_ph[idx] = ph;
+        s_pv[idx] = pv;
+        s_qh[idx] = qh;
+        s_qv[idx] = qv;
     }
-    __syncthreads();
-    const int i = threadIdx.x % kTX, j = threadIdx.x / kTX;
-    const int x = x0 + i, y = y0 + j;
-    if (x >= W || y >= H) return;
-    const long long p = (long long)y * W + x;
-    const uint32_t m = mask[p];
-    const rfloat uhb = s_uhb[j][i];
-    const rfloat ubt = s_ubt[j][i];
-    rfloat atp = 0.0, atq = 0.0;
-    if (x + 1 < W) {
-        atp += nxt.ph[p] * conj_dt(mfield(m, 10, 3));
-        atq += nxt.qh[p] * conj_dt(mfield(m, 4, 3));
+    for (int it = 0; it < n_iter; ++it) {
+        const uint16_t* mask = mask_hi - (size_t)it * mask_stride;
+        uint32_t mm[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int idx = (int)threadIdx.x + k * NT;
+            mm[k] = 0u;
+            if (idx >= NP) break;
+            const int x = ox + idx % RX, y = oy + idx / RX;
+            if (x >= 0 && x < W && y >= 0 && y < H) mm[k] = mask[(long long)y * W + x];
+            s_m[idx] = (uint16_t)mm[k];
+        }
+        __syncthreads();  // the masks, and (it > 0) the previous iteration's edges
+        rfloat ubt[PPT];
+        // Phase A: adjoint of u-hat, and the adjoint of the iteration's input u.
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int idx = (int)threadIdx.x + k * NT;
+            ubt[k] = 0.0;
+            if (idx >= NP) break;
+            const int rx = idx % RX, ry = idx / RX;
+            const int x = ox + rx, y = oy + ry;
+            rfloat uhb = 0.0, un = 0.0;
+            if (x >= 0 && x < W && y >= 0 && y < H) {
+                const uint32_t m = mm[k];
+                // (A^T p-bar-hat) and (A^T q-bar-hat): own edges, then the left / upper ones
+                rfloat atp = 0.0, atq = 0.0;
+                if (x + 1 < W) {
+                    atp += s_ph[idx] * conj_dt(mfield(m, 10, 3));
+                    atq += s_qh[idx] * conj_dt(mfield(m, 4, 3));
+                }
+                if (y + 1 < H) {
+                    atp += s_pv[idx] * conj_dt(mfield(m, 13, 3));
+                    atq += s_qv[idx] * conj_dt(mfield(m, 7, 3));
+                }
+                if (x > 0 && rx > 0) {
+                    const uint32_t ml = s_m[idx - 1];
+                    atp -= s_ph[idx - 1] * conj_dt(mfield(ml, 10, 3));
+                    atq -= s_qh[idx - 1] * conj_dt(mfield(ml, 4, 3));
+                }
+                if (y > 0 && ry > 0) {
+                    const uint32_t mu = s_m[idx - RX];
+                    atp -= s_pv[idx - RX] * conj_dt(mfield(mu, 13, 3));
+                    atq -= s_qv[idx - RX] * conj_dt(mfield(mu, 7, 3));
+                }
+                ubt[k] = su[k] + 2.0 * sc.sigma * atp;
+                const int zone = mfield(m, 0, 2), cl = mfield(m, 2, 2);
+                uhb = (cl == 0 && zone != 0) ? ubt[k] : 0.0;
+                un = uhb - sc.sigma * atp + sc.tau * atq;
+            }
+            s_uhb[idx] = uhb;
+            su[k] = un;
+        }
+        __syncthreads();
+        // Phase B: the edges' adjoints in place, the accumulators of the tile's pixels.
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int idx = (int)threadIdx.x + k * NT;
+            if (idx >= NP) break;
+            const int rx = idx % RX, ry = idx / RX;
+            const int x = ox + rx, y = oy + ry;
+            if (x < 0 || x >= W || y < 0 || y >= H) continue;
+            const uint32_t m = mm[k];
+            const rfloat uhb = s_uhb[idx];
+            if (x + 1 < W) {
+                const int cq = mfield(m, 4, 3), cp = mfield(m, 10, 3);
+                const int r = rx + 1 < RX ? idx + 1 : idx;  // beyond the region: a value that is never used
+                const rfloat du = uhb - s_uhb[r];
+                const rfloat ph = s_ph[idx], qh = s_qh[idx];
+                s_ph[idx] = ph * conj_dt(cp) - sc.tau * du;
+                s_qh[idx] = qh * conj_dt(cq) + sc.tau * du;
+                a_wh[k] += ph * conj_dw(cp, sc.eps) + qh * conj_dw(cq, 0.0);
+            }
+            if (y + 1 < H) {
+                const int cq = mfield(m, 7, 3), cp = mfield(m, 13, 3);
+                const int d = ry + 1 < RY ? idx + RX : idx;
+                const rfloat du = uhb - s_uhb[d];
+                const rfloat pv = s_pv[idx], qv = s_qv[idx];
+                s_pv[idx] = pv * conj_dt(cp) - sc.tau * du;
+                s_qv[idx] = qv * conj_dt(cq) + sc.tau * du;
+                a_wv[k] += pv * conj_dw(cp, sc.eps) + qv * conj_dw(cq, 0.0);
+            }
+            // u-prox adjoint into u0 and the slopes (selects)
+            const int zone = mfield(m, 0, 2), cl = mfield(m, 2, 2);
+            const bool pass_u0 = cl == 0 ? zone == 0 : (cl == 1 ? c0[k] - sc.h >= 0.0 : c0[k] + sc.h <= kmax);
+            a_u0[k] += ubt[k] * (pass_u0 ? 1.0 : 0.0);
+            a_sR[k] = (cl == 0 && zone == 1) ? a_sR[k] - sc.tau * ubt[k] : a_sR[k];
+            a_sL[k] = (cl == 0 && zone == 2) ? a_sL[k] - sc.tau * ubt[k] : a_sL[k];
+        }
+        __syncthreads();  // phase B's edges before the next iteration reads them
     }
-    if (y + 1 < H) {
-        atp += nxt.pv[p] * conj_dt(mfield(m, 13, 3));
-        atq += nxt.qv[p] * conj_dt(mfield(m, 7, 3));
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int idx = (int)threadIdx.x + k * NT;
+        if (idx >= NP) break;
+        const int rx = idx % RX, ry = idx / RX;
+        const int x = ox + rx, y = oy + ry;
+        if (rx < S || rx >= S + TX || ry < S || ry >= S + TY || x >= W || y >= H) continue;
+        const long long p = (long long)y * W + x;
+        prv.u[p] = su[k];
+        prv.ph[p] = s_ph[idx];
+        prv.pv[p] = s_pv[idx];
+        prv.qh[p] = s_qh[idx];
+        prv.qv[p] = s_qv[idx];
+        acc_u0[p] = a_u0[k];
+        acc_sL[p] = a_sL[k];
+        acc_sR[p] = a_sR[k];
+        acc_wh[p] = a_wh[k];
+        acc_wv[p] = a_wv[k];
     }
-    if (x > 0) {
-        const uint32_t ml = mask[p - 1];
-        atp -= nxt.ph[p - 1] * conj_dt(mfield(ml, 10, 3));
-        atq -= nxt.qh[p - 1] * conj_dt(mfield(ml, 4, 3));
-    }
-    if (y > 0) {
-        const uint32_t mu = mask[p - W];
-        atp -= nxt.pv[p - W] * conj_dt(mfield(mu, 13, 3));
-        atq -= nxt.qv[p - W] * conj_dt(mfield(mu, 7, 3));
-    }
-    prv.u[p] = uhb - sc.sigma * atp + sc.tau * atq;
-    if (x + 1 < W) {
-        const int cq = mfield(m, 4, 3), cp = mfield(m, 10, 3);
-        const rfloat du = uhb - s_uhb[j][i + 1];
-        prv.ph[p] = nxt.ph[p] * conj_dt(cp) - sc.tau * du;
-        prv.qh[p] = nxt.qh[p] * conj_dt(cq) + sc.tau * du;
-        acc_wh[p] += nxt.ph[p] * conj_dw(cp, sc.eps) + nxt.qh[p] * conj_dw(cq, 0.0);
-    }
-    if (y + 1 < H) {
-        const int cq = mfield(m, 7, 3), cp = mfield(m, 13, 3);
-        const rfloat du = uhb - s_uhb[j + 1][i];
-        prv.pv[p] = nxt.pv[p] * conj_dt(cp) - sc.tau * du;
-        prv.qv[p] = nxt.qv[p] * conj_dt(cq) + sc.tau * du;
-        acc_wv[p] += nxt.pv[p] * conj_dw(cp, sc.eps) + nxt.qv[p] * conj_dw(cq, 0.0);
-    }
-    // u-prox adjoint into u0 and the slopes
-    const int zone = mfield(m, 0, 2), cl = mfield(m, 2, 2);
-    const rfloat c0 = u0[p];
-    rfloat d_u0 = 0.0;
-    if (cl == 0) d_u0 = zone == 0 ? 1.0 : 0.0;
-    else if (cl == 1) d_u0 = (c0 - sc.h >= 0.0) ? 1.0 : 0.0;
-    else d_u0 = (c0 + sc.h <= kmax) ? 1.0 : 0.0;
-    acc_u0[p] += ubt * d_u0;
-    if (cl == 0 && zone == 1) acc_sR[p] -= sc.tau * ubt;
-    if (cl == 0 && zone == 2) acc_sL[p] -= sc.tau * ubt;
 }
 
 // Adjoint of the per-warp linearisation at u0: pushes the accumulated slope / u0
@@ -640,15 +709,18 @@ extern "C" int dm_refine_continuous_backward(const float* grad_u, const void* co
                        acc_wh, acc_wv);
     DM_HIP_TRY(hipGetLastError(), "adjoint init");
     const RefineScalars sc = refine_scalars(*p);
-    const dim3 grid((s.W + kTX - 1) / kTX, (s.H + kTY - 1) / kTY);
+    const dim3 fgrid((s.W + kFTX - 1) / kFTX, (s.H + kFTY - 1) / kFTY);
     int cur = 0;
     for (int wp = p->n_warps - 1; wp >= 0; --wp) {
         const rfloat* u0 = reinterpret_cast<const rfloat*>(fws + LF.tape_u0 + (size_t)wp * LF.plane);
-        for (int it = p->n_iters - 1; it >= 0; --it) {
+        // kFS reverse iterations per launch, the adjoint state on chip in between
+        for (int hi = p->n_iters - 1; hi >= 0; hi -= kFS) {
+            const int nit = std::min(kFS, hi + 1);
             const uint16_t* mask = reinterpret_cast<const uint16_t*>(
-                fws + LF.tape_mask + ((size_t)wp * p->n_iters + it) * LF.mask_plane);
-            hipLaunchKernelGGL(pdhg_adjoint_kernel, grid, dim3(256), 0, stream, A[cur], A[cur ^ 1], mask, u0, s.W, s.H,
-                               s.K, sc, acc_u0, acc_sL, acc_sR, acc_wh, acc_wv);
+                fws + LF.tape_mask + ((size_t)wp * p->n_iters + hi) * LF.mask_plane);
+            hipLaunchKernelGGL(pdhg_adjoint_fused_kernel, fgrid, dim3(256), 0, stream, A[cur], A[cur ^ 1], mask,
+                               LF.mask_plane / sizeof(uint16_t), nit, u0, s.W, s.H, s.K, sc, acc_u0, acc_sL, acc_sR,
+                               acc_wh, acc_wv);
             cur ^= 1;
         }
         DM_HIP_TRY(hipGetLastError(), "pdhg adjoint");
