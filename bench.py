@@ -326,6 +326,28 @@ def diff_extra(torch, ops, dev, n=8, W=960, H=320, K=96, n_iters=20, T=3, warps=
             "grad_finite": finite}
 
 
+def _note(msg):
+    """One progress line on stderr (the JSON result line stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _traffic(traffic_file):
+    """HBM bytes per launch from a stored rocprofv3 counter summary under profiles/, or None
+    when there is none or the kernel's sources have changed since it was taken."""
+    from paper_1601_06274_amd.traffic import source_hash
+    tpath = os.path.join(ROOT, "profiles", traffic_file)
+    if not os.path.exists(tpath):
+        return None
+    try:
+        with open(tpath) as f:
+            t = json.load(f)
+        if t.get("kernel_source_hash") == source_hash(t.get("sources", "sweep")):
+            return t.get("bytes_per_launch")
+    except (OSError, ValueError):
+        pass
+    return None
+
+
 def hierarchical_extra(torch, ops, cost, w_h, w_v, wl, tiles, reps=2):
     """The hierarchical minorant (Handshake) against the iterative one on the bench frame's
     FP16 cost volume: Dual_MM forward time, per half-step kernel time and algorithmic
@@ -347,7 +369,12 @@ def hierarchical_extra(torch, ops, cost, w_h, w_v, wl, tiles, reps=2):
             res[f"{mino}_{its}_its"] = {
                 "forward_ms": ms, "lower_bound": float(b[0]), "energy": float(b[1]),
                 "half_step_h_ms": msh / nh, "half_step_v_ms": msv / nv,
-                "half_step_h_GBps": bh / (msh * 1e-3) / 1e9, "half_step_v_GBps": bv / (msv * 1e-3) / 1e9}
+                "half_step_h_GBps": bh / (msh * 1e-3) / 1e9, "half_step_v_GBps": bv / (msv * 1e-3) / 1e9,
+                "half_step_h_alg_bytes": bh / nh, "half_step_v_alg_bytes": bv / nv}
+            if mino == "hierarchical":
+                # HBM bytes per launch from rocprofv3 counters (null once the kernel source changed)
+                res[f"{mino}_{its}_its"].update(half_step_h_traffic=_traffic("hier_h_traffic.json"),
+                                                half_step_v_traffic=_traffic("hier_v_traffic.json"))
     return {"workload": f"{wl['W']}x{wl['H']}, K={wl['K']}, FP16 SAD cost, T={wl['T']}: Dual_MM with the iterative "
                         f"and the hierarchical minorant (labels, bounds, no refinement)", **res}
 
@@ -434,7 +461,6 @@ def main():
         return 1
     import paper_1601_06274_amd as P
     from paper_1601_06274_amd import ops
-    from paper_1601_06274_amd.traffic import source_hash
     dev = torch.device("cuda:0")
     IL = torch.from_numpy(pair.left).to(dev)
     IR = torch.from_numpy(pair.right).to(dev)
@@ -490,6 +516,10 @@ def main():
                            keep_checkpoints=2, **k2)
         ops.solve_discrete_backward(cost, w_h, w_v, dual, ws_d2, grad_minmarg=G_m, grad_lb=g_lb, grad_cost=grad_cost,
                                     grad_w_h=grad_wh, grad_w_v=grad_wv, workspace=ws_db2, keep_checkpoints=2, **k2)
+        del ws_d2, ws_db2
+        # the hierarchical minorant's half-steps (2 dual iterations)
+        ops.solve_discrete(cost, w_h, w_v, T=wl["T"], n_iters=2, minorant="hierarchical", gammas=wl["gammas"],
+                           tile=tiles)
         torch.cuda.synchronize()
         print(json.dumps({"traffic_probe_bytes": 4 * n}), flush=True)
         return 0
@@ -540,6 +570,7 @@ def main():
     torch.cuda.synchronize()
     fwd_ms = (time.perf_counter() - t0) * 1e3 / args.steps
     ops.profiler_disable()
+    _note(f"forward-only frames: {fwd_ms:.2f} ms")
 
     prof = {k: ops.profiler_query(k) for k in ["sweep_h", "sweep_v", "sweep_final", "cost_volume"]}
 
@@ -555,6 +586,7 @@ def main():
     el = time.perf_counter() - t0
     ops.profiler_disable()
     ms_per_step = el * 1e3 / args.steps
+    _note(f"timed steps: {ms_per_step:.2f} ms per step")
     grad_finite = bool(torch.isfinite(grad_cost).all().item() and torch.isfinite(grad_wh).all().item())
     prof.update({k: ops.profiler_query(k) for k in bwd_kinds})
     record_gb = (ws_d2.numel() + ws_db2.numel()) / 1e9
@@ -563,16 +595,7 @@ def main():
         """Roofline object of one kernel kind: algorithmic bytes per launch / mean launch time."""
         n, ms, by = prof[kind]
         achieved = (by / n) / (ms / n * 1e-3) / 1e9 if n else 0.0
-        traffic = None  # HBM bytes per launch from rocprofv3 counters of the same kernel source
-        tpath = os.path.join(ROOT, "profiles", traffic_file)
-        if os.path.exists(tpath):
-            try:
-                with open(tpath) as f:
-                    t = json.load(f)
-                if t.get("kernel_source_hash") == source_hash(t.get("sources", "sweep")):
-                    traffic = t.get("bytes_per_launch")
-            except (OSError, ValueError):
-                traffic = None
+        traffic = _traffic(traffic_file)  # HBM bytes per launch from counters of the same kernel source
         return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "alg_bytes_per_launch": by / n if n else None,
                 "avg_launch_ms": ms / n if n else None, "launches": n}
@@ -663,12 +686,16 @@ def main():
     if not args.no_extras:
         del ws_r, ws_rb
         torch.cuda.empty_cache()
+        _note("extra: batched workload")
         out["batched"] = batched_extra(torch, ops, dev)
         torch.cuda.empty_cache()
+        _note("extra: differentiation workload")
         out["differentiation"] = diff_extra(torch, ops, dev)
         torch.cuda.empty_cache()
+        _note("extra: Census cost and left-right check")
         out["census_left_right"] = census_lr_extra(torch, ops, dev, pair, wl, tiles)
         torch.cuda.empty_cache()
+        _note("extra: hierarchical minorant")
         out["hierarchical_minorant"] = hierarchical_extra(torch, ops, cost, w_h, w_v, wl, tiles)
     if cpu is not None:
         out["cpu_baseline"] = cpu

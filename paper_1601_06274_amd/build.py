@@ -49,6 +49,9 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
     "-Wno-unused-result",
+    # device code objects stored compressed (zstd) in the library, unpacked by the HIP
+    # runtime at load: about a third of the size
+    "--offload-compress",
 ]
 
 

@@ -113,22 +113,32 @@ struct HierChain {
 #pragma unroll
         for (int i = 0; i < LPL; ++i) o[i] = lv[i] ? off + (unsigned)(i * E) : kOOB;
     }
-    // unaries of the family at a node: cost - dual (rows) or dual (columns); kBig for
-    // labels that do not exist
-    __device__ __forceinline__ void load_r(int node, float (&r)[LPL]) const {
+    // The raw words of a node's unaries (dual, and cost for rows), as loaded.
+    struct RawNode {
+        RawVec<float, LPL, FULL> l;
+        RawVec<TT, LPL, FULL> c;
+    };
+    __device__ __forceinline__ void load_raw(int node, RawNode& nd) const {
         unsigned o[LPL];
         const unsigned fo = f0 + (unsigned)node * f_step;
         offs<4>(fo, o);
-        RawVec<float, LPL, FULL> l;
-        l.load(r_lin, fo, o);
-        RawVec<TT, LPL, FULL> c;
+        nd.l.load(r_lin, fo, o);
         if constexpr (HAS_THETA) {
             const unsigned co = c0 + (unsigned)node * c_step;
             offs<ES>(co, o);
-            c.load(r_th, co, o);
+            nd.c.load(r_th, co, o);
         }
+    }
+    // unaries of the family at a node: cost - dual (rows) or dual (columns); kBig for
+    // labels that do not exist
+    __device__ __forceinline__ void unary_of(const RawNode& nd, float (&r)[LPL]) const {
 #pragma unroll
-        for (int i = 0; i < LPL; ++i) r[i] = lv[i] ? (HAS_THETA ? c.get(i) - l.get(i) : l.get(i)) : kBig;
+        for (int i = 0; i < LPL; ++i) r[i] = lv[i] ? (HAS_THETA ? nd.c.get(i) - nd.l.get(i) : nd.l.get(i)) : kBig;
+    }
+    __device__ __forceinline__ void load_r(int node, float (&r)[LPL]) const {
+        RawNode nd;
+        load_raw(node, nd);
+        unary_of(nd, r);
     }
     // the dual at a node (0 for labels that do not exist)
     __device__ __forceinline__ void load_lam(int node, float (&x)[LPL]) const {
@@ -235,6 +245,16 @@ struct HierChain {
     // index relative to the part's first node).
     struct Glob {
         const HierChain* h;
+        // a pass's prefetched node: raw unary words and the weight of its outgoing edge
+        struct Node {
+            RawNode u;
+            float w;
+        };
+        __device__ __forceinline__ void load_node(int k, int edge, Node& nd) const {
+            h->load_raw(k, nd.u);
+            nd.w = h->weight(edge);
+        }
+        __device__ __forceinline__ void unary(const Node& nd, float (&r)[LPL]) const { h->unary_of(nd.u, r); }
         __device__ __forceinline__ void load_r(int k, float (&r)[LPL]) const { h->load_r(k, r); }
         __device__ __forceinline__ void load_m(bool left, int k, float (&m)[LPL]) const { h->load_msg(left, k, m); }
         __device__ __forceinline__ void store_m(bool left, int k, const float (&m)[LPL]) const {
@@ -248,6 +268,18 @@ struct HierChain {
         int s;
         __device__ __forceinline__ lds_f32* at(int arr, int k) const {
             return base + ((size_t)arr * kHierChunk + (k - s)) * (64 * LPL) + h->lane * LPL;
+        }
+        struct Node {
+            float r[LPL];
+            float w;
+        };
+        __device__ __forceinline__ void load_node(int k, int edge, Node& nd) const {
+            load_r(k, nd.r);
+            nd.w = w(edge);
+        }
+        __device__ __forceinline__ void unary(const Node& nd, float (&r)[LPL]) const {
+#pragma unroll
+            for (int i = 0; i < LPL; ++i) r[i] = nd.r[i];
         }
         __device__ __forceinline__ void load_r(int k, float (&r)[LPL]) const {
             const lds_f32* p = at(0, k);
@@ -275,17 +307,21 @@ struct HierChain {
     template <class M>
     __device__ __forceinline__ void pass(const M& mem, int start, int count, int dir, float (&c)[LPL], double& opt) const {
         if (count <= 0) return;
-        // ring of the next nodes' unaries and the weights of their outgoing edges; the
-        // loads go unconditionally to a node of the pass (clamped to its last), so the
-        // full blocks have no branches and the waits stay exact
-        float ring[kHierPF][LPL], rw[kHierPF];
+        // ring of the next nodes' raw unary words and the weights of their outgoing edges,
+        // as loaded (the arithmetic at use); a slot is refilled only after its node's
+        // message, so no slot is live across its refill and the loop keeps each slot in
+        // the same registers (no copies, no drain of the loads in flight).  The loads go
+        // unconditionally to a node of the pass (clamped to its last), so the full blocks
+        // have no branches and the waits stay exact.
+        typename M::Node ring[kHierPF];
         const int eo = dir > 0 ? 0 : -1;  // edge of node k in the walking direction: k + eo
         auto node_of = [&](int t) { return start + dir * (t < count ? t : count - 1); };
+        // issued in slot order: the loop waits for slot q assuming later slots came after
 #pragma unroll
         for (int q = 0; q < kHierPF; ++q) {
             const int k = node_of(q);
-            mem.load_r(k, ring[q]);
-            rw[q] = mem.w(k + eo);
+            mem.load_node(k, k + eo, ring[q]);
+            __builtin_amdgcn_sched_barrier(0);
         }
         int t0 = 0;
         for (; t0 + kHierPF <= count; t0 += kHierPF) {
@@ -293,15 +329,17 @@ struct HierChain {
             for (int q = 0; q < kHierPF; ++q) {
                 const int t = t0 + q;
                 const int k = start + dir * t;
-                float v[LPL];
+                float r[LPL], v[LPL];
+                mem.unary(ring[q], r);
 #pragma unroll
-                for (int i = 0; i < LPL; ++i) v[i] = c[i] + ring[q][i];
-                const float wt = rw[q];
-                const int kn = node_of(t + kHierPF);
-                mem.load_r(kn, ring[q]);
-                rw[q] = mem.w(kn + eo);
-                opt += (double)message(v, wt, c);
+                for (int i = 0; i < LPL; ++i) v[i] = c[i] + r[i];
+                opt += (double)message(v, ring[q].w, c);
                 mem.store_m(dir > 0, k + dir, c);
+                const int kn = node_of(t + kHierPF);
+                mem.load_node(kn, kn + eo, ring[q]);
+                // one node per scheduling region: a later slot's conversions hoisted
+                // above this node would wait for its just-issued loads
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
 #pragma unroll
@@ -309,10 +347,11 @@ struct HierChain {
             const int t = t0 + q;
             if (t < count) {
                 const int k = start + dir * t;
-                float v[LPL];
+                float r[LPL], v[LPL];
+                mem.unary(ring[q], r);
 #pragma unroll
-                for (int i = 0; i < LPL; ++i) v[i] = c[i] + ring[q][i];
-                opt += (double)message(v, rw[q], c);
+                for (int i = 0; i < LPL; ++i) v[i] = c[i] + r[i];
+                opt += (double)message(v, ring[q].w, c);
                 mem.store_m(dir > 0, k + dir, c);
             }
         }
@@ -396,45 +435,63 @@ struct HierChain {
     }
 
     // A part of at most kHierChunk nodes (length >= 2): its unaries and valid messages
-    // are staged in LDS (all loads issued together), its parts are cut down to single
-    // nodes there, and the minorant of its nodes moves the dual.
-    __device__ __forceinline__ void solve_small(int s, int e, bool first, double& opt) const {
+    // are staged in LDS, its parts are cut down to single nodes there, and the minorant
+    // of its nodes moves the dual.  In three steps, so that the next part's loads are in
+    // flight while this part is computed: small_load issues every load of a part
+    // (nodes past its end read its last node again, edges past it its last edge: no
+    // branches, the waits stay exact); small_stage writes them to LDS and keeps the
+    // duals; small_finish cuts the part in LDS and moves the dual.
+    // The next part's loads in flight during the current part pay off with several waves
+    // per chain (the row family); with one wave per chain the extra registers and code
+    // cost more than the latency they hide (measured), so those load and compute in turn.
+    static constexpr bool kPrefetchSmall = NW > 1;
+    struct SmallIn {
+        RawNode u[kHierChunk];         // unaries as loaded (their dual words are the dual)
+        float mg[kHierChunk][LPL];     // the valid message of each node
+        float ew[kHierChunk - 1];      // edge weights
+    };
+    __device__ __forceinline__ void small_load(int s, int e, SmallIn& in) const {
+        const int m = e - s + 1;
+        const int cut = hsplit(s, e);
+#pragma unroll
+        for (int j = 0; j < kHierChunk; ++j) load_raw(s + (j < m ? j : m - 1), in.u[j]);
+#pragma unroll
+        for (int j = 0; j < kHierChunk - 1; ++j) in.ew[j] = weight(s + (j < m - 1 ? j : m - 2));
+#pragma unroll
+        for (int j = 0; j < kHierChunk; ++j) {
+            const int k = s + (j < m ? j : m - 1);
+            load_msg(k <= cut, k, in.mg[j]);
+        }
+    }
+    __device__ __forceinline__ void small_stage(int s, int e, const SmallIn& in, float (&lam)[kHierChunk][LPL]) const {
         const int m = e - s + 1;
         const int cut = hsplit(s, e);
         const Lds L{this, lds, s};
-        // every load of the part issued before the first LDS store: one memory latency
-        float rr[kHierChunk][LPL], mg[kHierChunk][LPL], ew[kHierChunk - 1];
-        float lam[kHierChunk][LPL];  // the dual, for the end (the columns' unaries are the dual)
-#pragma unroll
-        for (int j = 0; j < kHierChunk; ++j)
-            if (j < m) load_r(s + j, rr[j]);
-#pragma unroll
-        for (int j = 0; j < kHierChunk - 1; ++j)
-            if (j < m - 1) ew[j] = weight(s + j);
-#pragma unroll
-        for (int j = 0; j < kHierChunk; ++j)
-            if (j < m) load_msg(s + j <= cut, s + j, mg[j]);
-        if constexpr (HAS_THETA) {
-#pragma unroll
-            for (int j = 0; j < kHierChunk; ++j)
-                if (j < m) load_lam(s + j, lam[j]);
-        }
 #pragma unroll
         for (int j = 0; j < kHierChunk; ++j) {
+#pragma unroll
+            for (int i = 0; i < LPL; ++i) lam[j][i] = in.u[j].l.get(i);
             if (j < m) {
+                float r[LPL];
+                unary_of(in.u[j], r);
                 lds_f32* p = L.at(0, s + j);
 #pragma unroll
-                for (int i = 0; i < LPL; ++i) p[i] = rr[j][i];
-                L.store_m(s + j <= cut, s + j, mg[j]);
+                for (int i = 0; i < LPL; ++i) p[i] = r[i];
+                L.store_m(s + j <= cut, s + j, in.mg[j]);
             }
         }
         lds_f32* wl = lds + (size_t)3 * kHierChunk * (64 * LPL);
         if (lane == 0) {
 #pragma unroll
             for (int j = 0; j < kHierChunk - 1; ++j)
-                if (j < m - 1) wl[j] = ew[j];
+                if (j < m - 1) wl[j] = in.ew[j];
         }
         wave_lds_sync();
+    }
+    __device__ __forceinline__ void small_finish(int s, int e, const float (&lam)[kHierChunk][LPL], bool first,
+                                                 double& opt) const {
+        const int m = e - s + 1;
+        const Lds L{this, lds, s};
         bool f = first;
         split_parts(L, stk_small, s, e, f, opt);
         wave_lds_sync();
@@ -450,10 +507,7 @@ struct HierChain {
                 const float mn = wave_min(mm);
                 float out[LPL];
 #pragma unroll
-                for (int i = 0; i < LPL; ++i) {
-                    const float l0 = HAS_THETA ? lam[j][i] : r[i];
-                    out[i] = l0 + sign * (mm[i] - mn);
-                }
+                for (int i = 0; i < LPL; ++i) out[i] = lam[j][i] + sign * (mm[i] - mn);
                 store_lam(s + j, out);
             }
         }
@@ -519,11 +573,28 @@ struct HierChain {
                     nxt_i = next_big(wv);
                     if (nxt_i >= 0) hs_load(G, nxt_i, nxt);
                 }
+                // this wave's parts of at most the chunk, the next one's loads issued
+                // while the current one is computed
+                auto next_small = [&](int from, int& s1, int& e1) -> bool {
+                    for (int p = from; p < np; p += NW)
+                        if (part_at(depth, p, s1, e1) && e1 - s1 + 1 <= kHierChunk) return true;
+                    return false;
+                };
+                SmallIn sm;
+                int sm_s, sm_e;
+                if constexpr (kPrefetchSmall)
+                    if (next_small(wv, sm_s, sm_e)) small_load(sm_s, sm_e, sm);
                 for (int p = wv; p < np; p += NW) {
                     int s0, e0;
                     if (!part_at(depth, p, s0, e0)) continue;
                     if (e0 - s0 + 1 <= kHierChunk) {
-                        solve_small(s0, e0, depth == 0, opt);
+                        // with the prefetch, sm holds this part's loads (parts are visited in order)
+                        if constexpr (!kPrefetchSmall) small_load(s0, e0, sm);
+                        float lam[kHierChunk][LPL];
+                        small_stage(s0, e0, sm, lam);
+                        if constexpr (kPrefetchSmall)
+                            if (next_small(p + NW, sm_s, sm_e)) small_load(sm_s, sm_e, sm);
+                        small_finish(s0, e0, lam, depth == 0, opt);
                     } else {
                         const int i = nxt_i;  // == hsplit(s0, e0): parts are visited in order
                         const HsIn cur = nxt;

@@ -26,12 +26,14 @@ PROBE_KERNEL = "MulFunctor"
 
 
 SOURCES = {"sweep": ["dmm_kernels.h", "wave.h", "tiles.h"],
-           "adjoint": ["dmm_kernels.h", "wave.h", "tiles.h", "dmm_adjoint.h"]}
+           "adjoint": ["dmm_kernels.h", "wave.h", "tiles.h", "dmm_adjoint.h"],
+           "hier": ["dmm_hier.hip", "dmm_hier.h"]}
 
 
 def source_hash(which: str = "sweep") -> str:
-    """Hash of the sources of the chain sweep ("sweep") or adjoint ("adjoint") kernels (a
-    stored traffic figure is valid only for the kernel it was measured on)."""
+    """Hash of the sources of the chain sweep ("sweep"), adjoint ("adjoint") or
+    hierarchical-minorant ("hier") kernels (a stored traffic figure is valid only for the
+    kernel it was measured on)."""
     h = hashlib.sha256()
     for fn in SOURCES[which]:
         with open(os.path.join(HERE, "csrc", fn), "rb") as f:
