@@ -37,9 +37,13 @@
 namespace dm {
 
 // Parts of at most this many nodes are finished in LDS by one wave (App. A.3.3's
-// iteration count assumes that short parts sit in fast memory); 8 keeps a wave's
-// staging at 18.4 KB for K = 192, so every column chain of a frame stays resident.
-constexpr int hier_chunk(int) { return 8; }
+// iteration count assumes that short parts sit in fast memory).  A wave stages
+// 3 x chunk x 64 x LPL floats: 8 nodes keep it at 18.4 KB for K = 192, so two blocks of
+// four waves share a CU; with one wave per chain and at most 3 labels per lane, 12 nodes
+// (27.6 KB, five waves per CU) take one more level off the HBM passes.
+constexpr int hier_chunk(int nw, int lpl) { return nw == 1 && lpl <= 3 ? 12 : 8; }
+// Waves per chain: several when the chains alone leave most of the 1024 SIMDs idle.
+inline int hier_waves(int n_chains, int n) { return n_chains <= 512 && n >= 64 ? 4 : 1; }
 
 hipError_t launch_hier_lpl1(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st);
 hipError_t launch_hier_lpl2(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st);
@@ -64,7 +68,7 @@ __device__ __forceinline__ int hsplit(int s, int e) { return s + (e - s + 1) / 2
 // NW: waves per chain (a workgroup of NW waves).
 template <int LPL, typename TT, bool HAS_THETA, int TW, int NW, bool FULL>
 struct HierChain {
-    static constexpr int kHierChunk = hier_chunk(NW);
+    static constexpr int kHierChunk = hier_chunk(NW, LPL);
     static constexpr int kLdsFloats = 3 * kHierChunk * 64 * LPL + kHierChunk;  // per wave
     static constexpr int ES = (int)sizeof(TT);
     // buffers: cost, dual read, dual written, messages from the left / right, weights
@@ -678,10 +682,9 @@ hipError_t launch_nw(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStrea
     return launch_full<LPL, TW, NW, false>(a, msg_right, dt, st);
 }
 
-// Several waves per chain when the chains alone leave most SIMDs idle (1024 SIMDs).
 template <int LPL, int TW>
 hipError_t launch_tw(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st) {
-    if (a.n_chains <= 512 && a.n >= 64) return launch_nw<LPL, TW, 4>(a, msg_right, dt, st);
+    if (hier_waves(a.n_chains, a.n) == 4) return launch_nw<LPL, TW, 4>(a, msg_right, dt, st);
     return launch_nw<LPL, TW, 1>(a, msg_right, dt, st);
 }
 
@@ -723,7 +726,8 @@ double hier_half_step_bytes(const SweepArgs& a, dm_dtype dt) {
     // and its nodes' duals written.  The Handshakes' own loads and stores (two nodes per
     // cut, about one cut per LDS part) are left out.
     const double b = a.theta != nullptr ? (dt == DM_F16 ? 2.0 : 4.0) : 0.0;
-    const int chunk = hier_chunk(1);
+    const int lpl = a.K <= 64 ? 1 : a.K <= 128 ? 2 : a.K <= 192 ? 3 : 4;
+    const int chunk = hier_chunk(hier_waves(a.n_chains, a.n), lpl);
     int deep = 0;  // depths whose parts are longer than the LDS part
     for (int m = a.n; m > chunk; m = (m + 1) / 2) ++deep;
     const double step = b + 4.0 + 4.0;                 // unaries read, message written
