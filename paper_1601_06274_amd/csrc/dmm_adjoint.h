@@ -601,6 +601,7 @@ struct AdjWalker {
 #pragma unroll
         for (int i = 0; i < LPL; ++i) cbar[i] = 0.0f;
         int next_label = 0;
+        float unused_w = 0.0f;  // nodes outside the steady blocks add their edge sums one by one
         Cursor lc = cursor_start(FWD);
         Cursor sc = lc;
         Node ring[PF];
@@ -616,23 +617,33 @@ struct AdjWalker {
 #pragma unroll
             for (int q = 0; q < PF; ++q) {
                 if (q == 0)
-                    step_tape<FWD, KIND, IS_FIRST, MF, kOutNo>(ring[q], q, cbar, gamma, next_label, sc);
+                    step_tape<FWD, KIND, IS_FIRST, MF, kOutNo>(ring[q], q, cbar, gamma, next_label, sc, unused_w);
                 else
-                    step_tape<FWD, KIND, IS_FIRST, MF, kOutYes>(ring[q], q, cbar, gamma, next_label, sc);
+                    step_tape<FWD, KIND, IS_FIRST, MF, kOutYes>(ring[q], q, cbar, gamma, next_label, sc, unused_w);
                 load_tape<FWD, KIND, IS_FIRST>(ring[q], lc);
             }
+            // steady blocks: node q's edge sum goes to lane q, and the block's PF edges get
+            // one atomic (lanes 0..PF-1) instead of one lane-0 atomic per node
+            constexpr bool kBatchW = G >= PF;
             for (t0 = PF; t0 + PF <= n; t0 += PF) {
+                float wacc = 0.0f;
+                const unsigned w_blk = sc.w;
 #pragma unroll
                 for (int q = 0; q < PF; ++q) {
-                    step_tape<FWD, KIND, IS_FIRST, MF, kOutYes>(ring[q], t0 + q, cbar, gamma, next_label, sc);
+                    step_tape<FWD, KIND, IS_FIRST, MF, kOutYes, kBatchW>(ring[q], t0 + q, cbar, gamma, next_label, sc,
+                                                                         wacc, q);
                     load_tape<FWD, KIND, IS_FIRST>(ring[q], lc);
                 }
+                if constexpr (kBatchW)
+                    if (ok && sub < PF)
+                        add_edge_grad(FWD ? w_blk - (unsigned)sub * w_step : w_blk + (unsigned)sub * w_step, wacc);
             }
         }
 #pragma unroll
         for (int q = 0; q < PF; ++q)
             if (t0 + q < n)
-                step_tape<FWD, KIND, IS_FIRST, MF, kOutRuntime>(ring[q], t0 + q, cbar, gamma, next_label, sc);
+                step_tape<FWD, KIND, IS_FIRST, MF, kOutRuntime>(ring[q], t0 + q, cbar, gamma, next_label, sc,
+                                                                unused_w);
     }
 
     template <bool FWD, int KIND, bool IS_FIRST>
@@ -646,10 +657,11 @@ struct AdjWalker {
     // Adjoint of the forward step at the node visited t-th, from the tape (the same
     // formulas as step()).
     // OUTM: whether the node sends a message in the forward pass (kOutYes / kOutNo), or
-    // decided at run time (t != 0).
-    template <bool FWD, int KIND, bool IS_FIRST, int MF, int OUTM>
+    // decided at run time (t != 0).  BATCH: the node's edge sum goes to lane wb of wacc
+    // (the caller adds a block of edges at once); else lane 0 adds it now.
+    template <bool FWD, int KIND, bool IS_FIRST, int MF, int OUTM, bool BATCH = false>
     __device__ __forceinline__ void step_tape(const Node& nd, int t, float (&cbar)[LPL], float gamma, int& next_label,
-                                              Cursor& sc) {
+                                              Cursor& sc, float& wacc, int wb = 0) {
         const bool out = OUTM == kOutYes ? true : (OUTM == kOutNo ? false : t != 0);
         const unsigned rs = FWD ? sc.f : sc.f - f_step;
         unsigned os[LPL];
@@ -758,7 +770,10 @@ struct AdjWalker {
             label_offsets<4>(sc.f, os);
             store_f32<LPL, FULL>(r_abar, sc.f, os, rbar);
         }
-        if (ok && sub == 0 && out) add_edge_grad(sc.w, wl);
+        if constexpr (BATCH)
+            wacc = sub == wb ? wl : wacc;
+        else if (ok && sub == 0 && out)
+            add_edge_grad(sc.w, wl);
         advance<FWD>(sc);
     }
 
