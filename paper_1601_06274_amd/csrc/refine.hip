@@ -32,7 +32,7 @@
 //
 // Adjoint (reverse mode).  Every map of the iteration is piecewise linear; given the
 // recorded branches, the adjoint of one iteration is a linear stencil reaching one pixel,
-// run kFS reverse iterations per launch by temporal tiling (pdhg_adjoint_fused_kernel).
+// run kAS reverse iterations per launch by temporal tiling (pdhg_adjoint_fused_kernel).
 // At the start of each warp (processed in reverse) the accumulated adjoints of the
 // slopes and of u0 are pushed through the linearisation into the cost volume and into u
 // (linearize_adjoint_kernel).  At kinks
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void pdhg_kernel(const RefineState in, RefineS
               blockIdx.y * kTY);
 }
 
-__global__ __launch_bounds__(256, 3) void pdhg_fused_kernel(const RefineState in, RefineState out,
+__global__ __launch_bounds__(256, 2) void pdhg_fused_kernel(const RefineState in, RefineState out,
                                                          const rfloat* __restrict__ u0, const rfloat* __restrict__ sL,
                                                          const rfloat* __restrict__ sR, const float* __restrict__ w_h,
                                                          const float* __restrict__ w_v, int W, int H, int K,
@@ -231,9 +231,9 @@ __device__ __forceinline__ rfloat conj_dw(int code, rfloat alpha) {
     return code >= 3 ? s : s * alpha;
 }
 
-// n_iter <= kFS reverse iterations per launch (temporal tiling, as pdhg_fused_tile): the
-// adjoint of iteration it reaches one pixel (diagonals included), so a TX x TY output
-// tile is exact after n_iter iterations on the tile extended by kFS pixels on every side.
+// n_iter <= kAS reverse iterations per launch (temporal tiling, as pdhg_fused_tile): the
+// adjoint of iteration it reaches one pixel (diagonals included), so a kATX x kATY output
+// tile is exact after n_iter iterations on the tile extended by kAS pixels on every side.
 // The adjoint state sits in LDS between iterations; the accumulators of the tile's pixels
 // (u0, slopes, edge weights) are loaded once, carried in registers in the order of the
 // single-iteration kernel's additions and stored once, so the results equal that
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void pdhg_adjoint_fused_kernel(const RefineSta
                                                                  rfloat* __restrict__ acc_sL, rfloat* __restrict__ acc_sR,
                                                                  rfloat* __restrict__ acc_wh,
                                                                  rfloat* __restrict__ acc_wv) {
-    constexpr int TX = kFTX, TY = kFTY, S = kFS;
+    constexpr int TX = kATX, TY = kATY, S = kAS;
     constexpr int RX = TX + 2 * S, RY = TY + 2 * S, NP = RX * RY;
     constexpr int NT = 256, PPT = (NP + NT - 1) / NT;
     // the u adjoint of a pixel is read and written by that pixel only: in registers
@@ -709,13 +709,13 @@ extern "C" int dm_refine_continuous_backward(const float* grad_u, const void* co
                        acc_wh, acc_wv);
     DM_HIP_TRY(hipGetLastError(), "adjoint init");
     const RefineScalars sc = refine_scalars(*p);
-    const dim3 fgrid((s.W + kFTX - 1) / kFTX, (s.H + kFTY - 1) / kFTY);
+    const dim3 fgrid((s.W + kATX - 1) / kATX, (s.H + kATY - 1) / kATY);
     int cur = 0;
     for (int wp = p->n_warps - 1; wp >= 0; --wp) {
         const rfloat* u0 = reinterpret_cast<const rfloat*>(fws + LF.tape_u0 + (size_t)wp * LF.plane);
-        // kFS reverse iterations per launch, the adjoint state on chip in between
-        for (int hi = p->n_iters - 1; hi >= 0; hi -= kFS) {
-            const int nit = std::min(kFS, hi + 1);
+        // kAS reverse iterations per launch, the adjoint state on chip in between
+        for (int hi = p->n_iters - 1; hi >= 0; hi -= kAS) {
+            const int nit = std::min(kAS, hi + 1);
             const uint16_t* mask = reinterpret_cast<const uint16_t*>(
                 fws + LF.tape_mask + ((size_t)wp * p->n_iters + hi) * LF.mask_plane);
             hipLaunchKernelGGL(pdhg_adjoint_fused_kernel, fgrid, dim3(256), 0, stream, A[cur], A[cur ^ 1], mask,
