@@ -376,7 +376,9 @@ int dm_refine_flow(const void* cost, dm_dtype cost_dtype, const int32_t* labels1
  * parameters.  An instance with a bounds buffer gets, per run, its lower bound (the
  * row optima of the final pass plus the column optima at the final dual, eq. DD-dual)
  * and the energy of its labels, FP64, the same quantities as dm_solve_discrete's
- * bounds_out (sums in another fixed order).  No min-marginals in this form.
+ * bounds_out (sums in another fixed order).  An instance with a minmarg buffer gets the
+ * final row pass's normalized min-marginals (Sec. 2.3, the min-marginals of the
+ * horizontal family at the final dual), bit for bit dm_solve_discrete's minmarg_out.
  * ------------------------------------------------------------------------------- */
 typedef struct {
     dm_shape s;
@@ -387,6 +389,7 @@ typedef struct {
     float* dual;           /* [H][W][K] dual state                                  */
     float* u;              /* [H][W] refined disparities (required with refinement) */
     double* bounds;        /* device [2] = {LB, E(labels)} per run, or NULL          */
+    float* minmarg;        /* [H][W][K] output, 16-byte aligned, or NULL             */
 } dm_instance;
 
 int dm_plan_batched(const dm_instance* inst, int n, dm_dtype cost_dtype, const dm_discrete_params* p,

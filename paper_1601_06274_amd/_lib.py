@@ -60,7 +60,7 @@ class DmFlowShape(ctypes.Structure):
 class DmInstance(ctypes.Structure):
     _fields_ = [("s", DmShape), ("cost", ctypes.c_void_p), ("w_h", ctypes.c_void_p), ("w_v", ctypes.c_void_p),
                 ("labels", ctypes.c_void_p), ("dual", ctypes.c_void_p), ("u", ctypes.c_void_p),
-                ("bounds", ctypes.c_void_p)]
+                ("bounds", ctypes.c_void_p), ("minmarg", ctypes.c_void_p)]
 
 
 class DmGradInstance(ctypes.Structure):

@@ -159,8 +159,9 @@ extern "C" int dm_plan_batched(const dm_instance* inst, int n, dm_dtype cost_dty
         DM_REQUIRE(rp == nullptr || I.u != nullptr, DM_ERR_NULL, "instance %d: u required with refinement", i);
         DM_REQUIRE((long long)I.s.W * I.s.H * I.s.K * 4 < (long long)kOOB, DM_ERR_UNSUPPORTED,
                    "instance %d exceeds the 4 GiB buffer range", i);
-        DM_REQUIRE(((uintptr_t)I.cost % 16) == 0 && ((uintptr_t)I.dual % 16) == 0, DM_ERR_PARAM,
-                   "instance %d: volumes need 16-byte alignment", i);
+        DM_REQUIRE(((uintptr_t)I.cost % 16) == 0 && ((uintptr_t)I.dual % 16) == 0 &&
+                       ((uintptr_t)I.minmarg % 16) == 0,
+                   DM_ERR_PARAM, "instance %d: volumes need 16-byte alignment", i);
         dm_discrete_params q = *p;
         q.tile_lanes = q.labels_per_lane = q.tile_lanes_v = q.labels_per_lane_v = 0;
         q.keep_checkpoints = 0;
@@ -247,6 +248,7 @@ extern "C" int dm_plan_batched(const dm_instance* inst, int n, dm_dtype cost_dty
         d.w_v = I.w_v;
         d.labels = I.labels;
         d.bounds = I.bounds;
+        d.minmarg = I.minmarg;
         d.opt_rows = d.opt_cols = nullptr;
         if (I.bounds != nullptr) {
             d.opt_rows = opt_pool + opt_off;

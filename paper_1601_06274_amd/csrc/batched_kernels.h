@@ -23,6 +23,7 @@ struct InstDesc {
     double* opt_rows;       // [H] row chain optima (plan scratch; null without bounds)
     double* opt_cols;       // [W] column chain optima
     double* bounds;         // [2] = {LB, E(labels)} or null
+    float* minmarg;         // [H][W][K] final-pass min-marginals or null
     int W, H, K;
     unsigned vol_bytes_f32, vol_bytes_theta, wh_bytes, wv_bytes;
 };
@@ -51,7 +52,7 @@ __device__ __forceinline__ SweepArgs batch_args(const InstDesc& in, const BatchL
     a.lam_in = in.lam;
     a.msg = in.msg;
     a.w = rows ? in.w_h : in.w_v;
-    a.minmarg = nullptr;
+    a.minmarg = bl.mode == kModeFinal ? in.minmarg : nullptr;
     a.labels = in.labels;
     a.opt = bl.want_opt ? (rows ? in.opt_rows : in.opt_cols) : nullptr;
     a.chain_px = rows ? in.W : 1;

@@ -434,13 +434,14 @@ class BatchedPlan:
 
     ``instances``: list of dicts with GPU tensors ``cost`` [H][W][K] (all float32 or all
     float16), ``w_h``, ``w_v``; the plan allocates ``labels``, ``dual``, ``bounds``
-    (float64 [LB, E(labels)], with want_bounds) and (with refinement) ``u`` for each
+    (float64 [LB, E(labels)], with want_bounds), ``minmarg`` (the final row pass's
+    normalized min-marginals, with want_minmarg) and (with refinement) ``u`` for each
     instance unless given.  Keep the object alive while
     running; call ``close()`` (or drop it) to free the plan's device memory.
     """
 
     def __init__(self, instances, *, T=3, n_iters=20, n_half_steps=0, minorant="iterative",
-                 gammas=(0.25, 0.25, 1.0), tile=None, refine=None, want_bounds=True):
+                 gammas=(0.25, 0.25, 1.0), tile=None, refine=None, want_bounds=True, want_minmarg=False):
         self.instances = []
         arr = (L.DmInstance * len(instances))()
         dtype = instances[0]["cost"].dtype
@@ -457,11 +458,14 @@ class BatchedPlan:
                 d.setdefault("u", torch.empty((H, W), dtype=torch.float32, device=dev))
             if want_bounds:
                 d.setdefault("bounds", torch.empty(2, dtype=torch.float64, device=dev))
+            if want_minmarg:
+                d.setdefault("minmarg", torch.empty((H, W, K), dtype=torch.float32, device=dev))
             for k in ("cost", "w_h", "w_v", "labels", "dual"):
                 _check_dev(k, d[k])
             _check_dev("bounds", d.get("bounds"), torch.float64, (2,))
+            _check_dev("minmarg", d.get("minmarg"), torch.float32, (H, W, K))
             arr[i] = L.DmInstance(L.DmShape(W, H, K), _ptr(cost), _ptr(d["w_h"]), _ptr(d["w_v"]), _ptr(d["labels"]),
-                                  _ptr(d["dual"]), _ptr(d.get("u")), _ptr(d.get("bounds")))
+                                  _ptr(d["dual"]), _ptr(d.get("u")), _ptr(d.get("bounds")), _ptr(d.get("minmarg")))
             self.instances.append(d)
         p = discrete_params(T, n_iters, n_half_steps, minorant, gammas, False, tile, False)
         rp = None if refine is None else refine_params(**refine)

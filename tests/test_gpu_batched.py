@@ -40,9 +40,9 @@ SPECS = [(7, 11, 8, 1), (12, 5, 32, 2), (3, 30, 20, 3), (16, 16, 64, 4), (9, 23,
 
 @pytest.mark.parametrize("dtype,half", [(torch.float32, 0), (torch.float16, 0), (torch.float16, 5)])
 def test_batched_equals_single_instance_bitwise(dtype, half):
-    """Labels, duals and the lower bound bit for bit (the same chain optima summed in the
-    same order); the energy of the labels to FP64 rounding (partial sums in another
-    order).  half = 5: the last half-step is a row one, so the column optima come from
+    """Labels, duals, min-marginals and the lower bound bit for bit (the same chain optima
+    summed in the same order); the energy of the labels to FP64 rounding (partial sums in
+    another order).  half = 5: the last half-step is a row one, so the column optima come from
     the plan's column optimum pass."""
     ops = _need()
     insts = _instances(SPECS, dtype)
@@ -53,7 +53,7 @@ def test_batched_equals_single_instance_bitwise(dtype, half):
         tiles[K] = ops.tile_for(K)
     # one fixed tile per K: give the plan the per-K default through single-K batches
     plan = ops.BatchedPlan([{k: d[k] for k in ("cost", "w_h", "w_v")} for d in insts], T=3, n_iters=3,
-                           n_half_steps=half, tile=None)
+                           n_half_steps=half, tile=None, want_minmarg=True)
     try:
         singles = []
         for d in insts:
@@ -69,6 +69,7 @@ def test_batched_equals_single_instance_bitwise(dtype, half):
             for i, (pi, s) in enumerate(zip(plan.instances, singles)):
                 assert torch.equal(pi["labels"], s.labels), f"replay {rep} instance {i} labels"
                 assert torch.equal(pi["dual"], s.dual), f"replay {rep} instance {i} dual"
+                assert torch.equal(pi["minmarg"], s.minmarg), f"replay {rep} instance {i} min-marginals"
                 b, bs = pi["bounds"].cpu().numpy(), s.bounds.cpu().numpy()
                 assert b[0] == bs[0], f"replay {rep} instance {i} lower bound {b[0]} vs {bs[0]}"
                 assert b[1] == pytest.approx(bs[1], rel=1e-12, abs=1e-12), f"replay {rep} instance {i} energy"
