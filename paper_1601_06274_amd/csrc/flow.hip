@@ -205,8 +205,8 @@ __global__ __launch_bounds__(256) void flow_pdhg_kernel(FlowComps fc, int cur, c
                                                         const float* __restrict__ w_v, int W, int H, RefineScalars sc,
                                                         int n_iter) {
     const FlowComp& c = fc.c[blockIdx.z];
-    pdhg_fused_tile<kATX, kATY, kAS>(c.S[cur], c.S[cur ^ 1], QuadProx{c.u0, c.L, c.Q, sc.tau, sc.h}, w_h, w_v, W, H,
-                                     c.K, sc, nullptr, 0, n_iter, blockIdx.x * kATX, blockIdx.y * kATY);
+    pdhg_fused_tile<kQTX, kQTY, kQS>(c.S[cur], c.S[cur ^ 1], QuadProx{c.u0, c.L, c.Q, sc.tau, sc.h}, w_h, w_v, W, H,
+                                     c.K, sc, nullptr, 0, n_iter, blockIdx.x * kQTX, blockIdx.y * kQTY);
 }
 
 __global__ __launch_bounds__(256) void flow_init_kernel(const int* __restrict__ l1, const int* __restrict__ l2,
@@ -385,7 +385,7 @@ extern "C" int dm_refine_flow(const void* cost, dm_dtype cost_dtype, const int32
     hipLaunchKernelGGL(flow_init_kernel, dim3(eb), dim3(256), 0, stream, labels1, labels2, npx, fc);
     DM_HIP_TRY(hipGetLastError(), "flow refine init");
     const RefineScalars sc = refine_scalars(*p);
-    const dim3 grid((s.W + kATX - 1) / kATX, (s.H + kATY - 1) / kATY, 2);
+    const dim3 grid((s.W + kQTX - 1) / kQTX, (s.H + kQTY - 1) / kQTY, 2);
     int cur = 0;
     for (int wp = 0; wp < p->n_warps; ++wp) {
         ProfScope ps1(DM_PROF_REFINE_LINEARIZE, (double)npx * (16.0 + 20.0 * (cost_dtype == DM_F16 ? 2 : 4) + 48.0),
@@ -398,8 +398,8 @@ extern "C" int dm_refine_flow(const void* cost, dm_dtype cost_dtype, const int32
                                static_cast<const float*>(cost), npx, s.K1, s.K2, (rfloat)p->h, fc, cur);
         ps1.stop();
         DM_HIP_TRY(hipGetLastError(), "flow linearize");
-        for (int it0 = 0; it0 < p->n_iters; it0 += kAS) {
-            const int nit = std::min(kAS, p->n_iters - it0);
+        for (int it0 = 0; it0 < p->n_iters; it0 += kQS) {
+            const int nit = std::min(kQS, p->n_iters - it0);
             ProfScope ps2(DM_PROF_REFINE_ITER, 2.0 * nit * npx * (8.0 * 13.0 + 8.0), stream);
             hipLaunchKernelGGL(flow_pdhg_kernel, grid, dim3(256), 0, stream, fc, cur, w_h, w_v, s.W, s.H, sc, nit);
             cur ^= 1;

@@ -238,11 +238,14 @@ __device__ __forceinline__ void pdhg_fused_tile(const RefineState& in, const Ref
 // Fused tile shapes.  The stereo forward: 40 x 24 outputs, 4 iterations per launch, a
 // 48 x 32 region (73.7 KB of LDS, 6 pixels per thread), so two blocks share a CU and the
 // 512 blocks of a 1242 x 375 frame are all resident at once; 40 iterations per warp take
-// 10 launches.  Its adjoint and the flow refinement: 32 x 20 outputs, 3 iterations per
-// launch, a 38 x 26 region (47.4 KB in the forward form, 4 pixels per thread), three blocks
-// per CU, 741 blocks per frame.  (The adjoint on the forward's shape was measured slower.)
+// 10 launches.  Its adjoint: 32 x 16 outputs, 4 reverse iterations per launch, a 40 x 24
+// region (40.3 KB of LDS, 4 pixels per thread, 113 VGPRs), four blocks per CU and the 936
+// blocks of a frame resident (with 6 pixels per thread the adjoint's accumulators exceed
+// the register file).  The flow refinement (quadratic-fit model): 32 x 20 outputs, 3
+// iterations per launch, a 38 x 26 region, three blocks per CU.
 constexpr int kFTX = 40, kFTY = 24, kFS = 4;
-constexpr int kATX = 32, kATY = 20, kAS = 3;
+constexpr int kATX = 32, kATY = 16, kAS = 4;
+constexpr int kQTX = 32, kQTY = 20, kQS = 3;
 
 
 }  // namespace dm
