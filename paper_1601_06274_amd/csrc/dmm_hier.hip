@@ -520,19 +520,21 @@ struct HierChain {
 
     // The part at `depth` with index p (its path from the whole chain: bit depth-1-d of
     // p chooses the right part at depth d); false if an ancestor was at most
-    // kHierChunk long (finished in LDS, not cut further).
+    // kHierChunk long (finished in LDS, not cut further).  A cut leaves parts of at most
+    // the parent's length, so the parent is the shortest ancestor and the only one to
+    // test; the walk itself has no branches (scalar selects).
     __device__ __forceinline__ bool part_at(int depth, int p, int& s, int& e) const {
         s = 0;
         e = n - 1;
+        int plen = 0x7fffffff;  // the parent's length (depth 0: no parent, the whole chain exists)
         for (int d = depth - 1; d >= 0; --d) {
-            if (e - s + 1 <= kHierChunk) return false;
+            plen = e - s + 1;
             const int i = hsplit(s, e);
-            if ((p >> d) & 1)
-                s = i + 1;
-            else
-                e = i;
+            const bool right = (p >> d) & 1;
+            s = right ? i + 1 : s;
+            e = right ? e : i;
         }
-        return true;
+        return plen > kHierChunk;
     }
 
     // Level order: at each depth, first the cuts of the parts (Handshakes; parts of at
