@@ -15,7 +15,8 @@
 //                         I2 (66 + K1 - 1 columns) are staged in LDS; each thread sums the
 //                         3x3 window of |I1 - I2(displaced)| for its (pixel, i) pairs.
 //   flow_project_kernel : each wave owns one pixel at a time (1 to 4 waves per block, as LDS
-//                         allows); its K2 x K1 table goes into LDS
+//                         allows); its K2 x K1 table goes into LDS (16-byte loads when a row
+//                         holds whole vectors)
 //                         (row stride K1 + 1, so row and column reads are conflict-free), then
 //                         lane i takes the minimum down column i (f1) and lane j along row j
 //                         (f2).  The minima are exact, so the unaries keep the cost dtype.
@@ -103,7 +104,25 @@ __global__ __launch_bounds__(256) void flow_project_kernel(const TT* __restrict_
         const bool live = p < npx;
         if (live) {
             const TT* src = cost + p * (long long)n;
-            for (int e = lane; e < n; e += 64) tile[(e / K1) * ld + (e % K1)] = (float)src[e];
+            // 16-byte loads when a row holds whole vectors and the volume is 16-byte
+            // aligned (every pixel's table then is too): the wave's loads are issued
+            // together and a vector's elements share one row
+            constexpr int EPV = 16 / (int)sizeof(TT);
+            if (K1 % EPV == 0 && ((uintptr_t)cost & 15u) == 0) {
+                const uint4* s4 = reinterpret_cast<const uint4*>(src);
+                const int nv = n / EPV, vpr = K1 / EPV;
+#pragma unroll 8
+                for (int v = lane; v < nv; v += 64) {
+                    const uint4 w = s4[v];
+                    const TT* el = reinterpret_cast<const TT*>(&w);
+                    const int r = v / vpr, c = (v - r * vpr) * EPV;
+                    float* dst = tile + r * ld + c;
+#pragma unroll
+                    for (int k = 0; k < EPV; ++k) dst[k] = (float)el[k];
+                }
+            } else {
+                for (int e = lane; e < n; e += 64) tile[(e / K1) * ld + (e % K1)] = (float)src[e];
+            }
         }
         __syncthreads();
         if (live) {
