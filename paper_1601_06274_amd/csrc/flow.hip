@@ -14,6 +14,9 @@
 //                         three window rows of I1 (66 columns) and the three displaced rows of
 //                         I2 (66 + K1 - 1 columns) are staged in LDS; each thread sums the
 //                         3x3 window of |I1 - I2(displaced)| for its (pixel, i) pairs.
+//                         flow_sad_cols_kernel (windows of 1, 3 or 5): the same staging,
+//                         each lane one label i over 16 consecutive pixels, every window
+//                         column's sum formed once and shared by the outputs that use it.
 //   flow_project_kernel : each wave owns one pixel at a time (1 to 4 waves per block, as LDS
 //                         allows); its K2 x K1 table goes into LDS (16-byte loads when a row
 //                         holds whole vectors)
@@ -86,6 +89,78 @@ __global__ __launch_bounds__(256) void flow_sad_kernel(const float* __restrict__
             }
         }
         out[(((long long)y * W + x) * K2 + j) * K1 + i] = (OT)fminf(trunc, acc * inv_area);
+    }
+}
+
+// The same cost for windows of width 2R + 1 <= 5: each wave takes 16 consecutive pixels of
+// the block's 64 and each lane one horizontal label at a time, so a window column's sum
+// over the 2R + 1 rows is formed once and shared by the 2R + 1 outputs that use it (the
+// window summed column by column: the same terms as the general kernel, another order of
+// additions).  No divisions; the row validity is uniform and the column validity one
+// compare per lane.
+template <typename OT, int R>
+__global__ __launch_bounds__(256) void flow_sad_cols_kernel(const float* __restrict__ I1, const float* __restrict__ I2,
+                                                            int W, int H, int K1, int K2, int off1, int off2,
+                                                            float trunc, float inv_area, OT* __restrict__ out) {
+    constexpr int NW = 2 * R + 1, GX = 16, NC = GX + 2 * R;
+    extern __shared__ float lds[];
+    const int x0 = blockIdx.x * kFlowTX;
+    const int y = blockIdx.y;
+    const int j = blockIdx.z;
+    const int d2 = j - off2;
+    const int nc1 = kFlowTX + 2 * R;
+    const int nc2 = nc1 + K1 - 1;
+    float* a1 = lds;
+    float* a2 = lds + NW * nc1;
+    const int cx_first = min(max(x0 - R, 0), W - 1);
+    const int base2 = cx_first - off1;
+    for (int idx = threadIdx.x; idx < NW * nc1; idx += blockDim.x) {
+        const int dy = idx / nc1, t = idx % nc1;
+        const int cy = min(max(y + dy - R, 0), H - 1);
+        const int cx = min(max(x0 - R + t, 0), W - 1);
+        a1[idx] = I1[(long long)cy * W + cx];
+    }
+    for (int idx = threadIdx.x; idx < NW * nc2; idx += blockDim.x) {
+        const int dy = idx / nc2, t = idx % nc2;
+        const int my = min(max(min(max(y + dy - R, 0), H - 1) + d2, 0), H - 1);  // clamped: validity checked below
+        const int mx = min(max(base2 + t, 0), W - 1);
+        a2[idx] = I2[(long long)my * W + mx];
+    }
+    __syncthreads();
+    bool row_ok[NW];
+#pragma unroll
+    for (int dy = 0; dy < NW; ++dy) {
+        const int cy = min(max(y + dy - R, 0), H - 1);
+        row_ok[dy] = cy + d2 >= 0 && cy + d2 < H;
+    }
+    const int g = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+    const int t0 = g * GX;  // the wave's first output slot
+    for (int i = lane; i < K1; i += 64) {
+        const int d1 = i - off1;
+        float cs[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int t = t0 + c;                           // window slot of column x0 - R + t
+            const int cx = min(max(x0 - R + t, 0), W - 1);  // its clamped column
+            const int mx = cx + d1;
+            const bool col_ok = mx >= 0 && mx < W;
+            const int o2 = (cx - cx_first) + i;
+            float sum = 0.0f;
+#pragma unroll
+            for (int dy = 0; dy < NW; ++dy) {
+                const float e = (row_ok[dy] && col_ok) ? fabsf(a1[dy * nc1 + t] - a2[dy * nc2 + o2]) : trunc;
+                sum += e;
+            }
+            cs[c] = sum;
+        }
+#pragma unroll
+        for (int q = 0; q < GX; ++q) {
+            const int x = x0 + t0 + q;
+            float acc = cs[q];
+#pragma unroll
+            for (int dx = 1; dx < NW; ++dx) acc += cs[q + dx];
+            if (x < W) out[(((long long)y * W + x) * K2 + j) * K1 + i] = (OT)fminf(trunc, acc * inv_area);
+        }
     }
 }
 
@@ -324,12 +399,25 @@ extern "C" int dm_build_flow_cost_volume(const float* I1, const float* I2, dm_fl
     const float inv_area = 1.0f / (float)(nw * nw);
     const long long npx = (long long)s.W * s.H;
     ProfScope ps(DM_PROF_FLOW_COST, (double)npx * s.K1 * s.K2 * (out_dtype == DM_F16 ? 2 : 4) + 8.0 * npx, stream);
-    if (out_dtype == DM_F16)
-        hipLaunchKernelGGL(flow_sad_kernel<_Float16>, grid, dim3(256), lds, stream, I1, I2, s.W, s.H, s.K1, s.K2, s.off1,
-                           s.off2, r, p->trunc, inv_area, static_cast<_Float16*>(cost_out));
-    else
-        hipLaunchKernelGGL(flow_sad_kernel<float>, grid, dim3(256), lds, stream, I1, I2, s.W, s.H, s.K1, s.K2, s.off1,
-                           s.off2, r, p->trunc, inv_area, static_cast<float*>(cost_out));
+#define DM_FLOW_COLS(OT, R)                                                                                   \
+    hipLaunchKernelGGL((flow_sad_cols_kernel<OT, R>), grid, dim3(256), lds, stream, I1, I2, s.W, s.H, s.K1, s.K2, \
+                       s.off1, s.off2, p->trunc, inv_area, static_cast<OT*>(cost_out))
+    if (out_dtype == DM_F16) {
+        if (r == 0) DM_FLOW_COLS(_Float16, 0);
+        else if (r == 1) DM_FLOW_COLS(_Float16, 1);
+        else if (r == 2) DM_FLOW_COLS(_Float16, 2);
+        else
+            hipLaunchKernelGGL(flow_sad_kernel<_Float16>, grid, dim3(256), lds, stream, I1, I2, s.W, s.H, s.K1, s.K2,
+                               s.off1, s.off2, r, p->trunc, inv_area, static_cast<_Float16*>(cost_out));
+    } else {
+        if (r == 0) DM_FLOW_COLS(float, 0);
+        else if (r == 1) DM_FLOW_COLS(float, 1);
+        else if (r == 2) DM_FLOW_COLS(float, 2);
+        else
+            hipLaunchKernelGGL(flow_sad_kernel<float>, grid, dim3(256), lds, stream, I1, I2, s.W, s.H, s.K1, s.K2,
+                               s.off1, s.off2, r, p->trunc, inv_area, static_cast<float*>(cost_out));
+    }
+#undef DM_FLOW_COLS
     ps.stop();
     DM_HIP_TRY(hipGetLastError(), "flow cost launch");
     if (w_h != nullptr || w_v != nullptr)
