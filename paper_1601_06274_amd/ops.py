@@ -347,17 +347,31 @@ class FlowResult:
     u2: torch.Tensor           # [H][W] vertical component, label units (displacement u2 - off2)
 
 
-def solve_flow(cost, w_h, w_v, *, off1=0, off2=0, T=3, n_iters=20, refine=None, stream=None, **discrete_kw):
+def solve_flow(cost, w_h, w_v, *, off1=0, off2=0, T=3, n_iters=20, refine=None, stream=None, two_streams=True,
+               **discrete_kw):
     """The flow pipeline on a [H][W][K2][K1] cost: decoupled layer costs, one Dual_MM solve per
     layer, then the quadratic-fit refinement (dict of refine_flow parameters; None = the
-    defaults, False = none).  Composes the C calls only."""
+    defaults, False = none).  Composes the C calls only.  The two layers are independent
+    problems: with two_streams the second is solved on a forked stream (default priority),
+    joined before the refinement (each layer's chains alone fill only part of the chip)."""
     f1, f2 = flow_project(cost, stream=stream)
-    r1 = solve_discrete(f1, w_h, w_v, T=T, n_iters=n_iters, stream=stream, **discrete_kw)
-    r2 = solve_discrete(f2, w_h, w_v, T=T, n_iters=n_iters, stream=stream, **discrete_kw)
+    main = torch.cuda.current_stream(cost.device) if stream is None else stream
+    r1 = solve_discrete(f1, w_h, w_v, T=T, n_iters=n_iters, stream=main, **discrete_kw)
+    if two_streams:
+        side = torch.cuda.Stream(device=cost.device)
+        side.wait_stream(main)
+        r2 = solve_discrete(f2, w_h, w_v, T=T, n_iters=n_iters, stream=side, **discrete_kw)
+        # the allocator must not hand out what the side stream still uses
+        for t in (f2, w_h, w_v, r2.labels, r2.minmarg, r2.dual, r2.bounds, r2.lb_trace, r2.workspace):
+            if t is not None:
+                t.record_stream(side)
+        main.wait_stream(side)
+    else:
+        r2 = solve_discrete(f2, w_h, w_v, T=T, n_iters=n_iters, stream=main, **discrete_kw)
     if refine is False:
         u1, u2 = r1.labels.float(), r2.labels.float()
     else:
-        u1, u2 = refine_flow(cost, r1.labels, r2.labels, w_h, w_v, off1=off1, off2=off2, stream=stream,
+        u1, u2 = refine_flow(cost, r1.labels, r2.labels, w_h, w_v, off1=off1, off2=off2, stream=main,
                              **(refine or {}))
     return FlowResult(f1=f1, f2=f2, layer1=r1, layer2=r2, u1=u1, u2=u2)
 

@@ -176,3 +176,28 @@ def test_flow_full_frame_sampled():
     err = max(np.abs(u1.cpu().numpy() - r1).max(), np.abs(u2.cpu().numpy() - r2).max())
     print(f"[parity] flow full frame: refined |du| {err:.2e}", flush=True)
     assert err <= 1e-4
+
+
+def test_flow_layers_on_two_streams_equal_one_stream():
+    """The second layer's solve on a forked stream gives the one-stream results bit for bit
+    (labels, min-marginals, duals, bounds and the refined flow), on three calls in a row."""
+    ops = _need()
+    W, H, R = 200, 120, 8
+    K = 2 * R
+    pair = synth.flow_pair(W, H, R - 1.0, seed=63, segments=5, slope=0.01)
+    print(f"[case] flow two streams {W}x{H} K={K}", flush=True)
+    cost, w_h, w_v = ops.build_flow_cost_volume(_dev(pair.first), _dev(pair.second), K, K, R, R,
+                                                dtype=torch.float16)
+    ref = ops.solve_flow(cost, w_h, w_v, off1=R, off2=R, T=3, n_iters=6, two_streams=False,
+                         refine=dict(C=3.0, n_warps=2, n_iters=10))
+    torch.cuda.synchronize()
+    for rep in range(3):
+        got = ops.solve_flow(cost, w_h, w_v, off1=R, off2=R, T=3, n_iters=6, two_streams=True,
+                             refine=dict(C=3.0, n_warps=2, n_iters=10))
+        torch.cuda.synchronize()
+        for a, b in ((got.layer1, ref.layer1), (got.layer2, ref.layer2)):
+            assert torch.equal(a.labels, b.labels), f"call {rep}: labels"
+            assert torch.equal(a.minmarg, b.minmarg), f"call {rep}: min-marginals"
+            assert torch.equal(a.dual, b.dual), f"call {rep}: duals"
+            assert torch.equal(a.bounds, b.bounds), f"call {rep}: bounds"
+        assert torch.equal(got.u1, ref.u1) and torch.equal(got.u2, ref.u2), f"call {rep}: refined flow"
