@@ -457,7 +457,8 @@ def census_lr_extra(torch, ops, dev, pair, wl, tiles, reps=3):
     for v in ("left", "right"):
         c, wh, wv = ops.build_cost_volume_census(IL, IR, K, window=5, view=v, dtype=torch.float16)
         views[v] = dict(cost=c, w_h=wh, w_v=wv, dual=torch.empty((H, W, K), dtype=torch.float32, device=dev),
-                        ws=None, rws=None, u=torch.empty((H, W), dtype=torch.float32, device=dev))
+                        labels=torch.empty((H, W), dtype=torch.int32, device=dev), ws=None, rws=None,
+                        u=torch.empty((H, W), dtype=torch.float32, device=dev))
     ops.profiler_enable(["census", "lr_check"])
     for _ in range(reps):
         for v in ("left", "right"):
@@ -467,18 +468,20 @@ def census_lr_extra(torch, ops, dev, pair, wl, tiles, reps=3):
     n_c, ms_c, by_c = ops.profiler_query("census")
     out_u = torch.empty((H, W), dtype=torch.float32, device=dev)
 
-    def forward(v):
+    # every buffer of a view preallocated (after the first, untimed call): nothing is
+    # allocated per call, so the right view may run on another stream
+    def forward(v, stream=None):
         d = views[v]
         r = ops.solve_discrete(d["cost"], d["w_h"], d["w_v"], T=wl["T"], n_iters=wl["n_iters"],
-                               gammas=wl["gammas"], dual=d["dual"], workspace=d["ws"], want_minmarg=False,
-                               want_bounds=False, tile=tiles)
+                               gammas=wl["gammas"], dual=d["dual"], labels=d["labels"], workspace=d["ws"],
+                               want_minmarg=False, want_bounds=False, tile=tiles, stream=stream)
         d["ws"] = r.workspace
         if d["rws"] is None:
             d["rws"] = torch.empty(ops.refine_workspace_bytes((H, W, K), C=wl["C"], n_warps=wl["n_warps"],
                                                               n_iters=wl["refine_iters"]),
                                    dtype=torch.uint8, device=dev)
         ops.refine_continuous(d["cost"], r.labels, d["w_h"], d["w_v"], C=wl["C"], n_warps=wl["n_warps"],
-                              n_iters=wl["refine_iters"], workspace=d["rws"], u_out=d["u"])
+                              n_iters=wl["refine_iters"], workspace=d["rws"], u_out=d["u"], stream=stream)
 
     def left_only():
         ops.build_cost_volume_census(IL, IR, K, window=5, view="left", cost_out=views["left"]["cost"],
@@ -492,8 +495,24 @@ def census_lr_extra(torch, ops, dev, pair, wl, tiles, reps=3):
             forward(v)
         ops.lr_check(views["left"]["u"], views["right"]["u"], max_diff=1.0, invalid=-1.0, out=out_u)
 
+    # the two views are independent until the check: the right one on a forked stream
+    # (default priority), joined before the check
+    s_a, s_b = torch.cuda.current_stream(), torch.cuda.Stream(device=dev)
+
+    def both_two_streams():
+        s_b.wait_stream(s_a)
+        for v, st in (("left", s_a), ("right", s_b)):
+            ops.build_cost_volume_census(IL, IR, K, window=5, view=v, cost_out=views[v]["cost"],
+                                         w_h=views[v]["w_h"], w_v=views[v]["w_v"], stream=st)
+            forward(v, st)
+        s_a.wait_stream(s_b)
+        ops.lr_check(views["left"]["u"], views["right"]["u"], max_diff=1.0, invalid=-1.0, out=out_u)
+
     ms_left = _timed(left_only, reps, torch)
     ms_both = _timed(both, reps, torch)
+    kept1 = out_u.clone()
+    ms_both2 = _timed(both_two_streams, reps, torch)
+    same = bool(torch.equal(kept1, out_u))
     n_l, ms_l, _ = ops.profiler_query("lr_check")
     ops.profiler_disable()
     kept = float((out_u >= 0).float().mean().item())
@@ -504,7 +523,9 @@ def census_lr_extra(torch, ops, dev, pair, wl, tiles, reps=3):
             "census_alg_bytes_per_view": by_c / n_c,
             "lr_check_ms": ms_l / max(n_l, 1),
             "forward_left_view_ms": ms_left, "forward_both_views_and_check_ms": ms_both,
-            "ratio_both_to_left": ms_both / ms_left, "kept_fraction": kept}
+            "ratio_both_to_left": ms_both / ms_left,
+            "forward_both_views_two_streams_and_check_ms": ms_both2, "ratio_two_streams_to_left": ms_both2 / ms_left,
+            "two_streams_result_equal": same, "kept_fraction": kept}
 
 
 def main():
