@@ -7,10 +7,12 @@
 //     u+ = prox_{tau D~}( u - tau A^T (p - q) )
 //     q+ = prox_{tau R_-^*}( q + tau A u )
 //     p+ = prox_{sigma R_+^*}( p + sigma A (2 u+ - u) ),
-// (Au)_e = u_i - u_j for the right / lower neighbour j of i.  A block owns a TX x TY tile;
-// it first computes u+ on the tile plus a one-pixel halo to the right and below (the
-// halo values are recomputed, not exchanged), keeps u and u+ in LDS, then updates q and
-// p of the tile's edges.  State is double buffered (every read sees the previous iterate).
+// (Au)_e = u_i - u_j for the right / lower neighbour j of i.  Edge arrays are stored per
+// pixel: ph/qh at (x, y) belong to the edge (x, y)-(x+1, y) (unused in the last column),
+// pv/qv to (x, y)-(x, y+1) (unused in the last row).  State is double buffered between
+// launches (every read of a launch sees the previous launch's iterate).  DataProx is the
+// prox of tau D~ of a pixel around its model: load(p) reads the pixel's model once per
+// launch, apply(uh, model, kmax, code) returns the prox and its branch code (4 bits).
 #pragma once
 
 #include "refine.h"
@@ -34,85 +36,18 @@ __device__ __forceinline__ rfloat prox_conj(rfloat t, rfloat w, rfloat alpha, rf
     return r;
 }
 
-constexpr int kTX = 64, kTY = 4;
-
 // Mask layout (uint16 per pixel and iteration): [0,4) u-prox, [4,7) qh, [7,10) qv,
 // [10,13) ph, [13,16) pv.
 __device__ __forceinline__ int mfield(uint32_t m, int shift, int bits) { return (int)((m >> shift) & ((1u << bits) - 1u)); }
-
-// One full iteration on a TX x TY tile.  DataProx(uh, p, kmax, code) is the prox of tau D~
-// of pixel p at uh (the data term's model around u0), with its branch code (4 bits); the
-// fused form below takes the same prox in two steps, load(p) of the pixel's model once
-// per launch and apply(uh, model, kmax, code) per iteration.
-// Edge arrays are stored per pixel: ph/qh at (x, y) belong to the edge (x, y)-(x+1, y)
-// (unused in the last column), pv/qv to (x, y)-(x, y+1) (unused in the last row).
-template <class DataProx>
-__device__ __forceinline__ void pdhg_tile(const RefineState& in, const RefineState& out, const DataProx& prox,
-                                          const float* __restrict__ w_h, const float* __restrict__ w_v, int W, int H,
-                                          int K, const RefineScalars& sc, uint16_t* __restrict__ mask, int x0, int y0) {
-    __shared__ rfloat s_uo[kTY + 1][kTX + 1];
-    __shared__ rfloat s_un[kTY + 1][kTX + 1];
-    __shared__ int s_code[kTY][kTX];
-    const rfloat kmax = (rfloat)(K - 1);
-    // Phase A: u+ on the tile and its right / lower halo.
-    for (int idx = threadIdx.x; idx < (kTX + 1) * (kTY + 1); idx += blockDim.x) {
-        const int i = idx % (kTX + 1), j = idx / (kTX + 1);
-        const int x = x0 + i, y = y0 + j;
-        rfloat uo = 0.0, un = 0.0;
-        int code = 0;
-        if (x < W && y < H) {
-            const long long p = (long long)y * W + x;
-            // (A^T z)_i = z_h(i) + z_v(i) - z_h(left) - z_v(up), z = p - q
-            rfloat at = 0.0;
-            if (x + 1 < W) at += in.ph[p] - in.qh[p];
-            if (y + 1 < H) at += in.pv[p] - in.qv[p];
-            if (x > 0) at -= in.ph[p - 1] - in.qh[p - 1];
-            if (y > 0) at -= in.pv[p - W] - in.qv[p - W];
-            uo = in.u[p];
-            un = prox(uo - sc.tau * at, p, kmax, code);
-        }
-        s_uo[j][i] = uo;
-        s_un[j][i] = un;
-        if (i < kTX && j < kTY) s_code[j][i] = code;
-    }
-    __syncthreads();
-    // Phase B: q+ (old u) and p+ (extrapolated 2u+ - u) on the tile's edges.
-    const int i = threadIdx.x % kTX, j = threadIdx.x / kTX;
-    const int x = x0 + i, y = y0 + j;
-    if (x >= W || y >= H) return;
-    const long long p = (long long)y * W + x;
-    const rfloat uo = s_uo[j][i], un = s_un[j][i];
-    out.u[p] = un;
-    uint32_t m = (uint32_t)s_code[j][i];
-    int c;
-    if (x + 1 < W) {
-        const rfloat w = (rfloat)w_h[(long long)y * (W - 1) + x];
-        const rfloat gq = uo - s_uo[j][i + 1];
-        out.qh[p] = prox_conj(in.qh[p] + sc.tau * gq, w, 0.0, sc.beta_minus, sc.tau, c);
-        m |= (uint32_t)c << 4;
-        const rfloat gp = (2.0 * un - uo) - (2.0 * s_un[j][i + 1] - s_uo[j][i + 1]);
-        out.ph[p] = prox_conj(in.ph[p] + sc.sigma * gp, w, sc.eps, sc.delta, sc.sigma, c);
-        m |= (uint32_t)c << 10;
-    }
-    if (y + 1 < H) {
-        const rfloat w = (rfloat)w_v[p];
-        const rfloat gq = uo - s_uo[j + 1][i];
-        out.qv[p] = prox_conj(in.qv[p] + sc.tau * gq, w, 0.0, sc.beta_minus, sc.tau, c);
-        m |= (uint32_t)c << 7;
-        const rfloat gp = (2.0 * un - uo) - (2.0 * s_un[j + 1][i] - s_uo[j + 1][i]);
-        out.pv[p] = prox_conj(in.pv[p] + sc.sigma * gp, w, sc.eps, sc.delta, sc.sigma, c);
-        m |= (uint32_t)c << 13;
-    }
-    if (mask != nullptr) mask[p] = (uint16_t)m;
-}
 
 // n_iter <= S iterations in one launch (temporal tiling).  A block owns a TX x TY output
 // tile and loads the state of the tile extended by S pixels on every side into LDS; each
 // iteration runs phases A (u+) and B (q+, p+) on the whole region.  Values within s pixels
 // of the region's border are wrong after s iterations (their neighbours outside the region
 // are missing), but every dependency of the iteration reaches one pixel, so after n_iter
-// <= S iterations the output tile is exact: the arithmetic per pixel and iteration is that
-// of pdhg_tile (the same expressions in the same order), only the state stays on chip.
+// <= S iterations the output tile is exact, and the arithmetic per pixel and iteration
+// (the same expressions in the same order for every tile shape and S) does not depend on
+// the tiling: the results equal one iteration per launch bit for bit.
 // mask0: the branch-mask plane of the first iteration (nullptr: no tape), mask_stride the
 // element distance between consecutive iterations' planes.
 template <int TX, int TY, int S, class DataProx>

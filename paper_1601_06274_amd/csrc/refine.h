@@ -48,7 +48,7 @@ struct RefChunk {      // pixels [start, start + count) of one instance
     long long start;
     int count;
 };
-struct RefTile {       // one 64 x 4 tile of one instance
+struct RefTile {       // one fused-iteration tile (kFTX x kFTY outputs) of one instance
     int inst, bx, by;
 };
 void refine_tile_extent(int W, int H, int& nbx, int& nby);

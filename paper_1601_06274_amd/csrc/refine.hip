@@ -17,14 +17,10 @@
 //   linearize_kernel : u0 := u, slopes (s_L, s_R) of the data term at u0 by linear
 //                      interpolation of the cost volume along the label axis (once per warp)
 //   pdhg_fused_kernel: kFS iterations per launch on a tile extended by kFS pixels, the state
-//                      in LDS between iterations (temporal tiling, pdhg.h); the single
-//                      instance's refinement.
-//   pdhg_kernel      : one full iteration.  A block owns a TX x TY tile; it first computes
-//                      u+ on the tile plus a one-pixel halo to the right and below (the
-//                      halo values are recomputed, not exchanged), keeps u and u+ in LDS,
-//                      then updates q and p of the tile's edges.  State is double
-//                      buffered (every read sees the previous iterate).  Optionally records
-//                      the branch taken by every prox (16-bit mask per pixel) for the adjoint.
+//                      in LDS between iterations (temporal tiling, pdhg.h).  Optionally
+//                      records the branch taken by every prox (16-bit mask per pixel and
+//                      iteration) for the adjoint.  batched_pdhg_fused_kernel: the same
+//                      per (instance, tile) of a batched plan's table.
 // State and arithmetic are FP64 (rfloat); the cost volume and edge weights are read in
 // their storage types and widened.  The working set (about 11 doubles per pixel) stays
 // in L2 / MALL at these sizes, so the iteration is bound by on-chip bandwidth and
@@ -134,14 +130,6 @@ struct TwoSlopeProx {
     }
 };
 
-__global__ __launch_bounds__(256) void pdhg_kernel(const RefineState in, RefineState out, const rfloat* __restrict__ u0,
-                                                   const rfloat* __restrict__ sL, const rfloat* __restrict__ sR,
-                                                   const float* __restrict__ w_h, const float* __restrict__ w_v, int W,
-                                                   int H, int K, RefineScalars sc, uint16_t* __restrict__ mask) {
-    pdhg_tile(in, out, TwoSlopeProx{u0, sL, sR, sc.tau, sc.h}, w_h, w_v, W, H, K, sc, mask, blockIdx.x * kTX,
-              blockIdx.y * kTY);
-}
-
 __global__ __launch_bounds__(256, 2) void pdhg_fused_kernel(const RefineState in, RefineState out,
                                                          const rfloat* __restrict__ u0, const rfloat* __restrict__ sL,
                                                          const rfloat* __restrict__ sR, const float* __restrict__ w_h,
@@ -181,13 +169,14 @@ __global__ __launch_bounds__(256) void batched_linearize_kernel(const RefBatchIn
         linearize_px(static_cast<const TT*>(in.theta), in.S[cur].u, p, in.K, h, in.u0, in.sL, in.sR);
 }
 
-__global__ __launch_bounds__(256) void batched_pdhg_kernel(const RefBatchInst* __restrict__ insts,
-                                                           const RefTile* __restrict__ tiles, int cur,
-                                                           RefineScalars sc) {
+__global__ __launch_bounds__(256, 2) void batched_pdhg_fused_kernel(const RefBatchInst* __restrict__ insts,
+                                                                    const RefTile* __restrict__ tiles, int cur,
+                                                                    RefineScalars sc, int n_iter) {
     const RefTile t = tiles[blockIdx.x];
     const RefBatchInst& in = insts[t.inst];
-    pdhg_tile(in.S[cur], in.S[cur ^ 1], TwoSlopeProx{in.u0, in.sL, in.sR, sc.tau, sc.h}, in.w_h, in.w_v, in.W, in.H,
-              in.K, sc, nullptr, t.bx * kTX, t.by * kTY);
+    pdhg_fused_tile<kFTX, kFTY, kFS>(in.S[cur], in.S[cur ^ 1], TwoSlopeProx{in.u0, in.sL, in.sR, sc.tau, sc.h},
+                                     in.w_h, in.w_v, in.W, in.H, in.K, sc, nullptr, 0, n_iter, t.bx * kFTX,
+                                     t.by * kFTY);
 }
 
 __global__ __launch_bounds__(256) void batched_narrow_kernel(const RefBatchInst* __restrict__ insts,
@@ -198,8 +187,8 @@ __global__ __launch_bounds__(256) void batched_narrow_kernel(const RefBatchInst*
 }
 
 void refine_tile_extent(int W, int H, int& nbx, int& nby) {
-    nbx = (W + kTX - 1) / kTX;
-    nby = (H + kTY - 1) / kTY;
+    nbx = (W + kFTX - 1) / kFTX;
+    nby = (H + kFTY - 1) / kFTY;
 }
 
 hipError_t launch_batched_refine(const RefBatchInst* insts, const RefChunk* chunks, int n_chunks, const RefTile* tiles,
@@ -214,8 +203,10 @@ hipError_t launch_batched_refine(const RefBatchInst* insts, const RefChunk* chun
         else
             hipLaunchKernelGGL(batched_linearize_kernel<float>, dim3(n_chunks), dim3(256), 0, st, insts, chunks, cur,
                                (rfloat)p.h);
-        for (int it = 0; it < p.n_iters; ++it) {
-            hipLaunchKernelGGL(batched_pdhg_kernel, dim3(n_tiles), dim3(256), 0, st, insts, tiles, cur, sc);
+        // kFS iterations per launch, as the single-instance refinement
+        for (int it0 = 0; it0 < p.n_iters; it0 += kFS) {
+            const int nit = std::min(kFS, p.n_iters - it0);
+            hipLaunchKernelGGL(batched_pdhg_fused_kernel, dim3(n_tiles), dim3(256), 0, st, insts, tiles, cur, sc, nit);
             cur ^= 1;
         }
     }
@@ -236,10 +227,10 @@ __device__ __forceinline__ rfloat conj_dw(int code, rfloat alpha) {
 // tile is exact after n_iter iterations on the tile extended by kAS pixels on every side.
 // The adjoint state sits in LDS between iterations; the accumulators of the tile's pixels
 // (u0, slopes, edge weights) are loaded once, carried in registers in the order of the
-// single-iteration kernel's additions and stored once, so the results equal that
-// kernel's bit for bit.  Per iteration: the branch masks of the region into LDS; phase A
-// the adjoint of u-hat and the new u adjoint (from the own and the left / upper edges);
-// phase B the edge adjoints in place and the accumulators.  mask_hi: the mask plane of
+// additions of one reverse iteration at a time and stored once, so the results do not
+// depend on the tiling (bit for bit).  Per iteration: the branch masks of the region into
+// LDS; phase A the adjoint of u-hat and the new u adjoint (from the own and the left /
+// upper edges); phase B the edge adjoints in place and the accumulators.  mask_hi: the mask plane of
 // the launch's first (latest) iteration; earlier iterations lie mask_stride elements
 // below, one plane each.
 __global__ __launch_bounds__(256) void pdhg_adjoint_fused_kernel(const RefineState nxt, RefineState prv,
