@@ -12,8 +12,12 @@
 // received, its minimum subtracted; the family's dual moves by it as for the other
 // minorants (rows: lambda += h, columns: lambda -= h).
 //
-// Mapping: one chain per wave64 (lane l holds labels l*LPL .. l*LPL+LPL-1), the parts
-// processed depth first from a per-wave stack in LDS.  Messages live in two HBM volumes
+// Mapping: one chain per workgroup of one or four wave64s (lane l holds labels l*LPL ..
+// l*LPL+LPL-1), the parts processed level by level; parts of at most a few nodes are
+// finished in the wave's LDS, depth first from a per-wave stack.  When the chains are few
+// a half-step is two launches: a block of four waves per chain for the levels above a
+// split depth D, then a block per subtree at depth D (the parts of a depth are independent
+// once the passes above them have written their boundary messages).  Messages live in two HBM volumes
 // (into each node from the left and from the right), normalised by the minimum of the
 // message input; the per-node normalisation of the result makes those constants
 // irrelevant.  The message is the truncated-linear distance transform: for T - 1 <= LPL
@@ -542,28 +546,36 @@ struct HierChain {
     // parts up to the parts' own cuts, the work spread over the workgroup's waves with a
     // barrier after each step.  The whole chain's optimum is measured by the level-0
     // passes (waves 0 and 1) and the first cut (wave 0).
-    __device__ __forceinline__ void run(double* opt_out, double* opt_share) {
+    // d_root, p_root: the subtree of part p_root at depth d_root (0, 0: the whole chain,
+    // with the level-0 passes); the parts of one depth are independent once the passes of
+    // the depth above have written their boundary messages, so the subtrees of a depth
+    // are separate work.  d_stop: the depth whose cuts are left out (with those below).
+    __device__ __forceinline__ void run(double* opt_out, double* opt_share, int d_root, int p_root, int d_stop) {
         double opt = 0.0;
         if (n >= 2) {
             const Glob G{this};
-            const int i0 = hsplit(0, n - 1);
             float c[LPL];
-            if (wv == 0) {
+            if (d_root == 0) {
+                const int i0 = hsplit(0, n - 1);
+                if (wv == 0) {
 #pragma unroll
-                for (int q = 0; q < LPL; ++q) c[q] = 0.0f;
-                store_msg(true, 0, c);
-                pass(G, 0, i0, +1, c, opt);
-            }
-            if (wv == (NW > 1 ? 1 : 0)) {
+                    for (int q = 0; q < LPL; ++q) c[q] = 0.0f;
+                    store_msg(true, 0, c);
+                    pass(G, 0, i0, +1, c, opt);
+                }
+                if (wv == (NW > 1 ? 1 : 0)) {
 #pragma unroll
-                for (int q = 0; q < LPL; ++q) c[q] = 0.0f;
-                store_msg(false, n - 1, c);
-                pass(G, n - 1, n - 2 - i0, -1, c, opt);
+                    for (int q = 0; q < LPL; ++q) c[q] = 0.0f;
+                    store_msg(false, n - 1, c);
+                    pass(G, n - 1, n - 2 - i0, -1, c, opt);
+                }
+                __syncthreads();
             }
-            __syncthreads();
             int maxlen = n;  // longest part at this depth
-            for (int depth = 0;; ++depth) {
-                const int np = 1 << depth;
+            for (int d = 0; d < d_root; ++d) maxlen = (maxlen + 1) / 2;
+            for (int depth = d_root; depth < d_stop; ++depth) {
+                const int np = 1 << (depth - d_root);  // the subtree's parts at this depth
+                const int pb = p_root << (depth - d_root);  // the index of its first
                 // this wave's cuts, the inputs of the next one loaded while the current
                 // one is computed
                 HsIn nxt;
@@ -571,7 +583,7 @@ struct HierChain {
                 auto next_big = [&](int from) -> int {  // the next part of this wave longer than the chunk
                     for (int p = from; p < np; p += NW) {
                         int s1, e1;
-                        if (part_at(depth, p, s1, e1) && e1 - s1 + 1 > kHierChunk) return hsplit(s1, e1);
+                        if (part_at(depth, pb + p, s1, e1) && e1 - s1 + 1 > kHierChunk) return hsplit(s1, e1);
                     }
                     return -1;
                 };
@@ -583,7 +595,7 @@ struct HierChain {
                 // while the current one is computed
                 auto next_small = [&](int from, int& s1, int& e1) -> bool {
                     for (int p = from; p < np; p += NW)
-                        if (part_at(depth, p, s1, e1) && e1 - s1 + 1 <= kHierChunk) return true;
+                        if (part_at(depth, pb + p, s1, e1) && e1 - s1 + 1 <= kHierChunk) return true;
                     return false;
                 };
                 SmallIn sm;
@@ -592,7 +604,7 @@ struct HierChain {
                     if (next_small(wv, sm_s, sm_e)) small_load(sm_s, sm_e, sm);
                 for (int p = wv; p < np; p += NW) {
                     int s0, e0;
-                    if (!part_at(depth, p, s0, e0)) continue;
+                    if (!part_at(depth, pb + p, s0, e0)) continue;
                     if (e0 - s0 + 1 <= kHierChunk) {
                         // with the prefetch, sm holds this part's loads (parts are visited in order)
                         if constexpr (!kPrefetchSmall) small_load(s0, e0, sm);
@@ -616,7 +628,7 @@ struct HierChain {
                 // its own cut; 2p + 1: the right part's from the left, up to its cut
                 for (int q = wv; q < 2 * np; q += NW) {
                     int s0, e0;
-                    if (!part_at(depth, q >> 1, s0, e0) || e0 - s0 + 1 <= kHierChunk) continue;
+                    if (!part_at(depth, pb + (q >> 1), s0, e0) || e0 - s0 + 1 <= kHierChunk) continue;
                     const int i = hsplit(s0, e0);
                     double unused = 0.0;  // the parts' normalisation constants are not the optimum's
                     if ((q & 1) == 0) {
@@ -652,29 +664,67 @@ struct HierChain {
     }
 };
 
+// split: 0, a block per chain; else the depth D at which the chains' work is split:
+// split > 0 launches a block per chain for the levels above D (no LDS parts there),
+// split < 0 a block per subtree at depth D (2^D blocks per chain, chain-major).
 template <int LPL, typename TT, bool HAS_THETA, int TW, int NW, bool FULL>
-__global__ __launch_bounds__(64 * NW) void hier_chain_kernel(SweepArgs a, float* msg_right) {
+__global__ __launch_bounds__(64 * NW) void hier_chain_kernel(SweepArgs a, float* msg_right, int split) {
     using HC = HierChain<LPL, TT, HAS_THETA, TW, NW, FULL>;
     __shared__ int stk[NW][2 * 64];  // each wave's part stack (depth <= 32)
     __shared__ double opt_share[1];
     extern __shared__ float part[];  // per wave: [3][chunk][64 * LPL], then chunk weights
-    const int chain = blockIdx.x;
+    const int d = split < 0 ? -split : 0;
+    const int chain = (int)(blockIdx.x >> d);
     HC hc(a, msg_right, chain);
     hc.lds = (lds_f32*)(part + (size_t)hc.wv * HC::kLdsFloats);
     hc.stk_small = (lds_i32*)stk[hc.wv];
-    hc.run(a.opt != nullptr ? a.opt + chain : nullptr, opt_share);
+    hc.run(a.opt != nullptr && split >= 0 ? a.opt + chain : nullptr, opt_share, d, (int)(blockIdx.x & ((1u << d) - 1u)),
+           split > 0 ? split : 0x7fff);
+}
+
+// Depth at which the chains' work is split into separate blocks, 0 for none.  A block
+// per chain leaves the CUs unevenly loaded when the chains are few (the 375 rows of a
+// 1242 x 375 frame in blocks of four waves: some CUs hold one chain, some two, and the
+// kernel waits for the latter); the subtrees at depth D are 2^D times as many blocks of
+// equal work.  D is the shallowest depth giving at least 8192 waves (about eight per
+// SIMD, over several rounds of resident blocks), at most 4, and only while every part
+// above it is longer than the LDS part (n >= (chunk + 1) 2^D: a part at depth d has at
+// least floor(n / 2^d) nodes), so the block per chain meets no LDS part.
+inline int hier_split_depth(int n_chains, int nw, int chunk, int n) {
+    int D = 0;
+    while (D < 4 && (long long)n_chains * nw << D < 8192 && n >= ((chunk + 1) << (D + 1))) ++D;
+    return D;
+}
+
+template <int LPL, int TW, int NW, bool FULL>
+void launch_blocks(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st, int split, unsigned blocks,
+                   size_t shm) {
+    const dim3 grid(blocks), block(64 * NW);
+    if (a.theta == nullptr)
+        hipLaunchKernelGGL((hier_chain_kernel<LPL, float, false, TW, NW, FULL>), grid, block, shm, st, a, msg_right,
+                           split);
+    else if (dt == DM_F16)
+        hipLaunchKernelGGL((hier_chain_kernel<LPL, _Float16, true, TW, NW, FULL>), grid, block, shm, st, a, msg_right,
+                           split);
+    else
+        hipLaunchKernelGGL((hier_chain_kernel<LPL, float, true, TW, NW, FULL>), grid, block, shm, st, a, msg_right,
+                           split);
 }
 
 template <int LPL, int TW, int NW, bool FULL>
 hipError_t launch_full(const SweepArgs& a, float* msg_right, dm_dtype dt, hipStream_t st) {
-    const dim3 grid((unsigned)a.n_chains), block(64 * NW);
     const size_t lds = (size_t)NW * HierChain<LPL, float, false, TW, NW, FULL>::kLdsFloats * sizeof(float);
-    if (a.theta == nullptr)
-        hipLaunchKernelGGL((hier_chain_kernel<LPL, float, false, TW, NW, FULL>), grid, block, lds, st, a, msg_right);
-    else if (dt == DM_F16)
-        hipLaunchKernelGGL((hier_chain_kernel<LPL, _Float16, true, TW, NW, FULL>), grid, block, lds, st, a, msg_right);
-    else
-        hipLaunchKernelGGL((hier_chain_kernel<LPL, float, true, TW, NW, FULL>), grid, block, lds, st, a, msg_right);
+    const int D = hier_split_depth(a.n_chains, NW, hier_chunk(NW, LPL), a.n);
+    if (D == 0) {
+        launch_blocks<LPL, TW, NW, FULL>(a, msg_right, dt, st, 0, (unsigned)a.n_chains, lds);
+    } else {
+        // the levels above D: four waves per chain whatever NW (the two level-0 passes side
+        // by side, up to four passes per depth), no LDS parts, so no dynamic LDS
+        launch_blocks<LPL, TW, 4, FULL>(a, msg_right, dt, st, D, (unsigned)a.n_chains, 0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        launch_blocks<LPL, TW, NW, FULL>(a, msg_right, dt, st, -D, (unsigned)a.n_chains << D, lds);
+    }
     return hipGetLastError();
 }
 

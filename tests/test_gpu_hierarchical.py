@@ -26,6 +26,8 @@ CASES = [  # H, W, K, T, iters, cost dtype
     (3, 70, 256, 3, 2, torch.float32),  # four waves per chain with 4 labels per lane
     (5, 90, 200, 4, 2, torch.float16),
     (2, 300, 130, 2, 1, torch.float32),  # several depths above the LDS parts
+    (60, 20, 64, 2, 2, torch.float32),   # column chains split at depth 2 (one wave per subtree)
+    (40, 30, 50, 3, 2, torch.float16),   # column chains split at depth 1, ragged labels
 ]
 
 
