@@ -496,10 +496,27 @@ struct HierChain {
         }
         wave_lds_sync();
     }
+    // fill: 0, or the side of its parent this part is (-1 left, +1 right) when the parent
+    // left out its passes (every child at most kHierChunk long): the part then computes
+    // the messages its parent's pass would have written, from the one valid message at
+    // its outer end (the Handshake's) to its own cut, in LDS with the same pass.
     __device__ __forceinline__ void small_finish(int s, int e, const float (&lam)[kHierChunk][LPL], bool first,
-                                                 double& opt) const {
+                                                 double& opt, int fill) const {
         const int m = e - s + 1;
         const Lds L{this, lds, s};
+        if (fill != 0) {
+            double unused = 0.0;
+            float c[LPL];
+            const int cut = hsplit(s, e);
+            if (fill < 0) {  // left child: messages from the right, from e down to the cut
+                L.load_m(false, e, c);
+                pass(L, e, e - cut - 1, -1, c, unused);
+            } else {  // right child: messages from the left, from s up to the cut
+                L.load_m(true, s, c);
+                pass(L, s, cut - s, +1, c, unused);
+            }
+            wave_lds_sync();
+        }
         bool f = first;
         split_parts(L, stk_small, s, e, f, opt);
         wave_lds_sync();
@@ -528,9 +545,14 @@ struct HierChain {
     // the parent's length, so the parent is the shortest ancestor and the only one to
     // test; the walk itself has no branches (scalar selects).
     __device__ __forceinline__ bool part_at(int depth, int p, int& s, int& e) const {
+        int plen;
+        return part_at(depth, p, s, e, plen);
+    }
+    // ... and the parent's length (0x7fffffff at depth 0)
+    __device__ __forceinline__ bool part_at(int depth, int p, int& s, int& e, int& plen) const {
         s = 0;
         e = n - 1;
-        int plen = 0x7fffffff;  // the parent's length (depth 0: no parent, the whole chain exists)
+        plen = 0x7fffffff;  // the parent's length (depth 0: no parent, the whole chain exists)
         for (int d = depth - 1; d >= 0; --d) {
             plen = e - s + 1;
             const int i = hsplit(s, e);
@@ -603,8 +625,8 @@ struct HierChain {
                 if constexpr (kPrefetchSmall)
                     if (next_small(wv, sm_s, sm_e)) small_load(sm_s, sm_e, sm);
                 for (int p = wv; p < np; p += NW) {
-                    int s0, e0;
-                    if (!part_at(depth, pb + p, s0, e0)) continue;
+                    int s0, e0, plen;
+                    if (!part_at(depth, pb + p, s0, e0, plen)) continue;
                     if (e0 - s0 + 1 <= kHierChunk) {
                         // with the prefetch, sm holds this part's loads (parts are visited in order)
                         if constexpr (!kPrefetchSmall) small_load(s0, e0, sm);
@@ -612,7 +634,8 @@ struct HierChain {
                         small_stage(s0, e0, sm, lam);
                         if constexpr (kPrefetchSmall)
                             if (next_small(p + NW, sm_s, sm_e)) small_load(sm_s, sm_e, sm);
-                        small_finish(s0, e0, lam, depth == 0, opt);
+                        const int fill = plen <= 2 * kHierChunk ? (((pb + p) & 1) ? +1 : -1) : 0;
+                        small_finish(s0, e0, lam, depth == 0, opt, fill);
                     } else {
                         const int i = nxt_i;  // == hsplit(s0, e0): parts are visited in order
                         const HsIn cur = nxt;
@@ -625,10 +648,13 @@ struct HierChain {
                 __syncthreads();
                 if (maxlen <= kHierChunk) break;
                 // item 2p: the left part's messages from the right, from the cut down to
-                // its own cut; 2p + 1: the right part's from the left, up to its cut
+                // its own cut; 2p + 1: the right part's from the left, up to its cut.  A
+                // part of at most 2 kHierChunk nodes leaves them to its two parts (both
+                // finished in LDS, which recompute them there: no HBM round trip for a
+                // pass of a few nodes)
                 for (int q = wv; q < 2 * np; q += NW) {
                     int s0, e0;
-                    if (!part_at(depth, pb + (q >> 1), s0, e0) || e0 - s0 + 1 <= kHierChunk) continue;
+                    if (!part_at(depth, pb + (q >> 1), s0, e0) || e0 - s0 + 1 <= 2 * kHierChunk) continue;
                     const int i = hsplit(s0, e0);
                     double unused = 0.0;  // the parts' normalisation constants are not the optimum's
                     if ((q & 1) == 0) {
@@ -773,15 +799,16 @@ hipError_t launch_hier_half_step(const SweepArgs& a, float* msg_right, dm_dtype 
 double hier_half_step_bytes(const SweepArgs& a, dm_dtype dt) {
     // per label-node, HBM only: the two level-0 passes read every node's unaries (cost
     // and dual for rows, the dual for columns) and write its message; at every depth whose
-    // parts are longer than the LDS part, the passes after the cuts do so for half of the
-    // nodes; a part of at most that length is read once (unaries, one message) into LDS
-    // and its nodes' duals written.  The Handshakes' own loads and stores (two nodes per
-    // cut, about one cut per LDS part) are left out.
+    // parts are longer than twice the LDS part, the passes after the cuts do so for half
+    // of the nodes (shorter parts leave those passes to their parts, in LDS); a part of at
+    // most the LDS part's length is read once (unaries, one message) into LDS and its
+    // nodes' duals written.  The Handshakes' own loads and stores (two nodes per cut, about
+    // one cut per LDS part) are left out.
     const double b = a.theta != nullptr ? (dt == DM_F16 ? 2.0 : 4.0) : 0.0;
     const int lpl = a.K <= 64 ? 1 : a.K <= 128 ? 2 : a.K <= 192 ? 3 : 4;
     const int chunk = hier_chunk(hier_waves(a.n_chains, a.n), lpl);
-    int deep = 0;  // depths whose parts are longer than the LDS part
-    for (int m = a.n; m > chunk; m = (m + 1) / 2) ++deep;
+    int deep = 0;  // depths whose parts are longer than twice the LDS part
+    for (int m = a.n; m > 2 * chunk; m = (m + 1) / 2) ++deep;
     const double step = b + 4.0 + 4.0;                 // unaries read, message written
     const double per = step * (1.0 + 0.5 * deep) + (b + 4.0 + 4.0) + 4.0;  // + LDS part in, dual out
     return per * (double)a.n * a.n_chains * a.K;
