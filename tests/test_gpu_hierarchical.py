@@ -73,9 +73,11 @@ def test_hierarchical_stereo_frame():
 
 def test_hierarchical_full_frame_sampled_chains():
     """1242 x 375, K = 192, FP16 cost (four waves per row chain, seven cut levels above
-    the LDS parts): the GPU's dual after one row half-step and after the following
-    column half-step, on sampled rows and columns, against the oracle's hierarchical
-    minorant of those chains taken from the GPU's dual before the half-step."""
+    the LDS parts; both families split at depth 3 into a launch for the top levels and a
+    block per subtree): the GPU's dual after one row half-step and after the following
+    column half-step, on 22 rows and 42 columns spread over the frame (both ends
+    included), against the oracle's hierarchical minorant of those chains taken from the
+    GPU's dual before the half-step."""
     import paper_1601_06274_amd as P
     from oracle import chain, cost_volume as ocv
     W, H, K, T = 1242, 375, 192, 3
@@ -92,10 +94,10 @@ def test_hierarchical_full_frame_sampled_chains():
     torch.cuda.synchronize()
     lam1 = r1.dual.cpu().numpy().astype(np.float64)
     lam2 = r2.dual.cpu().numpy().astype(np.float64)
-    rows = [0, 187, 374]
+    rows = sorted(set(np.linspace(0, H - 1, 20).astype(int).tolist()) | {1, H - 2})
     h = chain.hierarchical_minorant(th[rows], wh[rows], T)  # rows start from lambda = 0
     err = np.abs(lam1[rows] - h) / np.maximum(np.abs(h), S)
-    cols = [0, 621, 1241]
+    cols = sorted(set(np.linspace(0, W - 1, 40).astype(int).tolist()) | {1, W - 2})
     a = np.transpose(lam1[:, cols], (1, 0, 2))  # column chains: unaries lambda
     g = chain.hierarchical_minorant(a, wv[:, cols].T, T)
     ref2 = a - g
