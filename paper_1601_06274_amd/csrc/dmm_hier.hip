@@ -43,9 +43,10 @@ namespace dm {
 // Parts of at most this many nodes are finished in LDS by one wave (App. A.3.3's
 // iteration count assumes that short parts sit in fast memory).  A wave stages
 // 3 x chunk x 64 x LPL floats: 8 nodes keep it at 18.4 KB for K = 192, so two blocks of
-// four waves share a CU; with one wave per chain and at most 3 labels per lane, 12 nodes
-// (27.6 KB, five waves per CU) take one more level off the HBM passes.
-constexpr int hier_chunk(int nw, int lpl) { return nw == 1 && lpl <= 3 ? 12 : 8; }
+// four waves, or eight blocks of one, share a CU.  (12 nodes for one wave per chain took
+// one more level off the HBM passes but left five waves per CU: 7 % slower on the
+// subtrees of the 1242 x 375 frame's columns, whose blocks outnumber the CU slots.)
+constexpr int hier_chunk(int, int) { return 8; }
 // Waves per chain: several when the chains alone leave most of the 1024 SIMDs idle.
 inline int hier_waves(int n_chains, int n) { return n_chains <= 512 && n >= 64 ? 4 : 1; }
 

@@ -27,7 +27,7 @@ CASES = [  # H, W, K, T, iters, cost dtype
     (5, 90, 200, 4, 2, torch.float16),
     (2, 300, 130, 2, 1, torch.float32),  # several depths above the LDS parts
     (60, 20, 64, 2, 2, torch.float32),   # column chains split at depth 2 (one wave per subtree)
-    (40, 30, 50, 3, 2, torch.float16),   # column chains split at depth 1, ragged labels
+    (40, 30, 50, 3, 2, torch.float16),   # columns split at depth 2, rows at depth 1, ragged labels
 ]
 
 
