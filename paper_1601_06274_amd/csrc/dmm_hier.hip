@@ -715,8 +715,9 @@ __global__ __launch_bounds__(64 * NW) void hier_chain_kernel(SweepArgs a, float*
 // kernel waits for the latter); the subtrees at depth D are 2^D times as many blocks of
 // equal work.  D is the shallowest depth giving at least 8192 waves (about eight per
 // SIMD, over several rounds of resident blocks), at most 4, and only while every part
-// above it is longer than the LDS part (n >= (chunk + 1) 2^D: a part at depth d has at
-// least floor(n / 2^d) nodes), so the block per chain meets no LDS part.
+// at depth D is longer than the LDS part (n >= (chunk + 1) 2^D: a part at depth d has at
+// least floor(n / 2^d) nodes), so the block per chain meets no LDS part and runs the
+// passes of every depth above D (its parts are longer than twice the LDS part).
 inline int hier_split_depth(int n_chains, int nw, int chunk, int n) {
     int D = 0;
     while (D < 4 && (long long)n_chains * nw << D < 8192 && n >= ((chunk + 1) << (D + 1))) ++D;
